@@ -1,0 +1,253 @@
+"""Pins of the oracle's lattice kinetics (Sec 2.1), thermodynamics (Sec 2.2) and
+full step against identities and closed forms the paper and mathematics fix."""
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_2205_09186_amd import inputs
+
+
+# --------------------------------------------------------------------------- #
+# Lattices and equilibrium (Eq 2, Eq 6, Eq 7)                                   #
+# --------------------------------------------------------------------------- #
+def test_d2q9_directions_follow_eq2(orc):
+    e, w = orc.lattice(orc.D2Q9)
+    expect = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    assert [tuple(v[:2]) for v in e] == expect
+    np.testing.assert_allclose(w, [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, rtol=2.5e-16, atol=0)
+    # the rounded weights sum to one exactly (no systematic mass change)
+    from fractions import Fraction
+    assert sum(Fraction(x) for x in w) == 1
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+def test_lattice_isotropy(orc, lat):
+    e, w = orc.lattice(lat)
+    dim = 2 if lat == 0 else 3
+    e = e[:, :dim].astype(float)
+    assert w.sum() == pytest.approx(1.0, abs=1e-15)
+    np.testing.assert_allclose(np.einsum("i,ia,ib->ab", w, e, e), np.eye(dim) / 3, atol=1e-15)
+    M4 = np.einsum("i,ia,ib,ic,id->abcd", w, e, e, e, e)
+    d = np.eye(dim)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d) + np.einsum("ad,bc->abcd", d, d)) / 9
+    np.testing.assert_allclose(M4, iso, atol=1e-15)
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+def test_feq_moments(orc, lat):
+    e, _ = orc.lattice(lat)
+    dim = 2 if lat == 0 else 3
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        rho = rng.uniform(0.01, 9.0)
+        u = rng.uniform(-0.1, 0.1, 3)
+        u[dim:] = 0.0
+        fe = orc.feq(lat, rho, u)
+        assert fe.sum() == pytest.approx(rho, rel=1e-14)
+        np.testing.assert_allclose(e.T @ fe, rho * u, atol=1e-14 * rho)
+        P = np.einsum("i,ia,ib->ab", fe, e[:, :dim], e[:, :dim])
+        np.testing.assert_allclose(P, rho / 3 * np.eye(dim) + rho * np.outer(u[:dim], u[:dim]), atol=1e-13 * rho)
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+def test_edm_collision_identities(orc, lat):
+    """Eq 8: sum_i F_i = 0 and sum_i e_i F_i = rho du = F; tau = 1 gives
+    f* = feq(rho, u + du) exactly (SRT reduction of Eq 1)."""
+    e, _ = orc.lattice(lat)
+    dim = 2 if lat == 0 else 3
+    q = len(e)
+    rng = np.random.default_rng(11)
+    for tau in (0.8, 1.0, 1.7):
+        f = orc.feq(lat, 3.0, [0.02, -0.01, 0.015][:dim]) * (1 + 0.05 * rng.standard_normal(q))
+        F = np.array([0.003, -0.002, 0.001])
+        F[dim:] = 0.0
+        fs = orc.collide_node(lat, tau, f, F)
+        rho = f.sum()
+        assert fs.sum() == pytest.approx(rho, rel=1e-14)
+        np.testing.assert_allclose(e.T @ fs, e.T @ f + F, atol=1e-15)
+        if tau == 1.0:
+            u = (e.T @ f) / rho
+            np.testing.assert_allclose(fs, orc.feq(lat, rho, u + F / rho), atol=1e-15)
+        # a relaxed (equilibrium) state without force is a fixed point
+        fe = orc.feq(lat, rho, (e.T @ f) / rho)
+        np.testing.assert_allclose(orc.collide_node(lat, tau, fe, [0, 0, 0]), fe, atol=1e-15)
+
+
+# --------------------------------------------------------------------------- #
+# Peng-Robinson EOS (Eq 13-15)                                                  #
+# --------------------------------------------------------------------------- #
+def test_pr_critical_point(orc):
+    Tc, rc, pc = orc.pr_critical()
+    a, b, R = orc.PR_A, orc.PR_B, orc.PR_R
+    h = 1e-4 * rc
+    p = lambda r: orc.pr_p0(r, Tc, a, b, R)
+    d1 = (p(rc + h) - p(rc - h)) / (2 * h)
+    d2 = (p(rc + h) - 2 * p(rc) + p(rc - h)) / h ** 2
+    assert abs(d1) < 1e-9 and abs(d2) < 1e-7
+    # textbook Peng-Robinson constants: a = 0.45724 R^2 Tc^2/pc, b = 0.07780 R Tc/pc, Zc = 0.3074
+    assert a * pc / (R * Tc) ** 2 == pytest.approx(0.45724, rel=2e-5)
+    assert b * pc / (R * Tc) == pytest.approx(0.07780, rel=2e-4)
+    assert pc / (rc * R * Tc) == pytest.approx(0.3074, rel=2e-4)
+    # above Tc the isotherm is monotone: no coexistence
+    with pytest.raises(ValueError):
+        orc.maxwell(1.0)
+
+
+def test_pr_alpha_and_gibbs_duhem(orc):
+    Tc, rc, pc = orc.pr_critical()
+    assert orc.pr_alpha(1.0) == 1.0
+    b, R = orc.PR_B, orc.PR_R
+    for Tr in (0.3, 0.6, 0.9):
+        T = Tr * Tc
+        aa = orc.PR_A * orc.pr_alpha(Tr)
+        for rho in (1e-6, 0.05, 1.3, 4.0, 9.5):
+            h = 1e-6 * rho
+            dmu = (orc.pr_mub(rho + h, T, aa) - orc.pr_mub(rho - h, T, aa)) / (2 * h)
+            dp = (orc.pr_p0(rho + h, T, aa) - orc.pr_p0(rho - h, T, aa)) / (2 * h)
+            assert dmu == pytest.approx(dp / rho, rel=1e-7, abs=1e-9)
+
+
+def test_pr_free_energy_eq10_eq13(orc):
+    """psi = rho (int p0/rho^2 drho + C) (Eq 13) by quadrature; then
+    p0 = rho psi' - psi (Eq 10) with psi' the oracle's mu_b, C chosen so the two
+    agree at one density."""
+    Tc, _, _ = orc.pr_critical()
+    Tr = 0.7
+    T, aa = Tr * Tc, orc.PR_A * orc.pr_alpha(Tr)
+    r0 = 1.0
+    # fix C from Eq 10 at r0
+    C0 = (r0 * orc.pr_mub(r0, T, aa) - orc.pr_p0(r0, T, aa)) / r0
+    for rho in (0.2, 2.5, 7.0):
+        I, _ = integrate.quad(lambda r: orc.pr_p0(r, T, aa) / r ** 2, r0, rho, epsabs=1e-14, epsrel=1e-13)
+        psi = rho * (I + C0)
+        assert rho * orc.pr_mub(rho, T, aa) - psi == pytest.approx(orc.pr_p0(rho, T, aa), rel=1e-9, abs=1e-12)
+
+
+@pytest.mark.parametrize("Tr", [0.95, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.25, 0.2])
+def test_maxwell_two_formulations(orc, Tr):
+    g1, l1 = orc.maxwell(Tr, "mu")
+    g2, l2 = orc.maxwell(Tr, "area")
+    assert g1 == pytest.approx(g2, rel=2e-12)
+    assert l1 == pytest.approx(l2, rel=1e-13)
+    Tc, rc, _ = orc.pr_critical()
+    assert g1 < rc < l1
+    T, aa = Tr * Tc, orc.PR_A * orc.pr_alpha(Tr)
+    # the liquid pressure is a difference of O(1) terms: compare on their scale
+    scale = l1 * orc.PR_R * T / (1 - orc.PR_B * l1)
+    assert abs(orc.pr_p0(g1, T, aa) - orc.pr_p0(l1, T, aa)) < 1e-13 * scale
+    assert orc.pr_mub(g1, T, aa) == pytest.approx(orc.pr_mub(l1, T, aa), rel=1e-12)
+
+
+def test_maxwell_density_ratio_trend(orc):
+    """Sec 3.3: the density ratio grows as the temperature falls; Sec 4 quotes
+    ratios up to ~1000 for the droplet runs (T_r = 0.6 is near 850)."""
+    ratios = [orc.maxwell(t)[1] / orc.maxwell(t)[0] for t in (0.9, 0.8, 0.7, 0.6)]
+    assert all(b > a for a, b in zip(ratios, ratios[1:]))
+    assert 500 < ratios[-1] < 1500
+
+
+# --------------------------------------------------------------------------- #
+# Full step: invariants                                                         #
+# --------------------------------------------------------------------------- #
+def _droplet_sim(orc, lat, n, scheme, Tr=0.8, k=0.16, kappa=0.004, W=2.0, R=None, amp=1e-6):
+    g, l = orc.maxwell(Tr)
+    if lat == orc.D2Q9:
+        p = orc.Params(lattice=lat, nx=n, ny=n, nz=1, Tr=Tr, k=k, kappa=kappa, scheme=scheme)
+        rho0 = inputs.droplet((n, n), R or n / 4, W, g, l, amplitude=amp)
+    else:
+        p = orc.Params(lattice=lat, nx=n, ny=n, nz=n, Tr=Tr, k=k, kappa=kappa, scheme=scheme)
+        rho0 = inputs.droplet((n, n, n), R or n / 4, W, g, l, amplitude=amp)
+    return orc.Sim(p, rho0), rho0
+
+
+def test_mass_conservation_2000_steps(orc):
+    s, rho0 = _droplet_sim(orc, orc.D2Q9, 100, orc.CD4)
+    _, m0 = s.observables()
+    s.step(2000)
+    u, m = s.observables()
+    assert np.isfinite(u)
+    assert abs(m - m0) / m0 < 1e-13
+
+
+@pytest.mark.parametrize("scheme", ["CD6", "E8", "OCFDS4"])
+def test_mass_conservation_3d(orc, scheme):
+    s, _ = _droplet_sim(orc, orc.D3Q19, 16, orc.SCHEME_NAMES[scheme], Tr=0.9, W=4.0)
+    _, m0 = s.observables()
+    s.step(20)
+    _, m = s.observables()
+    assert abs(m - m0) / m0 < 1e-14
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+@pytest.mark.parametrize("scheme", ["CD2", "CD6", "E8", "OCFDS4"])
+def test_uniform_state_is_fixed_point(orc, lat, scheme):
+    n = 12
+    p = orc.Params(lattice=lat, nx=n, ny=n - 2, nz=(1 if lat == 0 else n + 1), Tr=0.7, k=0.2, kappa=0.004,
+                   scheme=orc.SCHEME_NAMES[scheme])
+    rho0 = np.full(p.n, 3.3)
+    s = orc.Sim(p, rho0)
+    f0 = s.f.copy()
+    s.step(3)
+    np.testing.assert_allclose(s.f, f0, rtol=0, atol=4e-15)
+    r, vx, vy, vz = s.macros()
+    assert np.abs(vx).max() < 1e-16 and np.abs(vy).max() < 1e-16
+
+
+def test_droplet_symmetry_2d(orc):
+    """A centred, noise-free droplet on an even grid keeps the square's symmetry."""
+    s, _ = _droplet_sim(orc, orc.D2Q9, 40, orc.CD4, amp=0.0, W=4.0)
+    s.step(100)
+    r, vx, vy, _ = s.macros()
+    # centre at node 20: reflect x -> 40 - x about node 20
+    rr = np.roll(r[:, ::-1], 1, axis=1)
+    np.testing.assert_allclose(r, rr, atol=1e-12)
+    np.testing.assert_allclose(r, r.T, atol=1e-12)
+    np.testing.assert_allclose(vx, -np.roll(vx[:, ::-1], 1, axis=1), atol=1e-12)
+    np.testing.assert_allclose(vx, vy.T, atol=1e-12)
+
+
+def test_droplet_symmetry_3d(orc):
+    s, _ = _droplet_sim(orc, orc.D3Q19, 16, orc.CD4, Tr=0.9, amp=0.0, W=4.0)
+    s.step(10)
+    r, vx, vy, vz = s.macros()
+    np.testing.assert_allclose(r, r.transpose(0, 2, 1), atol=1e-12)
+    np.testing.assert_allclose(r, r.transpose(2, 1, 0), atol=1e-12)
+    np.testing.assert_allclose(vx, vy.transpose(0, 2, 1), atol=1e-12)
+    np.testing.assert_allclose(vx, vz.transpose(2, 1, 0), atol=1e-12)
+
+
+def test_spurious_currents_stay_below_sound_speed(orc):
+    s, _ = _droplet_sim(orc, orc.D2Q9, 64, orc.CD6, Tr=0.8)
+    s.step(500)
+    u, _ = s.observables()
+    assert 0 < u < 0.05
+
+
+def _slab_equilibrium(orc, scheme, Tr, steps=24000, H=160):
+    g, l = orc.maxwell(Tr)
+    p = orc.Params(nx=1, ny=H, Tr=Tr, k=0.1, kappa=0.004, scheme=orc.SCHEME_NAMES[scheme])
+    s = orc.Sim(p, inputs.slab((H, 1), 0, 10.0, g, l, amplitude=0.0))
+    s.step(steps)
+    r, vx, vy, _ = s.macros()
+    return (r[H // 2, 0] - l) / l, (r[0, 0] - g) / g, np.abs(vy).max()
+
+
+@pytest.mark.parametrize("scheme,Tr", [("CD4", 0.7), ("CD6", 0.8), ("OCFDS4", 0.8)])
+def test_flat_interface_liquid_density_vs_maxwell(orc, scheme, Tr):
+    """Sec 3.4 / Fig 13: a flat liquid layer relaxes to a liquid density within
+    1e-3 of the Maxwell construction with the accurate schemes.  Under the SRT
+    reading the gas density settles 15-25 % above the Maxwell value for every
+    scheme (an inconsistency of the forcing, not of the stencil order): that
+    part is recorded, with a loose bound, not claimed as agreement."""
+    el, eg, U = _slab_equilibrium(orc, scheme, Tr)
+    assert U < 2e-5
+    assert abs(el) < 1e-3
+    assert 0.0 < eg < 0.3
+
+
+def test_flat_interface_isotropic_deviates_more(orc):
+    """Sec 3.4: the coexistence densities of E4 deviate from the Maxwell curve
+    more than those of the fourth-order schemes."""
+    el4, eg4, _ = _slab_equilibrium(orc, "E4", 0.9)
+    elc, egc, _ = _slab_equilibrium(orc, "CD4", 0.9)
+    assert abs(el4) > 5 * abs(elc)

@@ -1,0 +1,296 @@
+"""Pins of the oracle's difference operators (Sec 2.3, Sec 3.1) against what the
+paper and mathematics fix: polynomial exactness, the Table 1 truncation
+constants, the modified wavenumber of Eq 28, the isotropy conditions that
+determine the weights of Eq 25, and brute-force cyclic solves."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import sympy as sp
+
+# Table 1 parameter sets (a, b, c, alpha) and their truncation constant C and
+# order p: D f - f' = C h^p f^(p+1).
+TABLE1 = {
+    "CD2": (dict(a=1, b=0, c=0, al=0), Fraction(1, math.factorial(3)), 2),
+    "CD4": (dict(a=Fraction(4, 3), b=Fraction(-1, 3), c=0, al=0), Fraction(-4, math.factorial(5)), 4),
+    "CD6": (dict(a=Fraction(3, 2), b=Fraction(-3, 5), c=Fraction(1, 10), al=0), Fraction(36, math.factorial(7)), 6),
+    "CFDS4": (dict(a=Fraction(3, 2), b=0, c=0, al=Fraction(1, 4)), Fraction(-1, math.factorial(5)), 4),
+    "CFDS6": (dict(a=Fraction(14, 9), b=Fraction(1, 9), c=0, al=Fraction(1, 3)), Fraction(4, math.factorial(7)), 6),
+    "CFDS8": (dict(a=Fraction(25, 16), b=Fraction(1, 5), c=Fraction(-1, 80), al=Fraction(3, 8)),
+              Fraction(-36, math.factorial(9)), 8),
+}
+# OCFDS4 as printed in Sec 3.1
+OCFDS_PRINTED = dict(a=1.541, b=0.40667, c=-0.0541132, al=0.446776)
+
+
+def eq28(w, a, b, c, al, beta=0.0):
+    """Modified wavenumber of Eq 28 (the printed 'cos 2 alpha' read as cos 2w)."""
+    return (a * np.sin(w) + b / 2 * np.sin(2 * w) + c / 3 * np.sin(3 * w)) / (
+        1 + 2 * al * np.cos(w) + 2 * beta * np.cos(2 * w))
+
+
+def rows(vals, ny=3):
+    return np.tile(np.asarray(vals, dtype=np.float64), (ny, 1))
+
+
+# --------------------------------------------------------------------------- #
+# Explicit schemes: polynomial exactness and Table 1 constants (exact)          #
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("name", ["CD2", "CD4", "CD6"])
+def test_explicit_gradient_polynomials_and_table1(orc, name):
+    sch = orc.SCHEME_NAMES[name]
+    _, C, p = TABLE1[name]
+    n, i0 = 40, 20
+    x = np.arange(n) - i0
+    for deg in range(0, p + 1):
+        g = rows(x.astype(float) ** deg)
+        d = orc.grad(g, sch)[0][1, i0]
+        exact = 1.0 if deg == 1 else 0.0
+        assert d == pytest.approx(exact, abs=1e-12), (name, deg)
+    # degree p+1: error is exactly C (p+1)! (h = 1), Table 1
+    g = rows(x.astype(float) ** (p + 1))
+    d = orc.grad(g, sch)[0][1, i0]
+    assert d == pytest.approx(float(C * math.factorial(p + 1)), rel=1e-12)
+
+
+@pytest.mark.parametrize("name,order", [("CD2", 2), ("CD4", 4), ("CD6", 6)])
+def test_explicit_laplacian_polynomials(orc, name, order):
+    sch = orc.SCHEME_NAMES[name]
+    n, i0 = 40, 20
+    x = np.arange(n) - i0
+    for deg in range(0, order + 2):
+        g = rows(x.astype(float) ** deg)
+        lap = orc.lap(g, sch)[1, i0]
+        exact = 2.0 if deg == 2 else 0.0
+        assert lap == pytest.approx(exact, abs=1e-10), (name, deg)
+    g = rows(x.astype(float) ** (order + 2))
+    lap = orc.lap(g, sch)[1, i0]
+    assert abs(lap) > 1.0  # not exact beyond its order
+
+
+# --------------------------------------------------------------------------- #
+# Table 1 constants of every row from the Taylor series of Eq 28               #
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("name", list(TABLE1))
+def test_table1_from_eq28_series(name):
+    pars, C, p = TABLE1[name]
+    w = sp.symbols("w")
+    a, b, c, al = (sp.Rational(pars[k].numerator, pars[k].denominator) if isinstance(pars[k], Fraction)
+                   else sp.Integer(pars[k]) for k in ("a", "b", "c", "al"))
+    num = a * sp.sin(w) + b / 2 * sp.sin(2 * w) + c / 3 * sp.sin(3 * w)
+    den = 1 + 2 * al * sp.cos(w)
+    # Table 1 gives the residual of Eq 21 (right side minus left side) with exact
+    # derivatives; on e^{iwx} it is i (num - w den) = C (i w)^(p+1) (h = 1).
+    ser = sp.series(num - w * den, w, 0, p + 3).removeO()
+    lead = sp.nsimplify(ser.coeff(w, p + 1))
+    assert sp.simplify(lead - sp.Rational(C.numerator, C.denominator) * sp.I ** p) == 0
+    for q in range(1, p + 1):
+        assert sp.simplify(ser.coeff(w, q)) == 0
+
+
+def test_ocfds_family_truncation_and_derived_coefficients(orc):
+    """Sec 3.1: the fourth-order compact family has error (12b + 72c - 4 alpha)/5!;
+    the oracle keeps the printed alpha, c and derives a, b from the order
+    conditions; they must round to the printed a = 1.541, b = 0.40667."""
+    al, a, b, c = orc.compact_coeffs(orc.OCFDS4)
+    assert al == OCFDS_PRINTED["al"] and c == OCFDS_PRINTED["c"]
+    assert a + b + c == pytest.approx(1 + 2 * al, abs=1e-15)
+    assert a + 4 * b + 9 * c == pytest.approx(6 * al, abs=1e-14)
+    assert round(a, 3) == OCFDS_PRINTED["a"]
+    assert round(b, 5) == OCFDS_PRINTED["b"]
+    # family error constant from the Taylor series equals (12b + 72c - 4 alpha)/5!
+    w = sp.symbols("w")
+    A, B, Cc, AL = (sp.nsimplify(v, rational=True) for v in (a, b, c, al))
+    num = A * sp.sin(w) + B / 2 * sp.sin(2 * w) + Cc / 3 * sp.sin(3 * w)
+    ser = sp.series(num - w * (1 + 2 * AL * sp.cos(w)), w, 0, 7).removeO()
+    assert abs(float(ser.coeff(w, 3))) < 1e-12
+    assert float(ser.coeff(w, 5)) == pytest.approx(float((12 * B + 72 * Cc - 4 * AL) / 120), rel=1e-9)
+
+
+@pytest.mark.parametrize("name", ["CFDS4", "CFDS6", "CFDS8"])
+def test_compact_coefficients_match_eq22_24(orc, name):
+    pars, _, _ = TABLE1[name]
+    al, a, b, c = orc.compact_coeffs(orc.SCHEME_NAMES[name])
+    assert (al, a, b, c) == pytest.approx((float(pars["al"]), float(pars["a"]), float(pars["b"]), float(pars["c"])),
+                                          abs=1e-15)
+
+
+@pytest.mark.parametrize("name,deg", [("OCFDS4", 4), ("CFDS4", 4), ("CFDS6", 6), ("CFDS8", 8)])
+def test_compact_relation_exact_on_polynomials(orc, name, deg):
+    """Eq 21 holds with the exact derivative of every polynomial up to the order."""
+    al, a, b, c = orc.compact_coeffs(orc.SCHEME_NAMES[name])
+    for d in range(deg + 1):
+        f = lambda x: float(x) ** d
+        fp = lambda x: d * float(x) ** (d - 1) if d > 0 else 0.0
+        lhs = al * fp(-1) + fp(0) + al * fp(1)
+        rhs = a * (f(1) - f(-1)) / 2 + b * (f(2) - f(-2)) / 4 + c * (f(3) - f(-3)) / 6
+        assert lhs == pytest.approx(rhs, abs=1e-12), (name, d)
+
+
+# --------------------------------------------------------------------------- #
+# Modified wavenumber (Eq 28) on periodic sine waves, all schemes               #
+# --------------------------------------------------------------------------- #
+def scheme_pars(orc, name):
+    if name in ("CD2", "CD4", "CD6"):
+        pars = TABLE1[name][0]
+        return float(pars["a"]), float(pars["b"]), float(pars["c"]), 0.0
+    al, a, b, c = orc.compact_coeffs(orc.SCHEME_NAMES[name])
+    return a, b, c, al
+
+
+@pytest.mark.parametrize("name", ["CD2", "CD4", "CD6", "OCFDS4", "CFDS4", "CFDS6", "CFDS8"])
+@pytest.mark.parametrize("n", [16, 37, 64])
+def test_modified_wavenumber_exact(orc, name, n):
+    sch = orc.SCHEME_NAMES[name]
+    a, b, c, al = scheme_pars(orc, name)
+    x = np.arange(n)
+    for m in (1, 3, n // 4, n // 2 - 1):
+        w = 2 * np.pi * m / n
+        g = rows(np.sin(w * x + 0.3))
+        d = orc.grad(g, sch)[0][1]
+        np.testing.assert_allclose(d, eq28(w, a, b, c, al) * np.cos(w * x + 0.3), atol=1e-13)
+        # Laplacian: matched second difference (explicit) or D(D) (compact)
+        L = orc.lap(g, sch)[1]
+        if al == 0.0:
+            r = {"CD2": [(-2, 1)], "CD4": [(-30 / 12, 16 / 12, -1 / 12)], "CD6": [(-490 / 180, 270 / 180, -27 / 180, 2 / 180)]}
+            cs = {"CD2": (-2.0, 1.0), "CD4": (-30 / 12, 16 / 12, -1 / 12), "CD6": (-490 / 180, 270 / 180, -27 / 180, 2 / 180)}[name]
+            sym = cs[0] + sum(2 * cs[k] * np.cos(k * w) for k in range(1, len(cs)))
+        else:
+            sym = -eq28(w, a, b, c, al) ** 2
+        np.testing.assert_allclose(L, sym * np.sin(w * x + 0.3), atol=1e-12)
+
+
+def test_ocfds_printed_curve(orc):
+    """The oracle's OCFDS curve agrees with Eq 28 at the printed (rounded)
+    coefficients to the rounding of the print, and beats CFDS8 in resolution
+    over the upper wavenumber range (Sec 3.1)."""
+    a, b, c, al = scheme_pars(orc, "OCFDS4")
+    w = np.linspace(0.01, np.pi - 0.01, 200)
+    p = OCFDS_PRINTED
+    assert np.max(np.abs(eq28(w, a, b, c, al) - eq28(w, p["a"], p["b"], p["c"], p["al"]))) < 2e-5
+    a8, b8, c8, al8 = scheme_pars(orc, "CFDS8")
+    hi = (w > 2.0) & (w < 2.6)
+    assert np.all(np.abs(eq28(w[hi], a, b, c, al) - w[hi]) < np.abs(eq28(w[hi], a8, b8, c8, al8) - w[hi]))
+
+
+def test_multidim_waves_per_axis(orc):
+    """Per-axis schemes act on each axis separately in 2D and 3D."""
+    nz, ny, nx = 12, 10, 14
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    kx, ky, kz = 2 * np.pi * 3 / nx, 2 * np.pi * 2 / ny, 2 * np.pi * 5 / nz
+    g = np.sin(kx * x + ky * y + kz * z)
+    for name in ("CD4", "OCFDS4"):
+        a, b, c, al = scheme_pars(orc, name)
+        G = orc.grad(g, orc.SCHEME_NAMES[name])
+        for comp, k in zip(G, (kx, ky, kz)):
+            np.testing.assert_allclose(comp, eq28(k, a, b, c, al) * np.cos(kx * x + ky * y + kz * z), atol=1e-12)
+
+
+# --------------------------------------------------------------------------- #
+# Cyclic tridiagonal solver vs dense inversion (brute force)                   #
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("n", list(range(1, 17)))
+def test_cyclic_solve_bruteforce(orc, n):
+    rng = np.random.default_rng(n)
+    for al in (0.25, 1 / 3, 0.375, 0.446776):
+        A = np.eye(n)
+        for i in range(n):
+            A[i, (i - 1) % n] += al
+            A[i, (i + 1) % n] += al
+        d = rng.standard_normal(n)
+        np.testing.assert_allclose(orc.cyclic_solve(al, d), np.linalg.solve(A, d), atol=1e-12)
+
+
+# --------------------------------------------------------------------------- #
+# Isotropic schemes (Eq 25)                                                     #
+# --------------------------------------------------------------------------- #
+def _iso_weights_from_isotropy(dim, shells):
+    """Solve the isotropy conditions for the shell weights: the lattice tensors
+    sum_i w(|e_i|^2) e_i^(2m) are isotropic for 2m up to 2*len(shells) (2D) or
+    to the order the shells allow (3D), normalised by sum w e_x^2 = 1."""
+    vecs = {}
+    R = 2
+    rng_ = range(-R, R + 1)
+    for v in ([(x, y, 0) for x in rng_ for y in rng_] if dim == 2 else
+              [(x, y, z) for x in rng_ for y in rng_ for z in rng_]):
+        s = sum(t * t for t in v)
+        if s in shells:
+            vecs.setdefault(s, []).append(v)
+    W = sp.symbols("w0:%d" % len(shells))
+
+    def mom(px, py, pz=0):
+        return sum(W[j] * sum(sp.Integer(v[0]) ** px * sp.Integer(v[1]) ** py * sp.Integer(v[2]) ** pz
+                              for v in vecs[s]) for j, s in enumerate(shells))
+
+    eqs = [sp.Eq(mom(2, 0), 1)]
+    df = lambda k: sp.factorial2(k - 1) if k > 0 else 1
+    max_m = 4 if len(shells) > 2 else 2
+    for m in range(2, max_m + 1):
+        comps = []
+        if dim == 2:
+            comps = [(2 * a, 2 * (m - a), 0) for a in range(m, -1, -1)]
+        else:
+            for a in range(m, -1, -1):
+                for b in range(m - a, -1, -1):
+                    c = m - a - b
+                    if a >= b >= c:
+                        comps.append((2 * a, 2 * b, 2 * c))
+        ref = comps[0]
+        for comp in comps[1:]:
+            eqs.append(sp.Eq(mom(*comp) * df(ref[0]) * df(ref[1]) * df(ref[2]),
+                             mom(*ref) * df(comp[0]) * df(comp[1]) * df(comp[2])))
+    sol = sp.solve(eqs, W, dict=True)
+    assert len(sol) == 1
+    return {s: sol[0][W[j]] for j, s in enumerate(shells)}
+
+
+@pytest.mark.parametrize("dim,name,shells", [
+    (2, "E4", (1, 2)), (3, "E4", (1, 2)),
+    (2, "E8", (1, 2, 4, 5, 8)), (3, "E8", (1, 2, 3, 4, 5, 6, 8))])
+def test_isotropic_weights_from_isotropy(orc, dim, name, shells):
+    wts = _iso_weights_from_isotropy(dim, shells)
+    if (dim, name) == (2, "E4"):
+        # Sec 2.3.3 prints w(1) = 1/3, w(2) = 1/12
+        assert wts == {1: sp.Rational(1, 3), 2: sp.Rational(1, 12)}
+    e, w = orc.iso_stencil(dim, orc.SCHEME_NAMES[name])
+    for v, wv in zip(e, w):
+        s = int((v ** 2).sum())
+        assert wv == pytest.approx(float(wts[s]), rel=1e-15)
+    # every vector of every shell is present exactly once
+    counts = {}
+    for v in e:
+        counts[int((v ** 2).sum())] = counts.get(int((v ** 2).sum()), 0) + 1
+    assert set(counts) == set(shells)
+
+
+def test_e4_equals_cd2_on_one_dimensional_fields(orc):
+    rng = np.random.default_rng(5)
+    g = rows(rng.standard_normal(23), ny=9)
+    G4, L4 = orc.grad(g, orc.E4), orc.lap(g, orc.E4)
+    G2, L2 = orc.grad(g, orc.CD2), orc.lap(g, orc.CD2)
+    np.testing.assert_allclose(G4[0], G2[0], atol=1e-14)
+    np.testing.assert_allclose(G4[1], 0.0, atol=1e-14)
+    np.testing.assert_allclose(L4, L2, atol=1e-13)
+    g3 = np.tile(rng.standard_normal(21), (7, 8, 1))
+    np.testing.assert_allclose(orc.grad(g3, orc.E4)[0], orc.grad(g3, orc.CD2)[0], atol=1e-14)
+    np.testing.assert_allclose(orc.lap(g3, orc.E4), orc.lap(g3, orc.CD2), atol=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("name", ["E4", "E8"])
+def test_isotropic_second_order_exact_on_quadratics(orc, dim, name):
+    sch = orc.SCHEME_NAMES[name]
+    shape = (13, 14) if dim == 2 else (11, 12, 13)
+    idx = np.meshgrid(*[np.arange(s) - s // 2 for s in shape], indexing="ij")
+    coords = idx[::-1]  # x, y[, z]
+    centre = tuple(s // 2 for s in shape)
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((dim, dim)); A = A + A.T
+    bvec = rng.standard_normal(dim)
+    g = 0.5 * sum(A[i, j] * coords[i] * coords[j] for i in range(dim) for j in range(dim)) + \
+        sum(bvec[i] * coords[i] for i in range(dim)) + 0.7
+    G = orc.grad(g, sch)
+    for d in range(dim):
+        assert G[d][centre] == pytest.approx(bvec[d], abs=1e-11)
+    assert orc.lap(g, sch)[centre] == pytest.approx(np.trace(A), abs=1e-11)
