@@ -1,0 +1,131 @@
+/*
+ * lbm.h -- C ABI of the gfx950 chemical-potential multiphase lattice Boltzmann
+ * step (Qin, Chen, Qin, Xu, Wen, arXiv 2205.09186).
+ *
+ * One time step, in lattice units (dx = dt = c = 1, cs^2 = 1/3, Sec 2.1):
+ *   1. moments rho = sum_i f_i, rho u = sum_i e_i f_i                  (Eq 7)
+ *   2. mu_hat = k^2 psi'(rho) - kappa_hat lap(rho), Peng-Robinson psi'  (Eq 14-16)
+ *   3. F = -rho grad(mu_hat) + cs^2 grad(rho)                           (Eq 12)
+ *      with grad/lap from the chosen difference scheme                  (Sec 2.3)
+ *   4. SRT collision with exact-difference forcing, du = F / rho:
+ *      f*_i = f_i - (f_i - feq_i(rho,u))/tau + feq_i(rho,u+du) - feq_i(rho,u)
+ *                                                          (Eq 1 with s_i = 1/tau, Eq 6, Eq 8)
+ *   5. streaming f_i(x + e_i, t + 1) = f*_i(x, t), all axes periodic    (Eq 1)
+ * Observables use the actual fluid velocity v = u + F/(2 rho) (after Eq 8);
+ * the spurious current is max |v| over the domain (Sec 3.3).
+ *
+ * Conventions
+ *   - Every field is indexed x fastest, then y, then z; node coordinates run
+ *     0..n-1 on each axis.  D2Q9 requires nz = 1.  Every axis used must be at
+ *     least 4 nodes long.
+ *   - Pointers are plain host or device addresses as stated per argument; no
+ *     HIP or C++ type appears in a signature.  The HIP stream is passed as a
+ *     void* (a hipStream_t; NULL is the default stream).
+ *   - Return codes: LBM_OK (0) or a negative LBM_E* code; details of the last
+ *     failure are available from lbm_last_error().  No exception crosses the
+ *     ABI.  A context is not thread-safe; separate contexts on separate streams
+ *     are independent.
+ *   - Ownership: the caller owns the device workspace, the stream and every
+ *     array passed in.  The library owns the lbm_ctx (and any graph it
+ *     captures) and releases them in lbm_free().
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Lattices: D2Q9 of Eq 2; D3Q19 (the standard 19-velocity set) for 3D runs. */
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+
+/* Difference schemes of Sec 2.3:
+ *   CD2, CD4, CD6  explicit central first derivatives of Eq 18-20; Laplacian
+ *                  the matched-order central second difference per axis;
+ *   E4, E8         isotropic differences of Eq 25a/25b (fourth- and
+ *                  eighth-order isotropy);
+ *   OCFDS4         the optimised fourth-order compact scheme of Sec 3.1
+ *                  (Eq 21 with beta = 0, alpha = 0.446776, c = -0.0541132);
+ *   CFDS4/6/8      the compact schemes of Eq 22-24.
+ * For the compact schemes the Laplacian is D(D(rho)) per axis. */
+enum { LBM_CD2 = 0, LBM_CD4 = 1, LBM_CD6 = 2, LBM_E4 = 3, LBM_E8 = 4,
+       LBM_OCFDS4 = 5, LBM_CFDS4 = 6, LBM_CFDS6 = 7, LBM_CFDS8 = 8 };
+
+enum { LBM_OK = 0, LBM_EINVAL = -1, LBM_ENOSPC = -2, LBM_EHIP = -3,
+       LBM_ENONFINITE = -4, LBM_ESTATE = -5 };
+
+typedef struct {
+    int    lattice;          /* LBM_D2Q9 | LBM_D3Q19 */
+    int    nx, ny, nz;       /* grid; nz = 1 for D2Q9; periodic on every axis */
+    double tau;              /* relaxation time, > 0.5 (Sec 2.1) */
+    double Tr;               /* reduced temperature T/Tc, 0 < Tr < 1 (Sec 2.2) */
+    double k;                /* proportional coefficient of Eq 16, > 0 */
+    double kappa;            /* kappa-hat of Eq 16, > 0 */
+    int    scheme;           /* LBM_CD2 .. LBM_CFDS8 */
+    double a, b, R, omega;   /* Peng-Robinson constants of Eq 14; 0 selects the
+                                paper's a = 2/49, b = 2/21, R = 1, omega = 0.344 */
+} lbm_params;
+
+/* Bytes of device workspace lbm_init() needs for these parameters (0 if the
+ * parameters are invalid).  The caller allocates it (e.g. a torch uint8 tensor). */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Create a context on the device workspace d_workspace (>= ws_bytes bytes,
+ * 256-byte aligned, owned by the caller, must outlive the context) and set the
+ * populations to feq(rho0, 0) (the initial condition before Eq 26's run).
+ *   rho0            N = nx*ny*nz initial densities, each finite and in
+ *                   (0, 1/b); a host pointer if rho0_on_device == 0, else a
+ *                   device pointer.
+ *   hip_stream      stream every later call of this context is ordered on.
+ * Errors: LBM_EINVAL (bad parameters or rho0), LBM_ENOSPC (workspace too
+ * small), LBM_EHIP (runtime failure).  On success *out holds the context.
+ * Synchronises the stream before returning. */
+int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device,
+             void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
+
+/* Enqueue nsteps >= 0 time steps on the context's stream and return. */
+int lbm_step(lbm_ctx* c, long nsteps);
+
+/* Macroscopic fields of the current state: rho and v = u + F/(2 rho).
+ * Each output holds N doubles; vz may be NULL (ignored for D2Q9).  Host
+ * pointers if out_on_device == 0, else device pointers.  Synchronises. */
+int lbm_macros(lbm_ctx* c, double* rho, double* vx, double* vy, double* vz,
+               int out_on_device);
+
+/* Spurious current U = max |v| and total mass M = sum rho of the current
+ * state (host scalars).  Deterministic fixed-order reduction.  Synchronises.
+ * Returns LBM_ENONFINITE (values still written) if any rho or v is not finite
+ * or U exceeds the lattice sound speed. */
+int lbm_spurious_max(lbm_ctx* c, double* umax, double* mass);
+
+/* Copy the current post-streaming populations f[q*N + node] (Q*N doubles) to
+ * host (out_on_device == 0) or device memory.  Synchronises. */
+int lbm_populations(lbm_ctx* c, double* f, int out_on_device);
+
+/* Number of completed steps of the context. */
+long lbm_steps_done(const lbm_ctx* c);
+
+/* Release the context (never the caller's workspace).  NULL is allowed. */
+void lbm_free(lbm_ctx* c);
+
+/* Message of the last failure of this context, or of the calling thread's last
+ * failure when c is NULL.  Never NULL. */
+const char* lbm_last_error(const lbm_ctx* c);
+
+/* Critical point of Eq 14 with alpha = 1 (the Tc, rho_c of Sec 2.2 that the
+ * paper leaves unprinted), for the EOS constants in p (defaults for zeros). */
+int lbm_critical(const lbm_params* p, double* Tc, double* rho_c, double* p_c);
+
+/* Coexistence densities at p->Tr from the Maxwell equal-area construction
+ * (Sec 3.4), host computation.  LBM_EINVAL outside 0 < Tr < 1. */
+int lbm_coexistence(const lbm_params* p, double* rho_g, double* rho_l);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,441 @@
+// lbm.hip -- C ABI (include/lbm.h) of the gfx950 chemical-potential multiphase
+// LBM step (arXiv 2205.09186): context, workspace layout, launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm.h"
+#include "lbm_eos_host.hpp"
+#include "lbm_fused.hpp"
+#include "lbm_kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t S0, S1, rho, mu, grho, gmu, lap, wtmp, partial, result, total;
+    long long nparts;
+};
+
+PR eos_constants(const lbm_params* p)
+{
+    PR e;
+    e.a = p->a > 0.0 ? p->a : 2.0 / 49.0;
+    e.b = p->b > 0.0 ? p->b : 2.0 / 21.0;
+    e.R = p->R > 0.0 ? p->R : 1.0;
+    e.omega = p->omega > 0.0 ? p->omega : 0.344;
+    return e;
+}
+
+const char* validate(const lbm_params* p)
+{
+    if (!p) return "params is NULL";
+    if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19) return "unknown lattice";
+    if (p->nx < 4 || p->ny < 4) return "nx and ny must be >= 4";
+    if (p->lattice == LBM_D2Q9 && p->nz != 1) return "D2Q9 needs nz == 1";
+    if (p->lattice == LBM_D3Q19 && p->nz < 4) return "D3Q19 needs nz >= 4";
+    if ((long long)p->nx * p->ny * p->nz > (1LL << 40)) return "grid too large";
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return "tau must be > 0.5";
+    if (!(p->Tr > 0.0 && p->Tr < 1.0)) return "Tr must lie in (0, 1)";
+    if (!(p->k > 0.0) || !std::isfinite(p->k)) return "k must be > 0";
+    if (!(p->kappa > 0.0) || !std::isfinite(p->kappa)) return "kappa must be > 0";
+    if (p->scheme < LBM_CD2 || p->scheme > LBM_CFDS8) return "unknown scheme";
+    if (p->a < 0.0 || p->b < 0.0 || p->R < 0.0 || p->omega < 0.0) return "negative EOS constant";
+    return nullptr;
+}
+
+Layout layout_of(const lbm_params* p)
+{
+    Layout L{};
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    const int Q = p->lattice == LBM_D2Q9 ? 9 : 19;
+    const int dim = p->lattice == LBM_D2Q9 ? 2 : 3;
+    const bool compact = p->scheme >= LBM_OCFDS4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    L.S0 = take(sizeof(double) * Q * N);
+    L.S1 = take(sizeof(double) * Q * N);
+    L.rho = take(sizeof(double) * N);
+    L.mu = take(sizeof(double) * N);
+    if (compact) {
+        L.grho = take(sizeof(double) * dim * N);
+        L.gmu = take(sizeof(double) * dim * N);
+        L.lap = take(sizeof(double) * N);
+        L.wtmp = take(sizeof(double) * N);
+    }
+    L.nparts = (N + 255) / 256;
+    L.partial = take(sizeof(double) * 2 * L.nparts);
+    L.result = take(sizeof(double) * 2);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params p;
+    Grid g;
+    Eos eos;
+    int Q, dim;
+    double one_m_omega;
+    hipStream_t stream;
+    char* ws;
+    Layout L;
+    double *S[2], *rho, *mu, *grho, *gmu, *lap, *wtmp, *partial, *result;
+    int cur;        // index of the buffer holding the current state
+    long steps;
+    std::string err;
+    // compact-scheme line geometry per axis
+    LineGeom lines[3];
+    double z, zscale;
+};
+
+namespace {
+
+int fail(lbm_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    g_thread_error = msg;
+    return code;
+}
+
+int hip_check(lbm_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return LBM_OK;
+    return fail(c, LBM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <int LAT>
+void launch_init(lbm_ctx* c, const double* rho0)
+{
+    hipLaunchKernelGGL(k_init<LAT>, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                       rho0, c->S[c->cur], c->g);
+}
+
+// Compact derivative of field `in` along axis d into `out` (optionally added).
+void compact_deriv(lbm_ctx* c, const double* in, double* out, int d, bool accumulate)
+{
+    const LineGeom& lg = c->lines[d];
+    const Compact cc = compact_scheme(c->p.scheme);
+    const long long items = (long long)lg.n1 * lg.n2 * lg.nch;
+    hipLaunchKernelGGL(k_compact_fwd, dim3(blocks_for(items, 256)), dim3(256), 0, c->stream,
+                       in, c->wtmp, lg, cc, c->z);
+    hipLaunchKernelGGL(k_compact_bwd, dim3(blocks_for(items, 256)), dim3(256), 0, c->stream,
+                       c->wtmp, out, lg, c->z, c->zscale, accumulate ? 1 : 0);
+}
+
+// rho of the current state, then the chemical potential and (compact schemes)
+// the gradient fields that the force needs.
+template <int LAT, int SCH>
+void launch_fields(lbm_ctx* c)
+{
+    constexpr int DIM = Lat<LAT>::DIM;
+    const double* S = c->S[c->cur];
+    hipLaunchKernelGGL(k_rho<LAT>, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream, S, c->rho, c->g);
+    if constexpr (is_compact(SCH)) {
+        for (int d = 0; d < DIM; ++d) compact_deriv(c, c->rho, c->grho + d * c->g.N, d, false);
+        for (int d = 0; d < DIM; ++d) compact_deriv(c, c->grho + d * c->g.N, c->lap, d, d > 0);
+        hipLaunchKernelGGL(k_mu_lap, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                           c->rho, c->lap, c->mu, c->g.N, c->eos);
+        for (int d = 0; d < DIM; ++d) compact_deriv(c, c->mu, c->gmu + d * c->g.N, d, false);
+    } else {
+        hipLaunchKernelGGL((k_mu<DIM, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                           c->rho, c->mu, c->g, c->eos);
+    }
+}
+
+template <int LAT, int SCH>
+void launch_step(lbm_ctx* c)
+{
+    if constexpr (!is_compact(SCH)) {
+        if (fused_available<LAT, SCH>(c->g)) {
+            launch_fused_step<LAT, SCH>(c->S[c->cur], c->S[1 - c->cur], c->rho, c->mu, c->g, c->eos,
+                                        c->one_m_omega, c->stream);
+            c->cur = 1 - c->cur;
+            return;
+        }
+    }
+    launch_fields<LAT, SCH>(c);
+    hipLaunchKernelGGL((k_collide<LAT, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                       c->S[c->cur], c->S[1 - c->cur], c->rho, c->mu, c->grho, c->gmu, c->g, c->one_m_omega);
+    c->cur = 1 - c->cur;
+}
+
+template <int LAT, int SCH>
+void launch_macros(lbm_ctx* c, double* orho, double* ovx, double* ovy, double* ovz)
+{
+    launch_fields<LAT, SCH>(c);
+    hipLaunchKernelGGL((k_macros<LAT, SCH>), dim3((unsigned)c->L.nparts), dim3(256), 0, c->stream,
+                       c->S[c->cur], c->rho, c->mu, c->grho, c->gmu, c->g, orho, ovx, ovy, ovz, c->partial);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->stream, c->partial, c->L.nparts, c->result);
+}
+
+// Runtime (lattice, scheme) -> template dispatch.
+template <template <int, int> class Op, typename... A>
+void dispatch(int lat, int sch, A... a)
+{
+#define LBM_CASE(L_, S_) case S_: Op<L_, S_>::run(a...); return;
+    if (lat == LBM_D2Q9) {
+        switch (sch) {
+            LBM_CASE(0, 0) LBM_CASE(0, 1) LBM_CASE(0, 2) LBM_CASE(0, 3) LBM_CASE(0, 4)
+            LBM_CASE(0, 5) LBM_CASE(0, 6) LBM_CASE(0, 7) LBM_CASE(0, 8)
+        }
+    } else {
+        switch (sch) {
+            LBM_CASE(1, 0) LBM_CASE(1, 1) LBM_CASE(1, 2) LBM_CASE(1, 3) LBM_CASE(1, 4)
+            LBM_CASE(1, 5) LBM_CASE(1, 6) LBM_CASE(1, 7) LBM_CASE(1, 8)
+        }
+    }
+#undef LBM_CASE
+}
+
+template <int LAT, int SCH> struct StepOp { static void run(lbm_ctx* c) { launch_step<LAT, SCH>(c); } };
+template <int LAT, int SCH> struct MacrosOp {
+    static void run(lbm_ctx* c, double* r, double* x, double* y, double* z) { launch_macros<LAT, SCH>(c, r, x, y, z); }
+};
+
+void set_lines(lbm_ctx* c)
+{
+    const int n[3] = { c->p.nx, c->p.ny, c->p.nz };
+    const long long st[3] = { 1, (long long)c->p.nx, (long long)c->p.nx * c->p.ny };
+    for (int d = 0; d < 3; ++d) {
+        LineGeom& lg = c->lines[d];
+        const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+        lg.n = n[d]; lg.sa = st[d];
+        lg.n1 = n[o1]; lg.s1 = st[o1];
+        lg.n2 = n[o2]; lg.s2 = st[o2];
+        lg.C = 64;
+        lg.nch = (lg.n + lg.C - 1) / lg.C;
+        lg.K = 0;
+    }
+    if (c->p.scheme >= LBM_OCFDS4) {
+        const Compact cc = compact_scheme(c->p.scheme);
+        c->z = (-1.0 + std::sqrt(1.0 - 4.0 * cc.al * cc.al)) / (2.0 * cc.al);
+        c->zscale = 1.0 + c->z * c->z;
+        const int K = (int)std::ceil(std::log(1e-18) / std::log(std::fabs(c->z)));
+        for (int d = 0; d < 3; ++d) c->lines[d].K = K;
+    } else {
+        c->z = 0.0; c->zscale = 1.0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params* p)
+{
+    if (validate(p)) return 0;
+    return layout_of(p).total;
+}
+
+int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* d_workspace,
+             size_t ws_bytes, void* hip_stream, lbm_ctx** out)
+{
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (const char* why = validate(p)) return fail(nullptr, LBM_EINVAL, why);
+    if (!rho0) return fail(nullptr, LBM_EINVAL, "rho0 is NULL");
+    if (!d_workspace) return fail(nullptr, LBM_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+        return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+    const Layout L = layout_of(p);
+    if (ws_bytes < L.total)
+        return fail(nullptr, LBM_ENOSPC, "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_EHIP, "out of host memory");
+    c->p = *p;
+    c->Q = p->lattice == LBM_D2Q9 ? 9 : 19;
+    c->dim = p->lattice == LBM_D2Q9 ? 2 : 3;
+    c->g.nx = p->nx; c->g.ny = p->ny; c->g.nz = p->nz;
+    c->g.nxy = (long long)p->nx * p->ny;
+    c->g.N = c->g.nxy * p->nz;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->ws = static_cast<char*>(d_workspace);
+    c->L = L;
+    c->S[0] = reinterpret_cast<double*>(c->ws + L.S0);
+    c->S[1] = reinterpret_cast<double*>(c->ws + L.S1);
+    c->rho = reinterpret_cast<double*>(c->ws + L.rho);
+    c->mu = reinterpret_cast<double*>(c->ws + L.mu);
+    const bool compact = p->scheme >= LBM_OCFDS4;
+    c->grho = compact ? reinterpret_cast<double*>(c->ws + L.grho) : nullptr;
+    c->gmu = compact ? reinterpret_cast<double*>(c->ws + L.gmu) : nullptr;
+    c->lap = compact ? reinterpret_cast<double*>(c->ws + L.lap) : nullptr;
+    c->wtmp = compact ? reinterpret_cast<double*>(c->ws + L.wtmp) : nullptr;
+    c->partial = reinterpret_cast<double*>(c->ws + L.partial);
+    c->result = reinterpret_cast<double*>(c->ws + L.result);
+    c->cur = 0;
+    c->steps = 0;
+    c->one_m_omega = 1.0 - 1.0 / p->tau;
+    set_lines(c);
+
+    // equation of state in mesh units (Eq 16): k^2 psi'
+    const PR e = eos_constants(p);
+    double Tc, rc, pc;
+    pr_critical(e, Tc, rc, pc);
+    const double T = p->Tr * Tc;
+    const double aa = e.a * pr_alpha(p->Tr, e.omega);
+    const double k2 = p->k * p->k;
+    c->eos.k2RT = k2 * e.R * T;
+    c->eos.k2c = k2 * aa / (2.0 * std::sqrt(2.0) * e.b);
+    c->eos.k2aa = k2 * aa;
+    c->eos.b = e.b;
+    c->eos.kappa = p->kappa;
+
+    // initial density: validate on the host, stage through the rho buffer
+    const long long N = c->g.N;
+    const double rho_max = 1.0 / e.b;
+    int rc_ = LBM_OK;
+    if (!rho0_on_device) {
+        for (long long n = 0; n < N; ++n) {
+            const double r = rho0[n];
+            if (!(r > 0.0 && r < rho_max)) { rc_ = fail(c, LBM_EINVAL, "rho0 must be finite and in (0, 1/b)"); break; }
+        }
+        if (rc_ == LBM_OK)
+            rc_ = hip_check(c, hipMemcpyAsync(c->rho, rho0, sizeof(double) * N, hipMemcpyHostToDevice, c->stream),
+                            "copy rho0");
+    } else {
+        rc_ = hip_check(c, hipMemcpyAsync(c->rho, rho0, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream),
+                        "copy rho0");
+    }
+    if (rc_ == LBM_OK) {
+        if (p->lattice == LBM_D2Q9) launch_init<0>(c, c->rho); else launch_init<1>(c, c->rho);
+        rc_ = hip_check(c, hipGetLastError(), "init launch");
+    }
+    if (rc_ == LBM_OK) rc_ = hip_check(c, hipStreamSynchronize(c->stream), "init sync");
+    if (rc_ == LBM_OK && rho0_on_device) {
+        // a device rho0 is validated through the observables of the initial state
+        double um, ms;
+        int r2 = lbm_spurious_max(c, &um, &ms);
+        if (r2 == LBM_ENONFINITE) rc_ = fail(c, LBM_EINVAL, "rho0 on device is not finite");
+        else if (r2 != LBM_OK) rc_ = r2;
+    }
+    if (rc_ != LBM_OK) { delete c; return rc_; }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, long nsteps)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+    for (long s = 0; s < nsteps; ++s) {
+        dispatch<StepOp>(c->p.lattice, c->p.scheme, c);
+        c->steps++;
+    }
+    return hip_check(c, hipGetLastError(), "step launch");
+}
+
+int lbm_macros(lbm_ctx* c, double* rho, double* vx, double* vy, double* vz, int out_on_device)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (c->dim == 2) vz = nullptr;
+    const long long N = c->g.N;
+    if (out_on_device) {
+        dispatch<MacrosOp>(c->p.lattice, c->p.scheme, c, rho, vx, vy, vz);
+        int r = hip_check(c, hipGetLastError(), "macros launch");
+        if (r) return r;
+        return hip_check(c, hipStreamSynchronize(c->stream), "macros sync");
+    }
+    // host outputs: compute into device scratch (the gradient buffers are free
+    // between steps only for compact schemes, so use the two population-sized
+    // halves of the idle buffer), then copy
+    double* idle = c->S[1 - c->cur];
+    double* d_r = idle;
+    double* d_x = idle + N;
+    double* d_y = idle + 2 * N;
+    double* d_z = c->dim == 3 ? idle + 3 * N : nullptr;
+    dispatch<MacrosOp>(c->p.lattice, c->p.scheme, c, d_r, d_x, d_y, d_z);
+    int r = hip_check(c, hipGetLastError(), "macros launch");
+    if (r) return r;
+    const size_t b = sizeof(double) * N;
+    if (rho && (r = hip_check(c, hipMemcpyAsync(rho, d_r, b, hipMemcpyDeviceToHost, c->stream), "copy rho"))) return r;
+    if (vx && (r = hip_check(c, hipMemcpyAsync(vx, d_x, b, hipMemcpyDeviceToHost, c->stream), "copy vx"))) return r;
+    if (vy && (r = hip_check(c, hipMemcpyAsync(vy, d_y, b, hipMemcpyDeviceToHost, c->stream), "copy vy"))) return r;
+    if (vz && d_z && (r = hip_check(c, hipMemcpyAsync(vz, d_z, b, hipMemcpyDeviceToHost, c->stream), "copy vz")))
+        return r;
+    return hip_check(c, hipStreamSynchronize(c->stream), "macros sync");
+}
+
+int lbm_spurious_max(lbm_ctx* c, double* umax, double* mass)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    dispatch<MacrosOp>(c->p.lattice, c->p.scheme, c, (double*)nullptr, (double*)nullptr, (double*)nullptr,
+                       (double*)nullptr);
+    int r = hip_check(c, hipGetLastError(), "observables launch");
+    if (r) return r;
+    double h[2];
+    r = hip_check(c, hipMemcpyAsync(h, c->result, sizeof(h), hipMemcpyDeviceToHost, c->stream), "copy result");
+    if (r) return r;
+    r = hip_check(c, hipStreamSynchronize(c->stream), "observables sync");
+    if (r) return r;
+    if (umax) *umax = h[0];
+    if (mass) *mass = h[1];
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || h[0] > std::sqrt(1.0 / 3.0))
+        return fail(c, LBM_ENONFINITE, "non-finite state or |v| above the lattice sound speed");
+    return LBM_OK;
+}
+
+int lbm_populations(lbm_ctx* c, double* f, int out_on_device)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (!f) return fail(c, LBM_EINVAL, "f is NULL");
+    // The stored buffer holds post-collision values at their source nodes;
+    // the post-streaming state is their pull, staged in the idle buffer.
+    const long long N = c->g.N;
+    const double* S = c->S[c->cur];
+    double* tmp = c->S[1 - c->cur];
+    if (c->p.lattice == LBM_D2Q9)
+        hipLaunchKernelGGL(k_pull_all<0>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, S, tmp, c->g);
+    else
+        hipLaunchKernelGGL(k_pull_all<1>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, S, tmp, c->g);
+    int r = hip_check(c, hipGetLastError(), "pull launch");
+    if (r) return r;
+    r = hip_check(c, hipMemcpyAsync(f, tmp, sizeof(double) * c->Q * N,
+                                    out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+                  "copy populations");
+    if (r) return r;
+    return hip_check(c, hipStreamSynchronize(c->stream), "populations sync");
+}
+
+long lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+void lbm_free(lbm_ctx* c) { delete c; }
+
+const char* lbm_last_error(const lbm_ctx* c)
+{
+    if (c) return c->err.c_str();
+    return g_thread_error.c_str();
+}
+
+int lbm_critical(const lbm_params* p, double* Tc, double* rho_c, double* p_c)
+{
+    if (!p || !Tc || !rho_c || !p_c) return fail(nullptr, LBM_EINVAL, "NULL argument");
+    pr_critical(eos_constants(p), *Tc, *rho_c, *p_c);
+    return LBM_OK;
+}
+
+int lbm_coexistence(const lbm_params* p, double* rho_g, double* rho_l)
+{
+    if (!p || !rho_g || !rho_l) return fail(nullptr, LBM_EINVAL, "NULL argument");
+    if (!pr_coexistence(eos_constants(p), p->Tr, *rho_g, *rho_l))
+        return fail(nullptr, LBM_EINVAL, "no coexistence at this Tr");
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// lbm_physics.hpp -- lattice, equilibrium, collision and equation of state for
+// the gfx950 step of the chemical-potential multiphase LBM (arXiv 2205.09186).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Velocity sets.
+// D2Q9 in the order of Eq 2: rest, the four axis links at angles (i-1) pi/2,
+// the four diagonals at angles (2i-9) pi/4.  D3Q19: rest, six axis links,
+// twelve edge links.  Weights 4/9, 1/9, 1/36 (Eq 6) and 1/3, 1/18, 1/36.  The
+// rest weight is the FP64 value that makes the rounded weights sum to exactly
+// one, so collision adds no systematic mass: 4/9 and 1/3 rounded up by one ulp.
+// ---------------------------------------------------------------------------
+template <int LAT> struct Lat;
+
+template <> struct Lat<0> {
+    static constexpr int Q = 9, DIM = 2;
+    __host__ __device__ static constexpr int ex(int i) {
+        return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int ey(int i) {
+        return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int ez(int) { return 0; }
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 0x1.c71c71c71c71dp-2 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+};
+
+template <> struct Lat<1> {
+    static constexpr int Q = 19, DIM = 3;
+    // rest; +x -x +y -y +z -z; xy edges; xz edges; yz edges
+    __host__ __device__ static constexpr int ex(int i) {
+        return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+             : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+    }
+    __host__ __device__ static constexpr int ey(int i) {
+        return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+             : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+    }
+    __host__ __device__ static constexpr int ez(int i) {
+        return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+             : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+    }
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 0x1.5555555555556p-2 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Collision at one node: SRT reduction of Eq 1 with exact-difference forcing
+// (Eq 8), equilibrium of Eq 6 with cs^2 = 1/3:
+//   f*_i = feq_i(rho, u + du) + (1 - 1/tau) (f_i - feq_i(rho, u)),  du = F/rho.
+// ---------------------------------------------------------------------------
+template <int LAT>
+__device__ __forceinline__ void collide(const double (&f)[Lat<LAT>::Q], double rho,
+                                        double jx, double jy, double jz,
+                                        double Fx, double Fy, double Fz, double one_m_omega,
+                                        double (&out)[Lat<LAT>::Q])
+{
+    using L = Lat<LAT>;
+    const double ir = 1.0 / rho;
+    const double ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const double vx = ux + Fx * ir, vy = uy + Fy * ir, vz = uz + Fz * ir;
+    const double uu = 1.0 - 1.5 * (ux * ux + uy * uy + uz * uz);
+    const double vv = 1.0 - 1.5 * (vx * vx + vy * vy + vz * vz);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double wr = L::w(i) * rho;
+        const double eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
+        const double ev = L::ex(i) * vx + L::ey(i) * vy + L::ez(i) * vz;
+        const double fe = wr * (uu + eu * (3.0 + 4.5 * eu));
+        const double fv = wr * (vv + ev * (3.0 + 4.5 * ev));
+        out[i] = fv + one_m_omega * (f[i] - fe);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Peng-Robinson bulk chemical potential psi'(rho) (Eq 15 without the gradient
+// term, integration constant zero), scaled by k^2 (Eq 16).  With x = b rho,
+// g = 1 - x, A = sqrt2 - 1 + x, B = sqrt2 + 1 - x and A B = 1 + 2x - x^2:
+//   psi' = RT ln(rho/g) - aa/(2 sqrt2 b) ln(A/B) + RT/g - aa rho/(A B).
+// The three quotients share one division.
+// ---------------------------------------------------------------------------
+struct Eos {
+    double k2RT;     // k^2 R T
+    double k2c;      // k^2 aa / (2 sqrt2 b)
+    double k2aa;     // k^2 a alpha(T)
+    double b;
+    double kappa;    // kappa-hat
+};
+
+__host__ __device__ __forceinline__ double mu_bulk(double rho, const Eos& e)
+{
+    const double s2 = 1.4142135623730951;
+    const double x = e.b * rho;
+    const double g = 1.0 - x, A = (s2 - 1.0) + x, B = (s2 + 1.0) - x;
+    const double inv = 1.0 / (g * (A * B));
+    const double inv_g = (A * B) * inv;
+    const double inv_B = (g * A) * inv;
+    const double inv_AB = g * inv;
+    return e.k2RT * (log(rho * inv_g) + inv_g) - e.k2c * log(A * inv_B) - e.k2aa * rho * inv_AB;
+}
+
+}  // namespace lbm

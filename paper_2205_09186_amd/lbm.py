@@ -1,0 +1,214 @@
+"""Python binding of the gfx950 library (``include/lbm.h``): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of ``liblbm.so``; PyTorch only
+provides device memory (the workspace and device-side arrays) and the stream.
+The binding refuses to run when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+D2Q9, D3Q19 = 0, 1
+CD2, CD4, CD6, E4, E8, OCFDS4, CFDS4, CFDS6, CFDS8 = range(9)
+SCHEMES = {"CD2": CD2, "CD4": CD4, "CD6": CD6, "E4": E4, "E8": E8, "OCFDS4": OCFDS4,
+           "CFDS4": CFDS4, "CFDS6": CFDS6, "CFDS8": CFDS8}
+LBM_OK, LBM_EINVAL, LBM_ENOSPC, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+class lbm_params(C.Structure):
+    _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("tau", C.c_double), ("Tr", C.c_double), ("k", C.c_double), ("kappa", C.c_double),
+                ("scheme", C.c_int), ("a", C.c_double), ("b", C.c_double), ("R", C.c_double),
+                ("omega", C.c_double)]
+
+
+_lib = None
+
+# Every symbol the header declares, with (restype, argtypes).
+_P = C.POINTER(lbm_params)
+_D = C.POINTER(C.c_double)
+SYMBOLS = {
+    "lbm_workspace_bytes": (C.c_size_t, [_P]),
+    "lbm_init": (C.c_int, [_P, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbm_step": (C.c_int, [C.c_void_p, C.c_long]),
+    "lbm_macros": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "lbm_spurious_max": (C.c_int, [C.c_void_p, _D, _D]),
+    "lbm_populations": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "lbm_steps_done": (C.c_long, [C.c_void_p]),
+    "lbm_free": (None, [C.c_void_p]),
+    "lbm_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_critical": (C.c_int, [_P, _D, _D, _D]),
+    "lbm_coexistence": (C.c_int, [_P, _D, _D]),
+}
+
+
+def lib():
+    """Load liblbm.so (fails loudly if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SYMBOLS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _err(ctx=None) -> str:
+    m = lib().lbm_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def _check(code: int, ctx=None):
+    if code != LBM_OK:
+        raise LbmError(code, _err(ctx))
+
+
+@dataclass
+class Params:
+    lattice: int = D2Q9
+    nx: int = 100
+    ny: int = 100
+    nz: int = 1
+    tau: float = 1.0
+    Tr: float = 0.8
+    k: float = 0.16
+    kappa: float = 0.004
+    scheme: int = CD4
+    a: float = 0.0
+    b: float = 0.0
+    R: float = 0.0
+    omega: float = 0.0
+
+    def c(self) -> lbm_params:
+        return lbm_params(self.lattice, self.nx, self.ny, self.nz, self.tau, self.Tr, self.k, self.kappa,
+                          self.scheme, self.a, self.b, self.R, self.omega)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def q(self) -> int:
+        return 9 if self.lattice == D2Q9 else 19
+
+    @property
+    def shape(self):
+        return (self.ny, self.nx) if self.lattice == D2Q9 else (self.nz, self.ny, self.nx)
+
+
+def workspace_bytes(p: Params) -> int:
+    cp = p.c()
+    return int(lib().lbm_workspace_bytes(C.byref(cp)))
+
+
+def critical(p: Params | None = None):
+    cp = (p or Params()).c()
+    Tc, rc, pc = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().lbm_critical(C.byref(cp), C.byref(Tc), C.byref(rc), C.byref(pc)))
+    return Tc.value, rc.value, pc.value
+
+
+def coexistence(Tr: float, p: Params | None = None):
+    """Maxwell-construction (rho_g, rho_l) at reduced temperature Tr."""
+    q = Params(**{**(p or Params()).__dict__, "Tr": Tr})
+    cp = q.c()
+    g, l = C.c_double(), C.c_double()
+    _check(lib().lbm_coexistence(C.byref(cp), C.byref(g), C.byref(l)))
+    return g.value, l.value
+
+
+class Simulation:
+    """One lattice on one GPU: a caller-owned torch workspace, a torch stream."""
+
+    def __init__(self, p: Params, rho0, device: str = "cuda:0", stream=None):
+        import torch
+        self.p = p
+        self.torch = torch
+        self.device = torch.device(device)
+        self._cp = p.c()
+        nbytes = workspace_bytes(p)
+        if nbytes == 0:
+            _check(LBM_EINVAL)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        if isinstance(rho0, torch.Tensor) and rho0.is_cuda:
+            r = rho0.to(torch.float64).contiguous()
+            self._rho0_keep = r
+            ptr, on_dev = C.c_void_p(r.data_ptr()), 1
+        else:
+            r = np.ascontiguousarray(rho0, dtype=np.float64).reshape(-1)
+            if r.size != p.n:
+                raise ValueError("rho0 has the wrong size")
+            self._rho0_keep = r
+            ptr, on_dev = r.ctypes.data_as(C.c_void_p), 0
+        code = lib().lbm_init(C.byref(self._cp), ptr, on_dev, C.c_void_p(self.ws.data_ptr()), nbytes,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        _check(code)
+        self.ctx = ctx
+
+    def step(self, n: int = 1) -> None:
+        _check(lib().lbm_step(self.ctx, int(n)), self.ctx)
+
+    @property
+    def steps_done(self) -> int:
+        return int(lib().lbm_steps_done(self.ctx))
+
+    def macros(self):
+        """(rho, vx, vy, vz) host arrays shaped like the grid (vz None in 2D)."""
+        p = self.p
+        out = [np.empty(p.n) for _ in range(4 if p.lattice == D3Q19 else 3)]
+        ptrs = [a.ctypes.data_as(C.c_void_p) for a in out] + ([None] if p.lattice == D2Q9 else [])
+        _check(lib().lbm_macros(self.ctx, *ptrs, 0), self.ctx)
+        res = [a.reshape(p.shape) for a in out]
+        return tuple(res) if p.lattice == D3Q19 else (res[0], res[1], res[2], None)
+
+    def macros_device(self):
+        """(rho, vx, vy[, vz]) as torch float64 tensors on the device."""
+        t = self.torch
+        k = 4 if self.p.lattice == D3Q19 else 3
+        out = [t.empty(self.p.n, dtype=t.float64, device=self.device) for _ in range(k)]
+        ptrs = [C.c_void_p(a.data_ptr()) for a in out] + ([None] if k == 3 else [])
+        _check(lib().lbm_macros(self.ctx, *ptrs, 1), self.ctx)
+        return [a.view(self.p.shape) for a in out]
+
+    def spurious_max(self, raise_on_nonfinite: bool = False):
+        """(U = max |v|, total mass, status code)."""
+        u, m = C.c_double(), C.c_double()
+        code = lib().lbm_spurious_max(self.ctx, C.byref(u), C.byref(m))
+        if code not in (LBM_OK, LBM_ENONFINITE) or (raise_on_nonfinite and code != LBM_OK):
+            _check(code, self.ctx)
+        return u.value, m.value, code
+
+    def populations(self) -> np.ndarray:
+        f = np.empty(self.p.q * self.p.n)
+        _check(lib().lbm_populations(self.ctx, f.ctypes.data_as(C.c_void_p), 0), self.ctx)
+        return f.reshape(self.p.q, -1)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            lib().lbm_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,82 @@
+"""CPU-side checks of the C ABI library: it loads, exports every symbol the
+header declares, validates parameters before touching the GPU, and its host
+EOS helpers agree with the oracle."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2205_09186_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.lib()
+    names = header_symbols()
+    assert "lbm_init" in names and "lbm_step" in names and "lbm_macros" in names and "lbm_spurious_max" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(lbm.SYMBOLS)
+
+
+def test_workspace_validation():
+    ok = lbm.Params(lattice=lbm.D3Q19, nx=16, ny=16, nz=16, scheme=lbm.CD6)
+    nb = lbm.workspace_bytes(ok)
+    assert nb >= 2 * 19 * 16 ** 3 * 8
+    bad = [dict(tau=0.5), dict(Tr=1.0), dict(Tr=0.0), dict(k=0.0), dict(kappa=-1.0), dict(scheme=9),
+           dict(nz=1), dict(nx=3), dict(lattice=2)]
+    for b in bad:
+        q = lbm.Params(**{**ok.__dict__, **b})
+        assert lbm.workspace_bytes(q) == 0, b
+    q2 = lbm.Params(lattice=lbm.D2Q9, nx=16, ny=16, nz=2)
+    assert lbm.workspace_bytes(q2) == 0
+    # compact schemes need the gradient fields as well
+    assert lbm.workspace_bytes(lbm.Params(**{**ok.__dict__, "scheme": lbm.OCFDS4})) > nb
+
+
+def test_init_rejects_bad_arguments_without_gpu():
+    L = lbm.lib()
+    p = lbm.Params(lattice=lbm.D2Q9, nx=8, ny=8).c()
+    ctx = C.c_void_p()
+    rc = L.lbm_init(C.byref(p), None, 0, None, 0, None, C.byref(ctx))
+    assert rc == lbm.LBM_EINVAL and ctx.value is None
+    assert "rho0" in L.lbm_last_error(None).decode()
+    bad = lbm.Params(lattice=lbm.D2Q9, nx=8, ny=8, tau=0.4).c()
+    rc = L.lbm_init(C.byref(bad), None, 0, None, 0, None, C.byref(ctx))
+    assert rc == lbm.LBM_EINVAL and "tau" in L.lbm_last_error(None).decode()
+    # workspace too small is reported before any device work
+    import numpy as np
+    rho = np.ones(64)
+    buf = (C.c_ubyte * 4096)()
+    addr = (C.addressof(buf) + 255) // 256 * 256
+    rc = L.lbm_init(C.byref(p), rho.ctypes.data_as(C.c_void_p), 0, C.c_void_p(addr), 1024, None, C.byref(ctx))
+    assert rc == lbm.LBM_ENOSPC
+    assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert L.lbm_last_error(None) is not None
+    L.lbm_free(None)
+
+
+def test_critical_point_matches_oracle(orc):
+    Tc, rc, pc = lbm.critical()
+    To, ro, po = orc.pr_critical()
+    assert Tc == pytest.approx(To, rel=1e-12)
+    assert rc == pytest.approx(ro, rel=1e-10)
+    assert pc == pytest.approx(po, rel=1e-12)
+
+
+@pytest.mark.parametrize("Tr", [0.95, 0.8, 0.7, 0.6, 0.4, 0.3, 0.2])
+def test_coexistence_matches_oracle(orc, Tr):
+    g, l = lbm.coexistence(Tr)
+    go, lo = orc.maxwell(Tr)
+    assert g == pytest.approx(go, rel=1e-11)
+    assert l == pytest.approx(lo, rel=1e-13)
+    with pytest.raises(lbm.LbmError):
+        lbm.coexistence(1.2)
