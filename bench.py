@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 chemical-potential multiphase LBM step.
+
+Workload (default): D3Q19 256^3 periodic FP64 droplet, R = 64 (0.25 L) centred,
+Tr = 0.7, CD6 (sixth-order explicit central differences), k = 0.1,
+kappa-hat = 0.004, tau = 1, tanh width 10 between the Maxwell densities plus
+seeded noise +-1e-6.  One step = one pass of the whole hot path over the grid
+(moments, chemical potential, stencils, force, EDM-BGK collision, streaming).
+Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line with MLUPS (whole-job throughput), the roofline of the
+dominant kernel (algorithmic bytes (2Q+2)*8 per node over its measured
+duration, against the 8 TB/s HBM3E peak) and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--lattice", default="D3Q19", choices=["D2Q9", "D3Q19"])
+    ap.add_argument("--n", type=int, default=256, help="grid side")
+    ap.add_argument("--scheme", default="CD6")
+    ap.add_argument("--Tr", type=float, default=0.7)
+    ap.add_argument("--k", type=float, default=0.1)
+    ap.add_argument("--kappa", type=float, default=0.004)
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2205_09186_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources and this workload; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    ent = rec.get(workload)
+    if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("kernel") != kernel:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(args, p, rho0):
+    import oracle
+    oracle.build(force=False)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    oracle.set_threads(nthreads)
+    op = oracle.Params(lattice=p.lattice, nx=p.nx, ny=p.ny, nz=p.nz, tau=p.tau, Tr=p.Tr, k=p.k,
+                       kappa=p.kappa, scheme=p.scheme)
+    sim = oracle.Sim(op, rho0)
+    sim.step(1)  # warm-up
+    t0 = time.perf_counter()
+    sim.step(args.cpu_steps)
+    dt = time.perf_counter() - t0
+    del sim
+    return {"value": round(p.n * args.cpu_steps / dt / 1e6, 4), "unit": "MLUPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"same {p.nx}x{p.ny}x{p.nz} grid and inputs, {args.cpu_steps} steps after 1 warm-up, "
+                      f"{dt:.2f} s of CPU time, OpenMP over nodes"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU runs are not part "
+                                   "of it)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2205_09186_amd import inputs, lbm
+
+    lat = lbm.D3Q19 if args.lattice == "D3Q19" else lbm.D2Q9
+    n = args.n
+    shape = (n, n, n) if lat == lbm.D3Q19 else (n, n)
+    p = lbm.Params(lattice=lat, nx=n, ny=n, nz=(n if lat == lbm.D3Q19 else 1), tau=1.0, Tr=args.Tr, k=args.k,
+                   kappa=args.kappa, scheme=lbm.SCHEMES[args.scheme])
+    rho_g, rho_l = lbm.coexistence(args.Tr)
+    rho0 = inputs.droplet(shape, 0.25 * n, 10.0, rho_g, rho_l)
+    stream = torch.cuda.current_stream()
+    sim = lbm.Simulation(p, torch.from_numpy(rho0.reshape(-1)).cuda())
+    # tile-shape tuner: times every launch variant of the step kernel on this
+    # grid and keeps the fastest (counts as warm-up)
+    tuned = sim.tune(steps=3) if sim.num_variants > 1 else {0: None}
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    mlups = p.n * args.steps / (ms_total * 1e-3) / 1e6
+    U, M, code = sim.spurious_max()
+
+    # per-phase durations from HIP events on the same stream (one kernel per
+    # phase on the fused path); the dominant kernel carries the roofline
+    phases = sim.step_timed(max(5, min(args.steps, 20)))
+    kname, kernel_ms = max(phases, key=lambda t: t[1])
+    Q = p.q
+    bytes_node = (2 * Q + 2) * 8
+    achieved = bytes_node * p.n / (kernel_ms * 1e-3) / 1e9
+    step_gbs = bytes_node * p.n / (ms_step * 1e-3) / 1e9
+    workload = f"{args.lattice} {n}^{len(shape)} droplet R={0.25 * n:g} Tr={args.Tr} {args.scheme} k={args.k}"
+    traffic = traffic_record(kname, workload)
+    out = {
+        "metric": "MLUPS D3Q19 FP64 (% HBM roofline)" if lat == lbm.D3Q19 else "MLUPS D2Q9 FP64",
+        "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": workload, "lattice": args.lattice, "grid": list(shape), "scheme": args.scheme,
+                   "Tr": args.Tr, "k": args.k, "kappa": args.kappa, "tau": 1.0, "nodes": p.n},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": kname, "kernel_ms": round(kernel_ms, 4),
+                     "algorithmic_bytes_per_node": bytes_node, "nodes_per_launch": p.n,
+                     "step_achieved": round(step_gbs, 1), "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                     "phases_ms": {k: round(v, 4) for k, v in phases}},
+        "tuner_ms_per_variant": {str(k): (round(v, 4) if v is not None else None) for k, v in tuned.items()},
+        "spurious_current": U, "mass": M, "status": code,
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args, p, rho0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,6 +109,21 @@ int lbm_populations(lbm_ctx* c, double* f, int out_on_device);
 /* Number of completed steps of the context. */
 long lbm_steps_done(const lbm_ctx* c);
 
+/* Profiling: run nsteps >= 1 steps with a HIP event on the context's stream at
+ * every phase boundary of the step (a phase is one kernel on the fused path).
+ * ms[k] (k < cap) receives the mean duration of phase k per step and
+ * *nphases the number of phases.  Synchronises after every step. */
+int lbm_step_timed(lbm_ctx* c, long nsteps, double* ms, int cap, int* nphases);
+
+/* Launch variants (tile shape / register budget) of the context's step
+ * kernel; lbm_set_variant selects one (0 = default).  Every variant computes
+ * the same step; a tuner times them and keeps the fastest. */
+int lbm_num_variants(const lbm_ctx* c);
+int lbm_set_variant(lbm_ctx* c, int v);
+
+/* Name of phase k of the last timed step ("" if none). */
+const char* lbm_phase_name(const lbm_ctx* c, int k);
+
 /* Release the context (never the caller's workspace).  NULL is allowed. */
 void lbm_free(lbm_ctx* c);
 

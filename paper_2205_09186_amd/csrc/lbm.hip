@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -25,7 +26,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t S0, S1, rho, mu, grho, gmu, lap, wtmp, partial, result, total;
+    size_t S0, S1, rho0, rho1, mu, grho, gmu, lap, wtmp, partial, result, total;
     long long nparts;
 };
 
@@ -67,7 +68,8 @@ Layout layout_of(const lbm_params* p)
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.S0 = take(sizeof(double) * Q * N);
     L.S1 = take(sizeof(double) * Q * N);
-    L.rho = take(sizeof(double) * N);
+    L.rho0 = take(sizeof(double) * N);
+    L.rho1 = take(sizeof(double) * N);
     L.mu = take(sizeof(double) * N);
     if (compact) {
         L.grho = take(sizeof(double) * dim * N);
@@ -93,13 +95,20 @@ struct lbm_ctx {
     hipStream_t stream;
     char* ws;
     Layout L;
-    double *S[2], *rho, *mu, *grho, *gmu, *lap, *wtmp, *partial, *result;
-    int cur;        // index of the buffer holding the current state
+    double *S[2], *rhob[2], *mu, *grho, *gmu, *lap, *wtmp, *partial, *result;
+    int cur;        // index of the buffers holding the current state (S and rho)
     long steps;
     std::string err;
     // compact-scheme line geometry per axis
     LineGeom lines[3];
     double z, zscale;
+    bool fused;     // explicit schemes: fused collide + next-density kernel
+    int variant = 0;  // launch variant of the fused kernel
+    // phase timing (lbm_step_timed)
+    bool timing = false;
+    int nmarks = 0;
+    hipEvent_t ev[16] = {};
+    const char* phase[16] = {};
 };
 
 namespace {
@@ -118,6 +127,15 @@ int hip_check(lbm_ctx* c, hipError_t e, const char* what)
 }
 
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Phase boundary for lbm_step_timed: an event on the context's stream.
+void mark(lbm_ctx* c, const char* name)
+{
+    if (!c->timing || c->nmarks >= 16) return;
+    (void)hipEventRecord(c->ev[c->nmarks], c->stream);
+    c->phase[c->nmarks] = name;
+    c->nmarks++;
+}
 
 template <int LAT>
 void launch_init(lbm_ctx* c, const double* rho0)
@@ -145,33 +163,46 @@ void launch_fields(lbm_ctx* c)
 {
     constexpr int DIM = Lat<LAT>::DIM;
     const double* S = c->S[c->cur];
-    hipLaunchKernelGGL(k_rho<LAT>, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream, S, c->rho, c->g);
+    double* rho = c->rhob[c->cur];
+    hipLaunchKernelGGL(k_rho<LAT>, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream, S, rho, c->g);
     if constexpr (is_compact(SCH)) {
-        for (int d = 0; d < DIM; ++d) compact_deriv(c, c->rho, c->grho + d * c->g.N, d, false);
+        for (int d = 0; d < DIM; ++d) compact_deriv(c, rho, c->grho + d * c->g.N, d, false);
         for (int d = 0; d < DIM; ++d) compact_deriv(c, c->grho + d * c->g.N, c->lap, d, d > 0);
         hipLaunchKernelGGL(k_mu_lap, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
-                           c->rho, c->lap, c->mu, c->g.N, c->eos);
+                           rho, c->lap, c->mu, c->g.N, c->eos);
         for (int d = 0; d < DIM; ++d) compact_deriv(c, c->mu, c->gmu + d * c->g.N, d, false);
     } else {
         hipLaunchKernelGGL((k_mu<DIM, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
-                           c->rho, c->mu, c->g, c->eos);
+                           rho, c->mu, c->g, c->eos);
     }
 }
 
 template <int LAT, int SCH>
 void launch_step(lbm_ctx* c)
 {
-    if constexpr (!is_compact(SCH)) {
-        if (fused_available<LAT, SCH>(c->g)) {
-            launch_fused_step<LAT, SCH>(c->S[c->cur], c->S[1 - c->cur], c->rho, c->mu, c->g, c->eos,
-                                        c->one_m_omega, c->stream);
+    if constexpr (SCH == CD2 || SCH == CD4 || SCH == CD6) {
+        if (c->fused) {
+            // rho of the current state is already in rhob[cur] (written by the
+            // previous fused step or at initialisation)
+            constexpr int DIM = Lat<LAT>::DIM;
+            mark(c, "k_mu");
+            hipLaunchKernelGGL((k_mu<DIM, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                               c->rhob[c->cur], c->mu, c->g, c->eos);
+            mark(c, "k_fused");
+            launch_fused_collide<LAT, SCH>(c->variant, c->S[c->cur], c->S[1 - c->cur], c->rhob[c->cur], c->mu,
+                                           c->rhob[1 - c->cur], c->g, c->one_m_omega, c->stream);
+            mark(c, nullptr);
             c->cur = 1 - c->cur;
             return;
         }
     }
+    mark(c, is_compact(SCH) ? "rho+compact derivatives+mu" : "k_rho+k_mu");
     launch_fields<LAT, SCH>(c);
+    mark(c, "k_collide");
     hipLaunchKernelGGL((k_collide<LAT, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
-                       c->S[c->cur], c->S[1 - c->cur], c->rho, c->mu, c->grho, c->gmu, c->g, c->one_m_omega);
+                       c->S[c->cur], c->S[1 - c->cur], c->rhob[c->cur], c->mu, c->grho, c->gmu, c->g,
+                       c->one_m_omega);
+    mark(c, nullptr);
     c->cur = 1 - c->cur;
 }
 
@@ -180,7 +211,8 @@ void launch_macros(lbm_ctx* c, double* orho, double* ovx, double* ovy, double* o
 {
     launch_fields<LAT, SCH>(c);
     hipLaunchKernelGGL((k_macros<LAT, SCH>), dim3((unsigned)c->L.nparts), dim3(256), 0, c->stream,
-                       c->S[c->cur], c->rho, c->mu, c->grho, c->gmu, c->g, orho, ovx, ovy, ovz, c->partial);
+                       c->S[c->cur], c->rhob[c->cur], c->mu, c->grho, c->gmu, c->g, orho, ovx, ovy, ovz,
+                       c->partial);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->stream, c->partial, c->L.nparts, c->result);
 }
 
@@ -270,7 +302,8 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->L = L;
     c->S[0] = reinterpret_cast<double*>(c->ws + L.S0);
     c->S[1] = reinterpret_cast<double*>(c->ws + L.S1);
-    c->rho = reinterpret_cast<double*>(c->ws + L.rho);
+    c->rhob[0] = reinterpret_cast<double*>(c->ws + L.rho0);
+    c->rhob[1] = reinterpret_cast<double*>(c->ws + L.rho1);
     c->mu = reinterpret_cast<double*>(c->ws + L.mu);
     const bool compact = p->scheme >= LBM_OCFDS4;
     c->grho = compact ? reinterpret_cast<double*>(c->ws + L.grho) : nullptr;
@@ -282,6 +315,7 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->cur = 0;
     c->steps = 0;
     c->one_m_omega = 1.0 - 1.0 / p->tau;
+    c->fused = p->scheme <= LBM_CD6 && c->g.N < (1LL << 31) && std::getenv("LBM_NO_FUSED") == nullptr;
     set_lines(c);
 
     // equation of state in mesh units (Eq 16): k^2 psi'
@@ -307,14 +341,21 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
             if (!(r > 0.0 && r < rho_max)) { rc_ = fail(c, LBM_EINVAL, "rho0 must be finite and in (0, 1/b)"); break; }
         }
         if (rc_ == LBM_OK)
-            rc_ = hip_check(c, hipMemcpyAsync(c->rho, rho0, sizeof(double) * N, hipMemcpyHostToDevice, c->stream),
-                            "copy rho0");
+            rc_ = hip_check(c, hipMemcpyAsync(c->rhob[1], rho0, sizeof(double) * N, hipMemcpyHostToDevice,
+                                              c->stream), "copy rho0");
     } else {
-        rc_ = hip_check(c, hipMemcpyAsync(c->rho, rho0, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream),
-                        "copy rho0");
+        rc_ = hip_check(c, hipMemcpyAsync(c->rhob[1], rho0, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                                          c->stream), "copy rho0");
     }
     if (rc_ == LBM_OK) {
-        if (p->lattice == LBM_D2Q9) launch_init<0>(c, c->rho); else launch_init<1>(c, c->rho);
+        // populations from rho0, then rho of that state (what the step reads)
+        if (p->lattice == LBM_D2Q9) {
+            launch_init<0>(c, c->rhob[1]);
+            hipLaunchKernelGGL(k_rho<0>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, c->S[0], c->rhob[0], c->g);
+        } else {
+            launch_init<1>(c, c->rhob[1]);
+            hipLaunchKernelGGL(k_rho<1>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, c->S[0], c->rhob[0], c->g);
+        }
         rc_ = hip_check(c, hipGetLastError(), "init launch");
     }
     if (rc_ == LBM_OK) rc_ = hip_check(c, hipStreamSynchronize(c->stream), "init sync");
@@ -415,7 +456,62 @@ int lbm_populations(lbm_ctx* c, double* f, int out_on_device)
 
 long lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
 
-void lbm_free(lbm_ctx* c) { delete c; }
+int lbm_step_timed(lbm_ctx* c, long nsteps, double* ms, int cap, int* nphases)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (nsteps < 1 || !ms || cap < 1 || !nphases) return fail(c, LBM_EINVAL, "bad timing arguments");
+    for (int k = 0; k < 16; ++k)
+        if (!c->ev[k]) {
+            int r = hip_check(c, hipEventCreate(&c->ev[k]), "event create");
+            if (r) return r;
+        }
+    for (int k = 0; k < cap; ++k) ms[k] = 0.0;
+    int np = 0;
+    c->timing = true;
+    for (long s = 0; s < nsteps; ++s) {
+        c->nmarks = 0;
+        dispatch<StepOp>(c->p.lattice, c->p.scheme, c);
+        c->steps++;
+        int r = hip_check(c, hipEventSynchronize(c->ev[c->nmarks - 1]), "timing sync");
+        if (r) { c->timing = false; return r; }
+        np = c->nmarks - 1;
+        for (int k = 0; k < np && k < cap; ++k) {
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]);
+            ms[k] += t / (double)nsteps;
+        }
+    }
+    c->timing = false;
+    *nphases = np;
+    return hip_check(c, hipGetLastError(), "timed step");
+}
+
+int lbm_num_variants(const lbm_ctx* c)
+{
+    return (c && c->fused) ? kNumFusedVariants : 1;
+}
+
+int lbm_set_variant(lbm_ctx* c, int v)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (v < 0 || v >= lbm_num_variants(c)) return fail(c, LBM_EINVAL, "variant out of range");
+    c->variant = v;
+    return LBM_OK;
+}
+
+const char* lbm_phase_name(const lbm_ctx* c, int k)
+{
+    if (!c || k < 0 || k >= 15 || !c->phase[k]) return "";
+    return c->phase[k];
+}
+
+void lbm_free(lbm_ctx* c)
+{
+    if (!c) return;
+    for (int k = 0; k < 16; ++k)
+        if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    delete c;
+}
 
 const char* lbm_last_error(const lbm_ctx* c)
 {

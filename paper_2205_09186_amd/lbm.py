@@ -48,6 +48,10 @@ SYMBOLS = {
     "lbm_spurious_max": (C.c_int, [C.c_void_p, _D, _D]),
     "lbm_populations": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "lbm_steps_done": (C.c_long, [C.c_void_p]),
+    "lbm_step_timed": (C.c_int, [C.c_void_p, C.c_long, _D, C.c_int, C.POINTER(C.c_int)]),
+    "lbm_phase_name": (C.c_char_p, [C.c_void_p, C.c_int]),
+    "lbm_num_variants": (C.c_int, [C.c_void_p]),
+    "lbm_set_variant": (C.c_int, [C.c_void_p, C.c_int]),
     "lbm_free": (None, [C.c_void_p]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_critical": (C.c_int, [_P, _D, _D, _D]),
@@ -166,6 +170,33 @@ class Simulation:
 
     def step(self, n: int = 1) -> None:
         _check(lib().lbm_step(self.ctx, int(n)), self.ctx)
+
+    def step_timed(self, n: int):
+        """Run n steps timing each phase with HIP events: [(name, mean ms per step)]."""
+        ms = (C.c_double * 16)()
+        npk = C.c_int()
+        _check(lib().lbm_step_timed(self.ctx, int(n), ms, 16, C.byref(npk)), self.ctx)
+        return [(lib().lbm_phase_name(self.ctx, k).decode(), ms[k]) for k in range(npk.value)]
+
+    @property
+    def num_variants(self) -> int:
+        return int(lib().lbm_num_variants(self.ctx))
+
+    def set_variant(self, v: int) -> None:
+        _check(lib().lbm_set_variant(self.ctx, int(v)), self.ctx)
+
+    def tune(self, steps: int = 5):
+        """Time every launch variant of the step kernel on this grid (the state
+        advances by steps * variants steps) and keep the fastest.  Returns
+        {variant: ms per step}."""
+        res = {}
+        for v in range(self.num_variants):
+            self.set_variant(v)
+            self.step_timed(1)
+            res[v] = sum(t for _, t in self.step_timed(steps))
+        best = min(res, key=res.get)
+        self.set_variant(best)
+        return res
 
     @property
     def steps_done(self) -> int:

@@ -142,3 +142,55 @@ def test_deterministic_repeat(L, orc):
     b = L.Simulation(p, rho0); b.step(10)
     assert np.array_equal(a.populations(), b.populations())
     assert a.spurious_max()[:2] == b.spurious_max()[:2]
+
+
+@pytest.mark.parametrize("lat,shape,scheme", [(0, (70, 130), "CD6"), (0, (45, 64), "CD4"), (0, (8, 200), "CD2"),
+                                              (1, (33, 20, 70), "CD6"), (1, (10, 13, 9), "CD4"),
+                                              (1, (40, 8, 66), "CD2"), (1, (70, 4, 5), "CD6")])
+def test_fused_equals_unfused(L, orc, lat, shape, scheme, monkeypatch):
+    """The fused collide kernel (tile + recomputed ring, LDS exchange for the
+    next density) against the plain node-parallel kernels: same state to
+    rounding, on grids with ragged tiles in every direction."""
+    g, l = orc.maxwell(0.9)
+    rho0 = inputs.droplet(shape, min(shape) / 4, 4.0, g, l)
+    nz, ny, nx = ((1,) + shape) if lat == 0 else shape
+    p = L.Params(lattice=lat, nx=nx, ny=ny, nz=nz, Tr=0.9, scheme=L.SCHEMES[scheme])
+    a = L.Simulation(p, rho0)
+    monkeypatch.setenv("LBM_NO_FUSED", "1")
+    b = L.Simulation(p, rho0)
+    monkeypatch.delenv("LBM_NO_FUSED")
+    a.step(20); b.step(20)
+    assert np.abs(a.populations() - b.populations()).max() < 1e-13
+    assert np.abs(a.macros()[0] - b.macros()[0]).max() < 1e-13
+
+
+def test_step_timed_phases(L, orc):
+    g, l = orc.maxwell(0.8)
+    rho0 = inputs.droplet((24, 24, 24), 6, 4.0, g, l)
+    p = L.Params(lattice=1, nx=24, ny=24, nz=24, Tr=0.8, scheme=L.CD4)
+    s = L.Simulation(p, rho0)
+    ph = s.step_timed(3)
+    assert [n for n, _ in ph] == ["k_mu", "k_fused"]
+    assert all(t > 0 for _, t in ph)
+    assert s.steps_done == 3
+
+
+@pytest.mark.parametrize("lat,shape", [(1, (37, 21, 70)), (0, (50, 131))])
+def test_launch_variants_identical(L, orc, lat, shape):
+    """Every launch variant of the fused step (tile height, register budget)
+    computes the same node arithmetic in the same order: bitwise equal."""
+    g, l = orc.maxwell(0.8)
+    rho0 = inputs.droplet(shape, min(shape) / 4, 4.0, g, l)
+    nz, ny, nx = ((1,) + shape) if lat == 0 else shape
+    p = L.Params(lattice=lat, nx=nx, ny=ny, nz=nz, Tr=0.8, scheme=L.CD6)
+    ref = None
+    for v in range(L.Simulation(p, rho0).num_variants):
+        s = L.Simulation(p, rho0)
+        s.set_variant(v)
+        s.step(7)
+        f = s.populations()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), v
+    assert ref is not None
