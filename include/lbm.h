@@ -139,6 +139,44 @@ int lbm_critical(const lbm_params* p, double* Tc, double* rho_c, double* p_c);
  * (Sec 3.4), host computation.  LBM_EINVAL outside 0 < Tr < 1. */
 int lbm_coexistence(const lbm_params* p, double* rho_g, double* rho_l);
 
+/* ------------------------------------------------------------------------
+ * Batched sweep: many uneven D2Q9 instances (droplets, flat slabs; any
+ * temperature, radius and scheme) stepped together by one cooperative
+ * persistent kernel per chunk of steps.  Each instance runs exactly the step
+ * above; every check_every steps its spurious current U is compared with the
+ * previous check and the instance retires as CONVERGED (|dU| < tol) or
+ * DIVERGED (non-finite state or U above the sound speed).
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+enum { LBM_RUNNING = 0, LBM_CONVERGED = 1, LBM_DIVERGED = 2 };
+
+/* Device bytes for the n instances ps[0..n-1] (0 if any is invalid). */
+size_t lbm_batch_workspace_bytes(const lbm_params* ps, int n);
+
+/* Create the batch on a caller-owned device workspace.  rho0s[i] is a host
+ * array of instance i's initial density.  Synchronises. */
+int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n,
+                   void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_batch** out);
+
+/* Workgroups of the cooperative launch (1..lbm_batch_max_grid; default the
+ * maximum that can be resident); a tuner picks the fastest. */
+int lbm_batch_set_grid(lbm_batch* b, int workgroups);
+int lbm_batch_max_grid(const lbm_batch* b);
+
+/* Advance running instances by up to nsteps steps, in launches of at most
+ * `chunk` steps; stops early once every instance has retired.  Host outputs
+ * (n entries each, any may be NULL): status (LBM_RUNNING/CONVERGED/DIVERGED),
+ * completed steps, and U at the last check.  Synchronises. */
+int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long chunk,
+                  int* status, long* steps, double* umax);
+
+/* Context view of instance i (owned by the batch; valid until lbm_batch_free)
+ * for lbm_macros, lbm_spurious_max and lbm_populations. */
+lbm_ctx* lbm_batch_instance(lbm_batch* b, int i);
+
+const char* lbm_batch_last_error(const lbm_batch* b);
+void lbm_batch_free(lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

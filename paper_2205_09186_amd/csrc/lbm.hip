@@ -9,8 +9,10 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lbm.h"
+#include "lbm_batch.hpp"
 #include "lbm_eos_host.hpp"
 #include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
@@ -532,6 +534,237 @@ int lbm_coexistence(const lbm_params* p, double* rho_g, double* rho_l)
     if (!pr_coexistence(eos_constants(p), p->Tr, *rho_g, *rho_l))
         return fail(nullptr, LBM_EINVAL, "no coexistence at this Tr");
     return LBM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched sweep
+// ---------------------------------------------------------------------------
+struct lbm_batch {
+    int n = 0;
+    std::vector<lbm_ctx*> ctx;
+    std::vector<BInst> inst;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    BInst* d_inst = nullptr;
+    BState* d_st = nullptr;
+    int* d_blk_inst = nullptr;
+    int* d_line_inst[2] = { nullptr, nullptr };
+    double* d_partial = nullptr;
+    int nblk_total = 0, nline_total[2] = { 0, 0 };
+    int has_compact = 0;
+    int grid = 0;          // workgroups of the cooperative launch (0: all resident)
+    int max_grid = 0;
+    std::string err;
+};
+
+namespace {
+
+struct BatchLayout {
+    std::vector<size_t> inst_off;
+    size_t tables, total;
+    int nblk, nline[2];
+};
+
+bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
+{
+    size_t off = 0;
+    B.inst_off.resize(n);
+    B.nblk = 0; B.nline[0] = B.nline[1] = 0;
+    for (int i = 0; i < n; ++i) {
+        if (const char* w = validate(&ps[i])) { *why = w; return false; }
+        if (ps[i].lattice != LBM_D2Q9) { *why = "the batched sweep runs D2Q9 instances"; return false; }
+        B.inst_off[i] = off;
+        off = align_up(off + layout_of(&ps[i]).total);
+        const long long N = (long long)ps[i].nx * ps[i].ny;
+        B.nblk += (int)((N + BNODES - 1) / BNODES);
+        B.nline[0] += ps[i].ny * ((ps[i].nx + 63) / 64);
+        B.nline[1] += ps[i].nx * ((ps[i].ny + 63) / 64);
+    }
+    B.tables = off;
+    off = align_up(off + sizeof(BInst) * n);
+    off = align_up(off + sizeof(BState) * n);
+    off = align_up(off + sizeof(int) * B.nblk);
+    off = align_up(off + sizeof(int) * B.nline[0]);
+    off = align_up(off + sizeof(int) * B.nline[1]);
+    off = align_up(off + sizeof(double) * B.nblk);
+    B.total = off;
+    return true;
+}
+
+int bfail(lbm_batch* b, int code, const std::string& msg)
+{
+    if (b) b->err = msg;
+    g_thread_error = msg;
+    return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(const lbm_params* ps, int n)
+{
+    if (!ps || n < 1) return 0;
+    BatchLayout B;
+    const char* why = nullptr;
+    if (!batch_layout(ps, n, B, &why)) return 0;
+    return B.total;
+}
+
+int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void* d_workspace, size_t ws_bytes,
+                   void* hip_stream, lbm_batch** out)
+{
+    if (!out) return bfail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ps || !rho0s || n < 1) return bfail(nullptr, LBM_EINVAL, "bad batch arguments");
+    BatchLayout B;
+    const char* why = nullptr;
+    if (!batch_layout(ps, n, B, &why)) return bfail(nullptr, LBM_EINVAL, why);
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+        return bfail(nullptr, LBM_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < B.total) return bfail(nullptr, LBM_ENOSPC, "batch workspace too small");
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return bfail(nullptr, LBM_EHIP, "out of host memory");
+    b->n = n;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->ws = static_cast<char*>(d_workspace);
+    b->ctx.assign(n, nullptr);
+    b->inst.resize(n);
+    std::vector<int> blk_inst, line_inst[2];
+    int rc = LBM_OK;
+    for (int i = 0; i < n && rc == LBM_OK; ++i) {
+        lbm_ctx* c = nullptr;
+        const size_t sz = layout_of(&ps[i]).total;
+        rc = lbm_init(&ps[i], rho0s[i], 0, b->ws + B.inst_off[i], sz, hip_stream, &c);
+        if (rc != LBM_OK) { b->err = "instance " + std::to_string(i) + ": " + g_thread_error; break; }
+        c->fused = false;
+        b->ctx[i] = c;
+        BInst& I = b->inst[i];
+        I.g = c->g;
+        I.scheme = ps[i].scheme;
+        I.one_m_omega = c->one_m_omega;
+        I.eos = c->eos;
+        I.S[0] = c->S[0]; I.S[1] = c->S[1];
+        I.rho = c->rhob[0]; I.mu = c->mu;
+        I.grho = c->grho; I.gmu = c->gmu; I.lap = c->lap; I.wtmp = c->wtmp;
+        I.lines[0] = c->lines[0]; I.lines[1] = c->lines[1];
+        I.cc = compact_scheme(ps[i].scheme);
+        I.z = c->z; I.zscale = c->zscale;
+        I.blk0 = (int)blk_inst.size();
+        I.nblk = (int)((c->g.N + BNODES - 1) / BNODES);
+        for (int k = 0; k < I.nblk; ++k) blk_inst.push_back(i);
+        I.part0 = I.blk0;
+        for (int d = 0; d < 2; ++d) {
+            I.line0[d] = (int)line_inst[d].size();
+            I.nline[d] = c->lines[d].n1 * c->lines[d].n2 * c->lines[d].nch;
+            for (int k = 0; k < I.nline[d]; ++k) line_inst[d].push_back(i);
+        }
+        if (ps[i].scheme >= LBM_OCFDS4) b->has_compact = 1;
+    }
+    if (rc != LBM_OK) { std::string e = b->err; lbm_batch_free(b); return bfail(nullptr, rc, e); }
+    size_t off = B.tables;
+    b->d_inst = reinterpret_cast<BInst*>(b->ws + off); off = align_up(off + sizeof(BInst) * n);
+    b->d_st = reinterpret_cast<BState*>(b->ws + off); off = align_up(off + sizeof(BState) * n);
+    b->d_blk_inst = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nblk);
+    b->d_line_inst[0] = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nline[0]);
+    b->d_line_inst[1] = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nline[1]);
+    b->d_partial = reinterpret_cast<double*>(b->ws + off);
+    b->nblk_total = (int)blk_inst.size();
+    b->nline_total[0] = (int)line_inst[0].size();
+    b->nline_total[1] = (int)line_inst[1].size();
+    std::vector<BState> st(n);
+    for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.U = 0.0; x.U_prev = 0.0; }
+    hipError_t e = hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_st, st.data(), sizeof(BState) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_blk_inst, blk_inst.data(), sizeof(int) * blk_inst.size(),
+                                            hipMemcpyHostToDevice, b->stream);
+    for (int d = 0; d < 2 && e == hipSuccess; ++d)
+        e = hipMemcpyAsync(b->d_line_inst[d], line_inst[d].data(), sizeof(int) * line_inst[d].size(),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BNODES, 0);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        std::string m = std::string("batch setup: ") + hipGetErrorString(e);
+        lbm_batch_free(b);
+        return bfail(nullptr, LBM_EHIP, m);
+    }
+    b->max_grid = std::max(1, per_cu * ncu);
+    b->grid = b->max_grid;
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_set_grid(lbm_batch* b, int workgroups)
+{
+    if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
+    if (workgroups < 1 || workgroups > b->max_grid) return bfail(b, LBM_EINVAL, "workgroups out of range");
+    b->grid = workgroups;
+    return LBM_OK;
+}
+
+int lbm_batch_max_grid(const lbm_batch* b) { return b ? b->max_grid : 0; }
+
+int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long chunk, int* status, long* steps,
+                  double* umax)
+{
+    if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
+    if (nsteps < 0 || check_every < 1 || chunk < 1 || !(tol >= 0.0)) return bfail(b, LBM_EINVAL, "bad run arguments");
+    std::vector<BState> st(b->n);
+    long done = 0;
+    while (done < nsteps) {
+        const long todo = std::min(chunk, nsteps - done);
+        BatchArgs a;
+        a.inst = b->d_inst; a.st = b->d_st; a.ninst = b->n;
+        a.nblk_total = b->nblk_total;
+        a.nline_total[0] = b->nline_total[0]; a.nline_total[1] = b->nline_total[1];
+        a.blk_inst = b->d_blk_inst;
+        a.line_inst[0] = b->d_line_inst[0]; a.line_inst[1] = b->d_line_inst[1];
+        a.partial = b->d_partial;
+        a.has_compact = b->has_compact;
+        a.nsteps = (int)todo;
+        a.check_every = (int)check_every;
+        a.tol = tol;
+        void* args[] = { &a };
+        hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_batch), dim3(b->grid),
+                                                  dim3(BNODES), args, 0, b->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(st.data(), b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost,
+                                                b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+        done += todo;
+        bool running = false;
+        for (const auto& x : st) running |= x.status == B_RUNNING;
+        if (!running) break;
+    }
+    for (int i = 0; i < b->n; ++i) {
+        lbm_ctx* c = b->ctx[i];
+        c->steps = (long)st[i].steps;
+        c->cur = (int)(st[i].steps & 1);
+        if (status) status[i] = st[i].status;
+        if (steps) steps[i] = (long)st[i].steps;
+        if (umax) umax[i] = st[i].U;
+    }
+    return LBM_OK;
+}
+
+lbm_ctx* lbm_batch_instance(lbm_batch* b, int i)
+{
+    if (!b || i < 0 || i >= b->n) return nullptr;
+    return b->ctx[i];
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : g_thread_error.c_str(); }
+
+void lbm_batch_free(lbm_batch* b)
+{
+    if (!b) return;
+    for (auto* c : b->ctx) lbm_free(c);
+    delete b;
 }
 
 }  // extern "C"

@@ -1,0 +1,294 @@
+// lbm_batch.hpp -- batched sweep: many uneven D2Q9 instances (droplets and flat
+// slabs at different temperatures, radii and schemes) advanced by one
+// cooperative persistent kernel.
+//
+// Every instance keeps its own populations, density and chemical potential in
+// one pool.  A step is a fixed sequence of phases (density, chemical potential
+// or the compact derivative line solves, collision); within a phase the
+// workgroups stride over the work items of all running instances, and a
+// grid-wide barrier separates the phases.  The cooperative launch guarantees
+// that every workgroup is resident, every workgroup executes the same phase
+// sequence, and every loop is bounded, so the barriers always complete.
+// Every check_every steps the spurious current U = max |v| of each instance is
+// reduced (fixed order) and compared with the previous check: an instance
+// whose U changed by less than tol is CONVERGED, one with a non-finite state
+// or U above the sound speed is DIVERGED; both stop stepping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+enum BatchStatus { B_RUNNING = 0, B_CONVERGED = 1, B_DIVERGED = 2 };
+
+struct BInst {
+    Grid g;
+    int scheme;
+    double one_m_omega;
+    Eos eos;
+    double *S[2], *rho, *mu, *grho, *gmu, *lap, *wtmp;
+    LineGeom lines[2];
+    Compact cc;
+    double z, zscale;
+    int blk0, nblk;         // node-block items [blk0, blk0 + nblk)
+    int line0[2], nline[2]; // line-chunk items per axis
+    int part0;              // first partial slot of its node blocks
+};
+
+struct BState {             // per instance, updated by the kernel
+    int status;
+    long long steps;
+    double U, U_prev;
+};
+
+constexpr int BNODES = 256;   // nodes per node-block item (one per thread)
+
+// ---------------------------------------------------------------------------
+// per-node bodies with runtime scheme dispatch
+// ---------------------------------------------------------------------------
+template <int SCH>
+__device__ void b_mu_node(const BInst& I, long long n, int x, int y)
+{
+    constexpr int R = radius(SCH);
+    Nbr<R, 2> nb(x, y, 0, I.g);
+    I.mu[n] = mu_bulk(I.rho[n], I.eos) - I.eos.kappa * lap_at<2, SCH, R>(I.rho, nb);
+}
+
+template <int SCH>
+__device__ void b_force(const BInst& I, long long n, int x, int y, double r, double& Fx, double& Fy, double& Fz)
+{
+    force_at<0, SCH>(I.rho, I.mu, I.grho, I.gmu, I.g, n, x, y, 0, r, Fx, Fy, Fz);
+}
+
+__device__ void b_force_any(const BInst& I, long long n, int x, int y, double r, double& Fx, double& Fy, double& Fz)
+{
+    switch (I.scheme) {
+    case CD2: b_force<CD2>(I, n, x, y, r, Fx, Fy, Fz); break;
+    case CD4: b_force<CD4>(I, n, x, y, r, Fx, Fy, Fz); break;
+    case CD6: b_force<CD6>(I, n, x, y, r, Fx, Fy, Fz); break;
+    case E4: b_force<E4>(I, n, x, y, r, Fx, Fy, Fz); break;
+    case E8: b_force<E8>(I, n, x, y, r, Fx, Fy, Fz); break;
+    default: b_force<OCFDS4>(I, n, x, y, r, Fx, Fy, Fz); break;   // gradient fields
+    }
+}
+
+__device__ void b_moments(const BInst& I, const double* S, long long n, int x, int y, double (&f)[9], double& r,
+                          double& jx, double& jy)
+{
+    using L = Lat<0>;
+    (void)n;
+    Nbr<1, 2> nb(x, y, 0, I.g);
+    r = jx = jy = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        f[i] = S[(long long)i * I.g.N + nb.at(-L::ex(i), -L::ey(i), 0)];
+        r += f[i];
+        jx += L::ex(i) * f[i];
+        jy += L::ey(i) * f[i];
+    }
+}
+
+// Compact derivative line chunk (forward or backward recursion) for one item.
+__device__ void b_line(const BInst& I, int axis, long long item, const double* in, double* out, bool fwd, bool acc)
+{
+    const LineGeom& lg = I.lines[axis];
+    const long long nl = (long long)lg.n1 * lg.n2;
+    if (item >= nl * lg.nch) return;
+    const int o1 = (int)(item % lg.n1);
+    const long long rest = item / lg.n1;
+    const int o2 = (int)(rest % lg.n2);
+    const int ch = (int)(rest / lg.n2);
+    const long long base = o1 * lg.s1 + o2 * lg.s2;
+    const int start = ch * lg.C;
+    const int end = min(start + lg.C, lg.n);
+    if (fwd) {
+        const double ha = 0.5 * I.cc.ca, hb = 0.25 * I.cc.cb, hc = I.cc.cc / 6.0;
+        double a = 0.0;
+        for (long long i = (long long)start - lg.K; i < end; ++i) {
+            const int im = pmod(i, lg.n);
+            const double v = ha * (in[base + pmod(i + 1, lg.n) * lg.sa] - in[base + pmod(i - 1, lg.n) * lg.sa])
+                           + hb * (in[base + pmod(i + 2, lg.n) * lg.sa] - in[base + pmod(i - 2, lg.n) * lg.sa])
+                           + hc * (in[base + pmod(i + 3, lg.n) * lg.sa] - in[base + pmod(i - 3, lg.n) * lg.sa]);
+            a = v + I.z * a;
+            if (i >= start) I.wtmp[base + im * lg.sa] = a;
+        }
+    } else {
+        double a = 0.0;
+        for (long long i = (long long)end - 1 + lg.K; i >= start; --i) {
+            const int im = pmod(i, lg.n);
+            a = I.wtmp[base + im * lg.sa] + I.z * a;
+            if (i < end) {
+                const long long o = base + im * lg.sa;
+                out[o] = acc ? out[o] + I.zscale * a : I.zscale * a;
+            }
+        }
+    }
+}
+
+struct BatchArgs {
+    BInst* inst;
+    BState* st;
+    int ninst;
+    int nblk_total;           // node-block items over all instances
+    int nline_total[2];       // line-chunk items per axis over all instances
+    int* blk_inst;            // node-block item -> instance
+    int* line_inst[2];        // line item -> instance
+    double* partial;          // one max |v| per node-block item
+    int has_compact;
+    int nsteps;
+    int check_every;
+    double tol;
+};
+
+__device__ __forceinline__ void bar(cooperative_groups::grid_group& gg) { gg.sync(); }
+
+__global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
+{
+    namespace cg = cooperative_groups;
+    cg::grid_group gg = cg::this_grid();
+    using L = Lat<0>;
+    __shared__ double red[BNODES / 64];
+
+    for (int s = 0; s < a.nsteps; ++s) {
+        // ---- phase: density of the current state ------------------------------
+        for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
+            const int ii = a.blk_inst[it];
+            const BInst& I = a.inst[ii];
+            if (a.st[ii].status != B_RUNNING) continue;
+            const double* Sc = I.S[a.st[ii].steps & 1];
+            const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
+            if (n < I.g.N) {
+                int x, y, z;
+                coords(n, I.g, x, y, z);
+                double f[9], r, jx, jy;
+                b_moments(I, Sc, n, x, y, f, r, jx, jy);
+                I.rho[n] = r;
+            }
+        }
+        bar(gg);
+        // ---- phase: chemical potential (explicit schemes) ----------------------
+        for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
+            const int ii = a.blk_inst[it];
+            const BInst& I = a.inst[ii];
+            if (a.st[ii].status != B_RUNNING || is_compact(I.scheme)) continue;
+            const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
+            if (n < I.g.N) {
+                int x, y, z;
+                coords(n, I.g, x, y, z);
+                switch (I.scheme) {
+                case CD2: b_mu_node<CD2>(I, n, x, y); break;
+                case CD4: b_mu_node<CD4>(I, n, x, y); break;
+                case CD6: b_mu_node<CD6>(I, n, x, y); break;
+                case E4: b_mu_node<E4>(I, n, x, y); break;
+                default: b_mu_node<E8>(I, n, x, y); break;
+                }
+            }
+        }
+        // ---- compact schemes: D rho, D(D rho), mu, D mu (line solves) ---------
+        if (a.has_compact) {
+            for (int stage = 0; stage < 3; ++stage) {
+                for (int d = 0; d < 2; ++d) {
+                    for (int pass = 0; pass < 2; ++pass) {
+                        const int nt = a.nline_total[d] * 1;
+                        for (int it = blockIdx.x * BNODES + threadIdx.x; it < nt; it += gridDim.x * BNODES) {
+                            const int ii = a.line_inst[d][it];
+                            const BInst& I = a.inst[ii];
+                            if (a.st[ii].status != B_RUNNING || !is_compact(I.scheme)) continue;
+                            const long long item = it - I.line0[d];
+                            const double* in = stage == 0 ? I.rho : stage == 1 ? I.grho + d * I.g.N : I.mu;
+                            double* out = stage == 0 ? I.grho + d * I.g.N : stage == 1 ? I.lap : I.gmu + d * I.g.N;
+                            b_line(I, d, item, in, out, pass == 0, stage == 1 && d > 0);
+                        }
+                        bar(gg);
+                    }
+                }
+                if (stage == 1) {
+                    for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
+                        const int ii = a.blk_inst[it];
+                        const BInst& I = a.inst[ii];
+                        if (a.st[ii].status != B_RUNNING || !is_compact(I.scheme)) continue;
+                        const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
+                        if (n < I.g.N) I.mu[n] = mu_bulk(I.rho[n], I.eos) - I.eos.kappa * I.lap[n];
+                    }
+                    bar(gg);
+                }
+            }
+        }
+        bar(gg);
+        // ---- convergence check on the current state (every check_every steps) --
+        const bool check = a.check_every > 0;
+        if (check) {
+            for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
+                const int ii = a.blk_inst[it];
+                if (a.st[ii].status != B_RUNNING || a.st[ii].steps % a.check_every != 0) continue;
+                const BInst& I = a.inst[ii];
+                const double* Sc = I.S[a.st[ii].steps & 1];
+                const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
+                double vm = 0.0;
+                if (n < I.g.N) {
+                    int x, y, z;
+                    coords(n, I.g, x, y, z);
+                    double f[9], r, jx, jy, Fx, Fy, Fz;
+                    b_moments(I, Sc, n, x, y, f, r, jx, jy);
+                    b_force_any(I, n, x, y, r, Fx, Fy, Fz);
+                    const double ir = 1.0 / r;
+                    const double vx = (jx + 0.5 * Fx) * ir, vy = (jy + 0.5 * Fy) * ir;
+                    vm = sqrt(vx * vx + vy * vy);
+                    if (!(r == r) || r - r != 0.0) vm = r - r;
+                }
+                for (int o = 32; o > 0; o >>= 1) vm = nmax(vm, __shfl_xor(vm, o));
+                if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = vm;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double m = red[0];
+                    for (int k = 1; k < BNODES / 64; ++k) m = nmax(m, red[k]);
+                    a.partial[it] = m;
+                }
+                __syncthreads();
+            }
+            bar(gg);
+            // one thread per instance folds its node-block maxima in order
+            for (int ii = blockIdx.x * BNODES + threadIdx.x; ii < a.ninst; ii += gridDim.x * BNODES) {
+                BState& S = a.st[ii];
+                if (S.status != B_RUNNING || S.steps % a.check_every != 0) continue;
+                const BInst& I = a.inst[ii];
+                double U = 0.0;
+                for (int k = 0; k < I.nblk; ++k) U = nmax(U, a.partial[I.blk0 + k]);
+                S.U_prev = S.U;
+                S.U = U;
+                if (!(U == U) || U - U != 0.0 || U > 0.5773502691896258) S.status = B_DIVERGED;
+                else if (S.steps > 0 && fabs(U - S.U_prev) < a.tol) S.status = B_CONVERGED;
+            }
+            bar(gg);
+        }
+        // ---- phase: collision of every running instance -------------------------
+        for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
+            const int ii = a.blk_inst[it];
+            if (a.st[ii].status != B_RUNNING) continue;
+            const BInst& I = a.inst[ii];
+            const int cur = (int)(a.st[ii].steps & 1);
+            const double* Sc = I.S[cur];
+            double* Sn = I.S[1 - cur];
+            const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
+            if (n < I.g.N) {
+                int x, y, z;
+                coords(n, I.g, x, y, z);
+                double f[9], r, jx, jy, Fx, Fy, Fz, out[9];
+                b_moments(I, Sc, n, x, y, f, r, jx, jy);
+                b_force_any(I, n, x, y, r, Fx, Fy, Fz);
+                collide<0>(f, r, jx, jy, 0.0, Fx, Fy, Fz, I.one_m_omega, out);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) Sn[(long long)i * I.g.N + n] = out[i];
+            }
+        }
+        bar(gg);
+        // ---- advance step counters ----------------------------------------------
+        for (int ii = blockIdx.x * BNODES + threadIdx.x; ii < a.ninst; ii += gridDim.x * BNODES)
+            if (a.st[ii].status == B_RUNNING) a.st[ii].steps++;
+        bar(gg);
+    }
+}
+
+}  // namespace lbm

@@ -55,6 +55,16 @@ SYMBOLS = {
     "lbm_free": (None, [C.c_void_p]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_critical": (C.c_int, [_P, _D, _D, _D]),
+    "lbm_batch_workspace_bytes": (C.c_size_t, [_P, C.c_int]),
+    "lbm_batch_init": (C.c_int, [_P, C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
+                                 C.POINTER(C.c_void_p)]),
+    "lbm_batch_set_grid": (C.c_int, [C.c_void_p, C.c_int]),
+    "lbm_batch_max_grid": (C.c_int, [C.c_void_p]),
+    "lbm_batch_run": (C.c_int, [C.c_void_p, C.c_long, C.c_long, C.c_double, C.c_long, C.POINTER(C.c_int),
+                                C.POINTER(C.c_long), _D]),
+    "lbm_batch_instance": (C.c_void_p, [C.c_void_p, C.c_int]),
+    "lbm_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_batch_free": (None, [C.c_void_p]),
     "lbm_coexistence": (C.c_int, [_P, _D, _D]),
 }
 
@@ -138,6 +148,14 @@ def coexistence(Tr: float, p: Params | None = None):
     return g.value, l.value
 
 
+class _View:
+    """Observables of a context owned elsewhere (an instance of a batch)."""
+
+    def __init__(self, ctx, p: Params, device, owner):
+        import torch
+        self.ctx, self.p, self.device, self.torch, self._owner = ctx, p, device, torch, owner
+
+
 class Simulation:
     """One lattice on one GPU: a caller-owned torch workspace, a torch stream."""
 
@@ -204,12 +222,7 @@ class Simulation:
 
     def macros(self):
         """(rho, vx, vy, vz) host arrays shaped like the grid (vz None in 2D)."""
-        p = self.p
-        out = [np.empty(p.n) for _ in range(4 if p.lattice == D3Q19 else 3)]
-        ptrs = [a.ctypes.data_as(C.c_void_p) for a in out] + ([None] if p.lattice == D2Q9 else [])
-        _check(lib().lbm_macros(self.ctx, *ptrs, 0), self.ctx)
-        res = [a.reshape(p.shape) for a in out]
-        return tuple(res) if p.lattice == D3Q19 else (res[0], res[1], res[2], None)
+        return _macros(self)
 
     def macros_device(self):
         """(rho, vx, vy[, vz]) as torch float64 tensors on the device."""
@@ -222,21 +235,123 @@ class Simulation:
 
     def spurious_max(self, raise_on_nonfinite: bool = False):
         """(U = max |v|, total mass, status code)."""
-        u, m = C.c_double(), C.c_double()
-        code = lib().lbm_spurious_max(self.ctx, C.byref(u), C.byref(m))
-        if code not in (LBM_OK, LBM_ENONFINITE) or (raise_on_nonfinite and code != LBM_OK):
-            _check(code, self.ctx)
-        return u.value, m.value, code
+        return _spurious(self, raise_on_nonfinite)
 
     def populations(self) -> np.ndarray:
-        f = np.empty(self.p.q * self.p.n)
-        _check(lib().lbm_populations(self.ctx, f.ctypes.data_as(C.c_void_p), 0), self.ctx)
-        return f.reshape(self.p.q, -1)
+        return _populations(self)
 
     def close(self) -> None:
         if getattr(self, "ctx", None):
             lib().lbm_free(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _macros(obj):
+    p = obj.p
+    out = [np.empty(p.n) for _ in range(4 if p.lattice == D3Q19 else 3)]
+    ptrs = [a.ctypes.data_as(C.c_void_p) for a in out] + ([None] if p.lattice == D2Q9 else [])
+    _check(lib().lbm_macros(obj.ctx, *ptrs, 0), obj.ctx)
+    res = [a.reshape(p.shape) for a in out]
+    return tuple(res) if p.lattice == D3Q19 else (res[0], res[1], res[2], None)
+
+
+def _spurious(obj, raise_on_nonfinite=False):
+    u, m = C.c_double(), C.c_double()
+    code = lib().lbm_spurious_max(obj.ctx, C.byref(u), C.byref(m))
+    if code not in (LBM_OK, LBM_ENONFINITE) or (raise_on_nonfinite and code != LBM_OK):
+        _check(code, obj.ctx)
+    return u.value, m.value, code
+
+
+def _populations(obj):
+    f = np.empty(obj.p.q * obj.p.n)
+    _check(lib().lbm_populations(obj.ctx, f.ctypes.data_as(C.c_void_p), 0), obj.ctx)
+    return f.reshape(obj.p.q, -1)
+
+
+_View.macros = _macros
+_View.spurious_max = _spurious
+_View.populations = _populations
+_View.steps_done = property(lambda self: int(lib().lbm_steps_done(self.ctx)))
+
+RUNNING, CONVERGED, DIVERGED = 0, 1, 2
+
+
+class Batch:
+    """Uneven D2Q9 instances stepped together by the cooperative persistent kernel."""
+
+    def __init__(self, params, rho0s, device: str = "cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = list(params)
+        n = len(self.params)
+        self._cps = (lbm_params * n)(*[p.c() for p in self.params])
+        nbytes = int(lib().lbm_batch_workspace_bytes(self._cps, n))
+        if nbytes == 0:
+            raise LbmError(LBM_EINVAL, _err(None))
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._rho = [np.ascontiguousarray(r, dtype=np.float64).reshape(-1) for r in rho0s]
+        ptrs = (C.c_void_p * n)(*[r.ctypes.data for r in self._rho])
+        h = C.c_void_p()
+        code = lib().lbm_batch_init(self._cps, ptrs, n, C.c_void_p(self.ws.data_ptr()), nbytes,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if code != LBM_OK:
+            raise LbmError(code, _err(None))
+        self.h = h
+        self.n = n
+
+    @property
+    def max_grid(self) -> int:
+        return int(lib().lbm_batch_max_grid(self.h))
+
+    def set_grid(self, wg: int) -> None:
+        code = lib().lbm_batch_set_grid(self.h, int(wg))
+        if code != LBM_OK:
+            raise LbmError(code, lib().lbm_batch_last_error(self.h).decode())
+
+    def run(self, nsteps: int, check_every: int = 100, tol: float = 1e-10, chunk: int = 1000):
+        """Advance; returns (status[n], steps[n], U[n]) numpy arrays."""
+        st = (C.c_int * self.n)()
+        sp = (C.c_long * self.n)()
+        um = (C.c_double * self.n)()
+        code = lib().lbm_batch_run(self.h, int(nsteps), int(check_every), float(tol), int(chunk), st, sp, um)
+        if code != LBM_OK:
+            raise LbmError(code, lib().lbm_batch_last_error(self.h).decode())
+        return np.array(st[:]), np.array(sp[:]), np.array(um[:])
+
+    def instance(self, i: int):
+        ctx = lib().lbm_batch_instance(self.h, int(i))
+        return _View(C.c_void_p(ctx), self.params[i], self.device, self)
+
+    def tune(self, steps: int = 50, candidates=None):
+        """Time the cooperative launch at several workgroup counts (the state
+        advances) and keep the fastest.  Returns {workgroups: ms per step}."""
+        import time
+        mg = self.max_grid
+        cands = candidates or sorted({mg, max(1, mg // 2), max(1, mg // 4)})
+        res = {}
+        for wg in cands:
+            self.set_grid(wg)
+            self.torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            self.run(steps, check_every=10 ** 9, tol=0.0, chunk=steps)
+            res[wg] = (time.perf_counter() - t0) * 1e3 / steps
+        best = min(res, key=res.get)
+        self.set_grid(best)
+        return res
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_batch_free(self.h)
+            self.h = None
 
     def __del__(self):
         try:

@@ -1,0 +1,92 @@
+"""Batched sweep (cooperative persistent kernel) against independent plain runs
+of each instance, retirement of converged / diverged instances, and launch
+size independence."""
+import numpy as np
+import pytest
+
+from paper_2205_09186_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_09186_amd import lbm
+    lbm.lib()
+    return lbm
+
+
+def _specs(L):
+    # (kind, ny, nx, scheme, Tr, k, R)
+    return [("slab", 64, 8, L.CD4, 0.8, 0.12, 0), ("slab", 96, 8, L.OCFDS4, 0.7, 0.1, 0),
+            ("drop", 48, 48, L.CD6, 0.8, 0.2, 12), ("drop", 48, 48, L.E8, 0.95, 0.1, 12),
+            ("drop", 56, 56, L.CD2, 0.9, 0.25, 14), ("drop", 64, 64, L.E4, 0.9, 0.1, 15),
+            ("drop", 72, 40, L.OCFDS4, 0.8, 0.16, 9)]
+
+
+def _build(L, specs):
+    ps, rs = [], []
+    for idx, (kind, ny, nx, sch, Tr, k, R) in enumerate(specs):
+        g, l = L.coexistence(Tr)
+        if kind == "slab":
+            r = inputs.slab((ny, nx), 0, 10.0, g, l, instance_id=idx)
+        else:
+            r = inputs.droplet((ny, nx), R, 4.0, g, l, instance_id=idx)
+        ps.append(L.Params(lattice=L.D2Q9, nx=nx, ny=ny, Tr=Tr, k=k, kappa=0.004, scheme=sch))
+        rs.append(r)
+    return ps, rs
+
+
+def test_batch_matches_plain_runs(L):
+    ps, rs = _build(L, _specs(L))
+    b = L.Batch(ps, rs)
+    print("batch grid", b.max_grid, flush=True)
+    st, steps, U = b.run(300, check_every=100, tol=0.0, chunk=120)
+    assert list(st) == [L.RUNNING] * len(ps)
+    assert list(steps) == [300] * len(ps)
+    for i, (p, r) in enumerate(zip(ps, rs)):
+        s = L.Simulation(p, r)
+        s.step(200)
+        U200 = s.spurious_max()[0]
+        s.step(100)
+        v = b.instance(i)
+        assert v.steps_done == 300
+        fa, fb = v.populations(), s.populations()
+        assert np.abs(fa - fb).max() < 1e-11, i
+        ra, rb = v.macros()[0], s.macros()[0]
+        assert np.abs(ra - rb).max() < 1e-11, i
+        # U of the last check (taken at step 200, before that step's collision)
+        assert U[i] == pytest.approx(U200, abs=1e-11)
+
+
+def test_batch_retires_diverged_and_converged(L):
+    specs = [("drop", 100, 100, L.CD2, 0.8, 0.16, 25), ("drop", 48, 48, L.CD4, 0.9, 0.16, 12),
+             ("slab", 64, 8, L.CD6, 0.8, 0.1, 0)]
+    ps, rs = _build(L, specs)
+    b = L.Batch(ps, rs)
+    st, steps, U = b.run(600, check_every=50, tol=0.0, chunk=200)
+    assert st[0] == L.DIVERGED and steps[0] < 600
+    assert list(st[1:]) == [L.RUNNING, L.RUNNING] and list(steps[1:]) == [600, 600]
+    # the diverged instance stopped stepping; the others are unaffected
+    for i in (1, 2):
+        s = L.Simulation(ps[i], rs[i])
+        s.step(600)
+        assert np.abs(b.instance(i).populations() - s.populations()).max() < 1e-11
+    # a loose tolerance retires the running instances at their next check
+    st2, steps2, _ = b.run(500, check_every=50, tol=1.0, chunk=500)
+    assert st2[0] == L.DIVERGED and steps2[0] == steps[0]
+    assert list(st2[1:]) == [L.CONVERGED, L.CONVERGED] and list(steps2[1:]) == [600, 600]
+
+
+def test_batch_launch_size_independent(L):
+    ps, rs = _build(L, _specs(L)[:4])
+    a = L.Batch(ps, rs)
+    b = L.Batch(ps, rs)
+    b.set_grid(max(1, b.max_grid // 7))
+    a.run(150, check_every=50, tol=0.0, chunk=150)
+    b.run(150, check_every=50, tol=0.0, chunk=60)
+    for i in range(len(ps)):
+        assert np.array_equal(a.instance(i).populations(), b.instance(i).populations())
