@@ -106,6 +106,13 @@ struct lbm_ctx {
     double z, zscale;
     bool fused;     // explicit schemes: fused collide + next-density kernel
     int variant = 0;  // launch variant of the fused kernel
+    // two-step launch graph replayed by lbm_step (captured on a private stream,
+    // launched on the context's stream); graph_cur is the state parity it
+    // starts from, graph_variant the launch variant it was captured with
+    hipGraphExec_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int graph_cur = -1, graph_variant = -1;
+    bool use_graph = true;
     // phase timing (lbm_step_timed)
     bool timing = false;
     int nmarks = 0;
@@ -318,6 +325,7 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->steps = 0;
     c->one_m_omega = 1.0 - 1.0 / p->tau;
     c->fused = p->scheme <= LBM_CD6 && c->g.N < (1LL << 31) && std::getenv("LBM_NO_FUSED") == nullptr;
+    c->use_graph = std::getenv("LBM_NO_GRAPH") == nullptr;
     set_lines(c);
 
     // equation of state in mesh units (Eq 16): k^2 psi'
@@ -373,11 +381,64 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     return LBM_OK;
 }
 
+namespace {
+
+// Capture the launch sequence of two consecutive steps (state parity cur, then
+// 1 - cur) into an executable graph.
+int capture_pair(lbm_ctx* c)
+{
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    int r;
+    if (!c->cap_stream &&
+        (r = hip_check(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream")))
+        return r;
+    hipStream_t user = c->stream;
+    const int cur0 = c->cur;
+    c->stream = c->cap_stream;
+    hipGraph_t g = nullptr;
+    r = hip_check(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (r == LBM_OK) {
+        dispatch<StepOp>(c->p.lattice, c->p.scheme, c);
+        dispatch<StepOp>(c->p.lattice, c->p.scheme, c);
+        r = hip_check(c, hipStreamEndCapture(c->cap_stream, &g), "end capture");
+    }
+    c->stream = user;
+    c->cur = cur0;   // capture only recorded the launches
+    if (r == LBM_OK) r = hip_check(c, hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0), "instantiate graph");
+    if (g) (void)hipGraphDestroy(g);
+    if (r == LBM_OK) { c->graph_cur = cur0; c->graph_variant = c->variant; }
+    else c->graph = nullptr;
+    return r;
+}
+
+}  // namespace
+
 int lbm_step(lbm_ctx* c, long nsteps)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
-    for (long s = 0; s < nsteps; ++s) {
+    long s = 0;
+    if (c->use_graph && nsteps >= 4) {
+        if (c->cur != c->graph_cur && c->graph && c->graph_variant == c->variant) {
+            // align the parity with the captured pair by one plain step
+            dispatch<StepOp>(c->p.lattice, c->p.scheme, c);
+            c->steps++;
+            s++;
+        }
+        if (!c->graph || c->graph_variant != c->variant || c->cur != c->graph_cur) {
+            if (capture_pair(c) != LBM_OK) {
+                // no graph on this runtime: plain launches from here on
+                c->use_graph = false;
+                (void)hipGetLastError();
+            }
+        }
+        for (; c->use_graph && s + 2 <= nsteps; s += 2) {
+            int r = hip_check(c, hipGraphLaunch(c->graph, c->stream), "graph launch");
+            if (r) return r;
+            c->steps += 2;
+        }
+    }
+    for (; s < nsteps; ++s) {
         dispatch<StepOp>(c->p.lattice, c->p.scheme, c);
         c->steps++;
     }
@@ -510,6 +571,8 @@ const char* lbm_phase_name(const lbm_ctx* c, int k)
 void lbm_free(lbm_ctx* c)
 {
     if (!c) return;
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (int k = 0; k < 16; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     delete c;

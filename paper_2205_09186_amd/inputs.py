@@ -6,7 +6,8 @@ and every other physical quantity are passed in by the caller.
 
 * Noise: a splitmix64 stream seeded with ``220509186 + instance_id``; the k-th
   draw (k = 1, 2, ...) is ``u = (x >> 11) * 2**-53`` and the noise is
-  ``(2u - 1) * amplitude``, assigned in node order, x fastest.
+  ``(2u - 1) * amplitude``, assigned in node order, x fastest; added to the
+  density, or (``relative``) applied as a factor ``1 + noise``.
 * Droplet: the tanh profile of Eq 26 between given liquid and gas densities,
   centred at node (nx/2, ny/2[, nz/2]), r the Euclidean node distance (no
   periodic image).
@@ -53,8 +54,11 @@ def _tanh_shape(dist: np.ndarray, r0: float, W: float, rho_g: float, rho_l: floa
 
 
 def droplet(shape, radius: float, width: float, rho_g: float, rho_l: float,
-            amplitude: float = 1e-6, instance_id: int = 0, center=None) -> np.ndarray:
-    """Circular (2D, shape (ny, nx)) or spherical (3D, shape (nz, ny, nx)) droplet."""
+            amplitude: float = 1e-6, instance_id: int = 0, center=None, relative: bool = False) -> np.ndarray:
+    """Circular (2D, shape (ny, nx)) or spherical (3D, shape (nz, ny, nx)) droplet.
+
+    relative=True applies the noise as rho (1 + n), which keeps the density
+    positive when the gas density is below the noise amplitude (low Tr)."""
     shape = tuple(int(s) for s in shape)
     if center is None:
         center = tuple(s // 2 for s in shape)   # node (n/2) on each axis
@@ -64,12 +68,13 @@ def droplet(shape, radius: float, width: float, rho_g: float, rho_l: float,
         r2 += (g - c) ** 2
     rho = _tanh_shape(np.sqrt(r2), radius, width, rho_g, rho_l)
     if amplitude:
-        rho = rho + noise(shape, amplitude, instance_id)
+        nz = noise(shape, amplitude, instance_id)
+        rho = rho * (1.0 + nz) if relative else rho + nz
     return np.ascontiguousarray(rho)
 
 
 def slab(shape, axis: int, width: float, rho_g: float, rho_l: float,
-         amplitude: float = 1e-6, instance_id: int = 0) -> np.ndarray:
+         amplitude: float = 1e-6, instance_id: int = 0, relative: bool = False) -> np.ndarray:
     """Flat liquid layer filling the central half of array axis ``axis``."""
     shape = tuple(int(s) for s in shape)
     H = shape[axis]
@@ -80,7 +85,8 @@ def slab(shape, axis: int, width: float, rho_g: float, rho_l: float,
     bshape[axis] = H
     rho = np.broadcast_to(prof.reshape(bshape), shape).copy()
     if amplitude:
-        rho = rho + noise(shape, amplitude, instance_id)
+        nz = noise(shape, amplitude, instance_id)
+        rho = rho * (1.0 + nz) if relative else rho + nz
     return np.ascontiguousarray(rho)
 
 

@@ -194,3 +194,27 @@ def test_launch_variants_identical(L, orc, lat, shape):
         else:
             assert np.array_equal(f, ref), v
     assert ref is not None
+
+
+@pytest.mark.parametrize("lat,shape,scheme", [(0, (100, 100), "CD4"), (1, (20, 24, 28), "CD6"),
+                                              (0, (40, 44), "OCFDS4")])
+def test_graph_replay_equals_plain_launches(L, orc, lat, shape, scheme, monkeypatch):
+    """lbm_step replays a captured two-step graph; the state after any mix of
+    odd and even step counts is bitwise that of plain launches."""
+    g, l = orc.maxwell(0.8)
+    rho0 = inputs.droplet(shape, min(shape) / 4, 4.0, g, l)
+    nz, ny, nx = ((1,) + shape) if lat == 0 else shape
+    p = L.Params(lattice=lat, nx=nx, ny=ny, nz=nz, Tr=0.8, scheme=L.SCHEMES[scheme])
+    a = L.Simulation(p, rho0)
+    monkeypatch.setenv("LBM_NO_GRAPH", "1")
+    b = L.Simulation(p, rho0)
+    monkeypatch.delenv("LBM_NO_GRAPH")
+    for n in (7, 10, 1, 5, 4):
+        a.step(n)
+        b.step(n)
+    assert a.steps_done == b.steps_done == 27
+    assert np.array_equal(a.populations(), b.populations())
+    a.set_variant(a.num_variants - 1)
+    b.set_variant(b.num_variants - 1)
+    a.step(9); b.step(9)
+    assert np.array_equal(a.populations(), b.populations())
