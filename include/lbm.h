@@ -177,6 +177,45 @@ lbm_ctx* lbm_batch_instance(lbm_batch* b, int i);
 const char* lbm_batch_last_error(const lbm_batch* b);
 void lbm_batch_free(lbm_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Learned initialiser: FP32 network 4 -> 64 -> 64 -> 64 -> 1 (SiLU) mapping
+ * (Tr, k, scheme id, signed distance to the interface), each scaled, to the
+ * normalised density phi = (rho - rho_g)/(rho_l - rho_g) of an equilibrium
+ * interface.  Flat parameter layout (mlp_param_count() = 8705 floats):
+ * W1 (64x4, row = output), b1, W2 (64x64), b2, W3 (64x64), b3, W4 (1x64), b4.
+ * All pointers are device pointers; calls are enqueued on `stream` and return.
+ * ------------------------------------------------------------------------ */
+int mlp_param_count(void);
+
+/* y[B] = net(x[B][4]); acts (B*192 floats, may be NULL) receives the
+ * pre-activations for mlp_backward. */
+int mlp_forward(const float* d_params, const float* d_x, int B, float* d_y, float* d_acts, void* stream);
+
+/* Mean-squared-error gradient dy = 2 (y - t)/B and per-64-sample partial sums
+ * of (y - t)^2 (ceil(B/64) floats). */
+int mlp_loss_grad(const float* d_y, const float* d_t, int B, float* d_dy, float* d_loss_partial, void* stream);
+
+/* Parameter gradient of the loss (8705 floats) by backpropagation; d_gpart is
+ * scratch of ceil(B/64)*8705 floats.  Deterministic: fixed summation order. */
+int mlp_backward(const float* d_params, const float* d_x, const float* d_acts, const float* d_dy, int B,
+                 float* d_grad, float* d_gpart, void* stream);
+
+/* One Adam update (step >= 1) of the parameters with moments m, v. */
+int mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr, float b1,
+             float b2, float eps, void* stream);
+
+/* Initial density field for the grid of p: rho = rho_g + clamp(phi,0,1)(rho_l
+ * - rho_g) with phi = net(feat3[0..2], (|x - c| - R)/norm7[6]); norm7 holds the
+ * feature scaling (Tr shift, scale, k shift, scale, scheme shift, scale,
+ * distance scale), feat3 the scaled (Tr, k, scheme).  d_rho: N doubles. */
+int mlp_field(const float* d_params, const float* norm7, const lbm_params* p, double cx, double cy, double cz,
+              double R, const float* feat3, double rho_g, double rho_l, double* d_rho, void* stream);
+
+/* Deterministic sum of n device doubles (scratch: lbm_sum_scratch_bytes(n)).
+ * Synchronises. */
+size_t lbm_sum_scratch_bytes(long n);
+int lbm_sum(const double* d_x, long n, double* d_scratch, double* h_sum, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

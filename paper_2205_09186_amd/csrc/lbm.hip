@@ -16,6 +16,7 @@
 #include "lbm_eos_host.hpp"
 #include "lbm_fused.hpp"
 #include "lbm_kernels.hpp"
+#include "lbm_mlp.hpp"
 
 using namespace lbm;
 
@@ -624,6 +625,27 @@ struct lbm_batch {
 
 namespace {
 
+constexpr int kConvMax = 128;   // longest convolution kernel (M + 1 entries)
+
+// Antisymmetric convolution kernel c_0..c_M of the periodic compact derivative:
+// the cyclic inverse of 1 + al (S + S^-1) has entries (1+z^2)/(1-z^2) z^|k|,
+// applied to the right-hand side sum_m r_m (g_{i+m} - g_{i-m}) of Eq 21.
+int compact_conv(int scheme, double* c)
+{
+    const Compact cc = compact_scheme(scheme);
+    const double z = (-1.0 + std::sqrt(1.0 - 4.0 * cc.al * cc.al)) / (2.0 * cc.al);
+    const int K = (int)std::ceil(std::log(1e-18) / std::log(std::fabs(z)));
+    const int M = K + 3;
+    const double r[4] = { 0.0, 0.5 * cc.ca, 0.25 * cc.cb, cc.cc / 6.0 };
+    auto h = [&](int k) { return (1.0 + z * z) / (1.0 - z * z) * std::pow(z, std::abs(k)); };
+    for (int j = 0; j <= M && j < kConvMax; ++j) {
+        double s = 0.0;
+        for (int m = 1; m <= 3; ++m) s += r[m] * (h(j - m) - h(j + m));
+        c[j] = s;
+    }
+    return std::min(M, kConvMax - 1);
+}
+
 struct BatchLayout {
     std::vector<size_t> inst_off;
     size_t tables, total;
@@ -652,6 +674,7 @@ bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
     off = align_up(off + sizeof(int) * B.nline[0]);
     off = align_up(off + sizeof(int) * B.nline[1]);
     off = align_up(off + sizeof(double) * B.nblk);
+    off = align_up(off + sizeof(double) * 4 * kConvMax);
     B.total = off;
     return true;
 }
@@ -733,13 +756,28 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     b->d_blk_inst = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nblk);
     b->d_line_inst[0] = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nline[0]);
     b->d_line_inst[1] = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nline[1]);
-    b->d_partial = reinterpret_cast<double*>(b->ws + off);
+    b->d_partial = reinterpret_cast<double*>(b->ws + off); off = align_up(off + sizeof(double) * B.nblk);
+    double* d_conv = reinterpret_cast<double*>(b->ws + off);
+    std::vector<double> conv(4 * kConvMax, 0.0);
+    int convM[4];
+    for (int k = 0; k < 4; ++k) convM[k] = compact_conv(LBM_OCFDS4 + k, conv.data() + k * kConvMax);
+    for (int i = 0; i < n; ++i) {
+        if (ps[i].scheme >= LBM_OCFDS4) {
+            const int k = ps[i].scheme - LBM_OCFDS4;
+            b->inst[i].cconv = d_conv + k * kConvMax;
+            b->inst[i].M = convM[k];
+        } else {
+            b->inst[i].cconv = nullptr;
+            b->inst[i].M = 0;
+        }
+    }
     b->nblk_total = (int)blk_inst.size();
     b->nline_total[0] = (int)line_inst[0].size();
     b->nline_total[1] = (int)line_inst[1].size();
     std::vector<BState> st(n);
     for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.U = 0.0; x.U_prev = 0.0; }
-    hipError_t e = hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, b->stream);
+    hipError_t e = hipMemcpyAsync(d_conv, conv.data(), sizeof(double) * conv.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_st, st.data(), sizeof(BState) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_blk_inst, blk_inst.data(), sizeof(int) * blk_inst.size(),
                                             hipMemcpyHostToDevice, b->stream);
@@ -828,6 +866,87 @@ void lbm_batch_free(lbm_batch* b)
     if (!b) return;
     for (auto* c : b->ctx) lbm_free(c);
     delete b;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned initialiser (FP32 network kernels)
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int mlp_param_count(void) { return MP; }
+
+int mlp_forward(const float* d_params, const float* d_x, int B, float* d_y, float* d_acts, void* stream)
+{
+    if (!d_params || !d_x || !d_y || B < 1) return fail(nullptr, LBM_EINVAL, "mlp_forward: bad arguments");
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((B + MB - 1) / MB), dim3(MB), 0, reinterpret_cast<hipStream_t>(stream),
+                       d_params, d_x, B, d_y, d_acts);
+    return hip_check(nullptr, hipGetLastError(), "mlp_forward");
+}
+
+int mlp_loss_grad(const float* d_y, const float* d_t, int B, float* d_dy, float* d_loss_partial, void* stream)
+{
+    if (!d_y || !d_t || !d_dy || !d_loss_partial || B < 1) return fail(nullptr, LBM_EINVAL, "mlp_loss_grad: bad arguments");
+    hipLaunchKernelGGL(k_mlp_loss, dim3((B + MB - 1) / MB), dim3(MB), 0, reinterpret_cast<hipStream_t>(stream),
+                       d_y, d_t, B, d_dy, d_loss_partial);
+    return hip_check(nullptr, hipGetLastError(), "mlp_loss_grad");
+}
+
+int mlp_backward(const float* d_params, const float* d_x, const float* d_acts, const float* d_dy, int B,
+                 float* d_grad, float* d_gpart, void* stream)
+{
+    if (!d_params || !d_x || !d_acts || !d_dy || !d_grad || !d_gpart || B < 1)
+        return fail(nullptr, LBM_EINVAL, "mlp_backward: bad arguments");
+    const int nb = (B + MB - 1) / MB;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_mlp_bwd, dim3(nb), dim3(MB), 0, st, d_params, d_x, d_acts, d_dy, B, d_gpart);
+    hipLaunchKernelGGL(k_mlp_gsum, dim3((MP + 255) / 256), dim3(256), 0, st, d_gpart, nb, d_grad);
+    return hip_check(nullptr, hipGetLastError(), "mlp_backward");
+}
+
+int mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr, float b1, float b2,
+             float eps, void* stream)
+{
+    if (!d_params || !d_grad || !d_m || !d_v || step < 1) return fail(nullptr, LBM_EINVAL, "mlp_adam: bad arguments");
+    const float c1 = 1.0f - std::pow(b1, (float)step), c2 = 1.0f - std::pow(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((MP + 255) / 256), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), d_params,
+                       d_grad, d_m, d_v, lr, b1, b2, eps, c1, c2);
+    return hip_check(nullptr, hipGetLastError(), "mlp_adam");
+}
+
+int mlp_field(const float* d_params, const float* norm7, const lbm_params* p, double cx, double cy, double cz,
+              double R, const float* feat3, double rho_g, double rho_l, double* d_rho, void* stream)
+{
+    if (!d_params || !norm7 || !feat3 || !d_rho) return fail(nullptr, LBM_EINVAL, "mlp_field: bad arguments");
+    if (const char* why = validate(p)) return fail(nullptr, LBM_EINVAL, why);
+    Grid g;
+    g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
+    g.nxy = (long long)p->nx * p->ny;
+    g.N = g.nxy * p->nz;
+    MlpNorm nm = { norm7[0], norm7[1], norm7[2], norm7[3], norm7[4], norm7[5], norm7[6] };
+    hipLaunchKernelGGL(k_mlp_field, dim3((unsigned)((g.N + MB - 1) / MB)), dim3(MB), 0,
+                       reinterpret_cast<hipStream_t>(stream), d_params, nm, g, cx, cy, cz, R, feat3[0], feat3[1],
+                       feat3[2], rho_g, rho_l, d_rho);
+    return hip_check(nullptr, hipGetLastError(), "mlp_field");
+}
+
+size_t lbm_sum_scratch_bytes(long n) { return n < 1 ? 0 : sizeof(double) * (2 * ((n + 255) / 256) + 2); }
+
+int lbm_sum(const double* d_x, long n, double* d_scratch, double* h_sum, void* stream)
+{
+    if (!d_x || !d_scratch || !h_sum || n < 1) return fail(nullptr, LBM_EINVAL, "lbm_sum: bad arguments");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const long long nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)nb), dim3(256), 0, st, d_x, (long long)n, d_scratch);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, st, d_scratch, nb, d_scratch + 2 * nb);
+    double h[2];
+    int r = hip_check(nullptr, hipMemcpyAsync(h, d_scratch + 2 * nb, sizeof(h), hipMemcpyDeviceToHost, st), "sum copy");
+    if (r) return r;
+    r = hip_check(nullptr, hipStreamSynchronize(st), "sum sync");
+    if (r) return r;
+    *h_sum = h[1];
+    return LBM_OK;
 }
 
 }  // extern "C"

@@ -32,6 +32,8 @@ struct BInst {
     LineGeom lines[2];
     Compact cc;
     double z, zscale;
+    const double* cconv;    // compact derivative as a periodic convolution: c_1..c_M
+    int M;
     int blk0, nblk;         // node-block items [blk0, blk0 + nblk)
     int line0[2], nline[2]; // line-chunk items per axis
     int part0;              // first partial slot of its node blocks
@@ -87,43 +89,6 @@ __device__ void b_moments(const BInst& I, const double* S, long long n, int x, i
         r += f[i];
         jx += L::ex(i) * f[i];
         jy += L::ey(i) * f[i];
-    }
-}
-
-// Compact derivative line chunk (forward or backward recursion) for one item.
-__device__ void b_line(const BInst& I, int axis, long long item, const double* in, double* out, bool fwd, bool acc)
-{
-    const LineGeom& lg = I.lines[axis];
-    const long long nl = (long long)lg.n1 * lg.n2;
-    if (item >= nl * lg.nch) return;
-    const int o1 = (int)(item % lg.n1);
-    const long long rest = item / lg.n1;
-    const int o2 = (int)(rest % lg.n2);
-    const int ch = (int)(rest / lg.n2);
-    const long long base = o1 * lg.s1 + o2 * lg.s2;
-    const int start = ch * lg.C;
-    const int end = min(start + lg.C, lg.n);
-    if (fwd) {
-        const double ha = 0.5 * I.cc.ca, hb = 0.25 * I.cc.cb, hc = I.cc.cc / 6.0;
-        double a = 0.0;
-        for (long long i = (long long)start - lg.K; i < end; ++i) {
-            const int im = pmod(i, lg.n);
-            const double v = ha * (in[base + pmod(i + 1, lg.n) * lg.sa] - in[base + pmod(i - 1, lg.n) * lg.sa])
-                           + hb * (in[base + pmod(i + 2, lg.n) * lg.sa] - in[base + pmod(i - 2, lg.n) * lg.sa])
-                           + hc * (in[base + pmod(i + 3, lg.n) * lg.sa] - in[base + pmod(i - 3, lg.n) * lg.sa]);
-            a = v + I.z * a;
-            if (i >= start) I.wtmp[base + im * lg.sa] = a;
-        }
-    } else {
-        double a = 0.0;
-        for (long long i = (long long)end - 1 + lg.K; i >= start; --i) {
-            const int im = pmod(i, lg.n);
-            a = I.wtmp[base + im * lg.sa] + I.z * a;
-            if (i < end) {
-                const long long o = base + im * lg.sa;
-                out[o] = acc ? out[o] + I.zscale * a : I.zscale * a;
-            }
-        }
     }
 }
 
@@ -186,34 +151,54 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
                 }
             }
         }
-        // ---- compact schemes: D rho, D(D rho), mu, D mu (line solves) ---------
+        // ---- compact schemes: D rho; then D(D rho) and mu; then D mu ------------
+        // The periodic compact derivative equals a convolution with the
+        // antisymmetric kernel c_j (|j| <= M) of the exact cyclic inverse:
+        // (D g)_i = sum_{j=1..M} c_j (g_{i+j} - g_{i-j}), indices mod n.
         if (a.has_compact) {
             for (int stage = 0; stage < 3; ++stage) {
-                for (int d = 0; d < 2; ++d) {
-                    for (int pass = 0; pass < 2; ++pass) {
-                        const int nt = a.nline_total[d] * 1;
-                        for (int it = blockIdx.x * BNODES + threadIdx.x; it < nt; it += gridDim.x * BNODES) {
-                            const int ii = a.line_inst[d][it];
-                            const BInst& I = a.inst[ii];
-                            if (a.st[ii].status != B_RUNNING || !is_compact(I.scheme)) continue;
-                            const long long item = it - I.line0[d];
-                            const double* in = stage == 0 ? I.rho : stage == 1 ? I.grho + d * I.g.N : I.mu;
-                            double* out = stage == 0 ? I.grho + d * I.g.N : stage == 1 ? I.lap : I.gmu + d * I.g.N;
-                            b_line(I, d, item, in, out, pass == 0, stage == 1 && d > 0);
+                for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
+                    const int ii = a.blk_inst[it];
+                    const BInst& I = a.inst[ii];
+                    if (a.st[ii].status != B_RUNNING || !is_compact(I.scheme)) continue;
+                    const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
+                    if (n >= I.g.N) continue;
+                    int x, y, z;
+                    coords(n, I.g, x, y, z);
+                    const int nx = I.g.nx, ny = I.g.ny;
+                    const long long row = (long long)y * nx;
+                    auto dx = [&](const double* f) {
+                        double acc = 0.0;
+                        int xp = x, xm = x;
+                        for (int j = 1; j <= I.M; ++j) {
+                            xp = xp + 1 == nx ? 0 : xp + 1;
+                            xm = xm == 0 ? nx - 1 : xm - 1;
+                            acc += I.cconv[j] * (f[row + xp] - f[row + xm]);
                         }
-                        bar(gg);
+                        return acc;
+                    };
+                    auto dy = [&](const double* f) {
+                        double acc = 0.0;
+                        int yp = y, ym = y;
+                        for (int j = 1; j <= I.M; ++j) {
+                            yp = yp + 1 == ny ? 0 : yp + 1;
+                            ym = ym == 0 ? ny - 1 : ym - 1;
+                            acc += I.cconv[j] * (f[(long long)yp * nx + x] - f[(long long)ym * nx + x]);
+                        }
+                        return acc;
+                    };
+                    if (stage == 0) {
+                        I.grho[n] = dx(I.rho);
+                        I.grho[I.g.N + n] = dy(I.rho);
+                    } else if (stage == 1) {
+                        const double lp = dx(I.grho) + dy(I.grho + I.g.N);
+                        I.mu[n] = mu_bulk(I.rho[n], I.eos) - I.eos.kappa * lp;
+                    } else {
+                        I.gmu[n] = dx(I.mu);
+                        I.gmu[I.g.N + n] = dy(I.mu);
                     }
                 }
-                if (stage == 1) {
-                    for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
-                        const int ii = a.blk_inst[it];
-                        const BInst& I = a.inst[ii];
-                        if (a.st[ii].status != B_RUNNING || !is_compact(I.scheme)) continue;
-                        const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
-                        if (n < I.g.N) I.mu[n] = mu_bulk(I.rho[n], I.eos) - I.eos.kappa * I.lap[n];
-                    }
-                    bar(gg);
-                }
+                bar(gg);
             }
         }
         bar(gg);

@@ -65,6 +65,17 @@ SYMBOLS = {
     "lbm_batch_instance": (C.c_void_p, [C.c_void_p, C.c_int]),
     "lbm_batch_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_batch_free": (None, [C.c_void_p]),
+    "mlp_param_count": (C.c_int, []),
+    "mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mlp_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                               C.c_void_p]),
+    "mlp_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_float, C.c_float,
+                           C.c_float, C.c_float, C.c_void_p]),
+    "mlp_field": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), _P, C.c_double, C.c_double, C.c_double, C.c_double,
+                            C.POINTER(C.c_float), C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
+    "lbm_sum_scratch_bytes": (C.c_size_t, [C.c_long]),
+    "lbm_sum": (C.c_int, [C.c_void_p, C.c_long, C.c_void_p, _D, C.c_void_p]),
     "lbm_coexistence": (C.c_int, [_P, _D, _D]),
 }
 
@@ -320,15 +331,26 @@ class Batch:
         if code != LBM_OK:
             raise LbmError(code, lib().lbm_batch_last_error(self.h).decode())
 
-    def run(self, nsteps: int, check_every: int = 100, tol: float = 1e-10, chunk: int = 1000):
-        """Advance; returns (status[n], steps[n], U[n]) numpy arrays."""
+    def run(self, nsteps: int, check_every: int = 100, tol: float = 1e-10, chunk: int = 1000, progress=None):
+        """Advance; returns (status[n], steps[n], U[n]) numpy arrays.  With a
+        progress callback the run is issued chunk by chunk and the callback
+        receives (steps issued, status array) after each."""
         st = (C.c_int * self.n)()
         sp = (C.c_long * self.n)()
         um = (C.c_double * self.n)()
-        code = lib().lbm_batch_run(self.h, int(nsteps), int(check_every), float(tol), int(chunk), st, sp, um)
-        if code != LBM_OK:
-            raise LbmError(code, lib().lbm_batch_last_error(self.h).decode())
-        return np.array(st[:]), np.array(sp[:]), np.array(um[:])
+        done = 0
+        while True:
+            todo = nsteps - done if progress is None else min(chunk, nsteps - done)
+            code = lib().lbm_batch_run(self.h, int(todo), int(check_every), float(tol), int(chunk), st, sp, um)
+            if code != LBM_OK:
+                raise LbmError(code, lib().lbm_batch_last_error(self.h).decode())
+            done += todo
+            status = np.array(st[:])
+            if progress is not None:
+                progress(done, status)
+            if done >= nsteps or not (status == RUNNING).any():
+                break
+        return status, np.array(sp[:]), np.array(um[:])
 
     def instance(self, i: int):
         ctx = lib().lbm_batch_instance(self.h, int(i))

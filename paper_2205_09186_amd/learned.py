@@ -1,0 +1,324 @@
+"""Learned initial condition: a small network, trained by the library's FP32
+kernels on equilibrium droplet profiles produced by the batched sweep, proposes
+the equilibrium radial density profile and replaces the tanh start of Eq 26.
+
+Data: droplets (D2Q9) run by the batched kernel; from each, four rays (+x, -x,
++y, -y) from the centre give profiles rho(r); R_eq is where rho crosses the
+mean of its centre and edge values (linear interpolation); samples are
+(Tr, k, scheme id, r - R_eq) -> phi = (rho - rho_g^M)/(rho_l^M - rho_g^M) with
+the Maxwell densities.  Training: mean-squared error, Adam, on the GPU kernels
+(mlp_forward / mlp_loss_grad / mlp_backward / mlp_adam).  Use: the initial
+field comes from mlp_field with R chosen by bisection so that the total mass
+equals that of the tanh start; a non-finite or failed match falls back to tanh.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import inputs, lbm
+
+SCHEMES6 = [lbm.CD2, lbm.CD4, lbm.CD6, lbm.E4, lbm.E8, lbm.OCFDS4]
+# feature scaling: (Tr - 0.75) / 0.15, (k - 0.175) / 0.05, (scheme - 2.5) / 1.7,
+# distance / 10
+NORM = np.array([0.75, 1 / 0.15, 0.175, 1 / 0.05, 2.5, 1 / 1.7, 10.0], dtype=np.float32)
+
+
+def features(Tr, k, scheme):
+    return np.array([(Tr - NORM[0]) * NORM[1], (k - NORM[2]) * NORM[3], (scheme - NORM[4]) * NORM[5]],
+                    dtype=np.float32)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _progress(tag):
+    def cb(done, status):
+        log(f"{tag}: {done} steps, running {(status == 0).sum()}, converged {(status == 1).sum()}, "
+            f"diverged {(status == 2).sum()}")
+    return cb
+
+
+class Net:
+    """Network parameters and Adam moments on the device (torch float32)."""
+
+    def __init__(self, seed: int = 0, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.P = int(lbm.lib().mlp_param_count())
+        self.params = torch.from_numpy(self.init_params(seed)).to(self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.stream = torch.cuda.current_stream(self.device)
+
+    @staticmethod
+    def init_params(seed: int) -> np.ndarray:
+        rng = np.random.default_rng(inputs.SEED_BASE + 1000 + seed)
+        sizes = [4, 64, 64, 64, 1]
+        parts = []
+        for i in range(4):
+            fi, fo = sizes[i], sizes[i + 1]
+            lim = np.sqrt(6.0 / fi) * (0.5 if i == 3 else 1.0)
+            parts.append(rng.uniform(-lim, lim, fo * fi))
+            parts.append(np.zeros(fo))
+        return np.concatenate(parts).astype(np.float32)
+
+    def forward(self, X, acts=None):
+        t = self.torch
+        B = X.shape[0]
+        y = t.empty(B, dtype=t.float32, device=self.device)
+        lbm._check(lbm.lib().mlp_forward(_ptr(self.params), _ptr(X), B, _ptr(y),
+                                         _ptr(acts) if acts is not None else None, C.c_void_p(self.stream.cuda_stream)))
+        return y
+
+    def grad(self, X, T):
+        """(loss, gradient) of the mean-squared error on (X, T), all on the device."""
+        t = self.torch
+        B = X.shape[0]
+        nb = (B + 63) // 64
+        acts = t.empty(B * 192, dtype=t.float32, device=self.device)
+        y = self.forward(X, acts)
+        dy = t.empty(B, dtype=t.float32, device=self.device)
+        lp = t.empty(nb, dtype=t.float32, device=self.device)
+        g = t.empty(self.P, dtype=t.float32, device=self.device)
+        gp = t.empty(nb * self.P, dtype=t.float32, device=self.device)
+        s = C.c_void_p(self.stream.cuda_stream)
+        lbm._check(lbm.lib().mlp_loss_grad(_ptr(y), _ptr(T), B, _ptr(dy), _ptr(lp), s))
+        lbm._check(lbm.lib().mlp_backward(_ptr(self.params), _ptr(X), _ptr(acts), _ptr(dy), B, _ptr(g), _ptr(gp), s))
+        return lp, g
+
+    def adam(self, g, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.t += 1
+        lbm._check(lbm.lib().mlp_adam(_ptr(self.params), _ptr(g), _ptr(self.m), _ptr(self.v), self.t, lr, b1, b2, eps,
+                                      C.c_void_p(self.stream.cuda_stream)))
+
+    def train(self, X, T, iters=3000, batch=4096, lr=2e-3, seed=0, log_every=500):
+        """Minibatch Adam on device data X (n, 4), T (n,)."""
+        t = self.torch
+        rng = np.random.default_rng(inputs.SEED_BASE + 2000 + seed)
+        n = X.shape[0]
+        hist = []
+        for it in range(1, iters + 1):
+            idx = t.from_numpy(rng.integers(0, n, batch)).to(self.device)
+            xb, tb = X.index_select(0, idx).contiguous(), T.index_select(0, idx).contiguous()
+            lr_t = lr * (0.1 ** (it / iters))
+            lp, g = self.grad(xb, tb)
+            self.adam(g, lr=lr_t)
+            if it % log_every == 0 or it == iters:
+                hist.append((it, float(lp.sum().item()) / batch))
+                log(f"train {it}/{iters} loss {hist[-1][1]:.3e}")
+        return hist
+
+    def field(self, p: lbm.Params, R, Tr, k, scheme, rho_g, rho_l, center=None):
+        """Initial density of the whole grid (device float64 tensor)."""
+        t = self.torch
+        out = t.empty(p.n, dtype=t.float64, device=self.device)
+        c = center or (p.nx // 2, p.ny // 2, p.nz // 2 if p.lattice == lbm.D3Q19 else 0)
+        norm = (C.c_float * 7)(*NORM.tolist())
+        feat = (C.c_float * 3)(*features(Tr, k, scheme).tolist())
+        cp = p.c()
+        lbm._check(lbm.lib().mlp_field(_ptr(self.params), norm, C.byref(cp), float(c[0]), float(c[1]), float(c[2]),
+                                       float(R), feat, float(rho_g), float(rho_l), _ptr(out),
+                                       C.c_void_p(self.stream.cuda_stream)))
+        return out
+
+    def state(self):
+        return self.params.cpu().numpy()
+
+    def load(self, arr):
+        self.params.copy_(self.torch.from_numpy(np.asarray(arr, dtype=np.float32)).to(self.device))
+
+
+def device_sum(x) -> float:
+    import torch
+    n = x.numel()
+    scratch = torch.empty(int(lbm.lib().lbm_sum_scratch_bytes(n)) // 8 + 1, dtype=torch.float64, device=x.device)
+    s = C.c_double()
+    lbm._check(lbm.lib().lbm_sum(_ptr(x), n, _ptr(scratch), C.byref(s),
+                                 C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)))
+    return s.value
+
+
+def mass_matched_field(net: Net, p: lbm.Params, R0, Tr, k, scheme, rho_g, rho_l, target_mass, iters=60):
+    """Bisection on the radius so that the learned field has the target mass.
+    Returns (rho0 device tensor or None, radius)."""
+    lo, hi = 0.25 * R0, min(p.nx, p.ny) * 0.5
+    f_lo = device_sum(net.field(p, lo, Tr, k, scheme, rho_g, rho_l)) - target_mass
+    f_hi = device_sum(net.field(p, hi, Tr, k, scheme, rho_g, rho_l)) - target_mass
+    if not (np.isfinite(f_lo) and np.isfinite(f_hi)) or f_lo > 0 or f_hi < 0:
+        return None, R0
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        fm = device_sum(net.field(p, mid, Tr, k, scheme, rho_g, rho_l)) - target_mass
+        if fm < 0:
+            lo = mid
+        else:
+            hi = mid
+    R = 0.5 * (lo + hi)
+    rho = net.field(p, R, Tr, k, scheme, rho_g, rho_l)
+    # the last bit of mass (discrete radius steps) goes into a uniform scaling
+    m = device_sum(rho)
+    rho.mul_(target_mass / m)
+    return rho, R
+
+
+# Under the SRT collision the second-order and isotropic schemes are stable
+# only near the critical point; each scheme draws its temperature from the
+# range where it runs.
+STABLE_TR = {lbm.CD2: (0.9, 0.95), lbm.E4: (0.9, 0.95), lbm.E8: (0.9, 0.95)}
+
+
+def droplet_set(n, seed, r_range=(12.0, 50.0), tr_range=(0.6, 0.9), k_range=(0.1, 0.25), lmax=256):
+    rng = np.random.default_rng(inputs.SEED_BASE + 3000 + seed)
+    out = []
+    for i in range(n):
+        R = float(rng.uniform(*r_range))
+        lo = max(64, int(np.ceil((2 * R + 64) / 8.0)) * 8)
+        L = int(rng.integers(lo // 8, max(lo, lmax) // 8 + 1)) * 8
+        sch = SCHEMES6[int(rng.integers(0, 6))]
+        tr = STABLE_TR.get(sch, tr_range)
+        out.append(dict(L=L, R=R, Tr=float(rng.uniform(*tr)), k=float(rng.uniform(*k_range)),
+                        scheme=sch, instance_id=10000 + 1000 * seed + i))
+    return out
+
+
+def _tanh_batch(specs, width=10.0, kappa=0.004):
+    ps, rs = [], []
+    for d in specs:
+        g, l = lbm.coexistence(d["Tr"])
+        ps.append(lbm.Params(lattice=lbm.D2Q9, nx=d["L"], ny=d["L"], Tr=d["Tr"], k=d["k"], kappa=kappa,
+                             scheme=d["scheme"]))
+        rs.append(inputs.droplet((d["L"], d["L"]), d["R"], width, g, l, instance_id=d["instance_id"], relative=True))
+    return ps, rs
+
+
+def profiles(batch_views, specs):
+    """Samples (features..., distance) -> phi from the rays of each droplet."""
+    X, T = [], []
+    for v, d in zip(batch_views, specs):
+        r = v.macros()[0]
+        L = d["L"]
+        c = L // 2
+        g, l = lbm.coexistence(d["Tr"])
+        f = features(d["Tr"], d["k"], d["scheme"])
+        rays = [r[c, c:], r[c, c::-1], r[c:, c], r[c::-1, c]]
+        for ray in rays:
+            ray = np.asarray(ray[: L // 2])
+            mid = 0.5 * (ray[0] + ray[-1])
+            below = np.nonzero(ray < mid)[0]
+            if below.size == 0 or below[0] == 0:
+                continue
+            j = below[0]
+            Req = (j - 1) + (ray[j - 1] - mid) / (ray[j - 1] - ray[j])
+            dist = (np.arange(ray.size) - Req) / NORM[6]
+            phi = (ray - g) / (l - g)
+            X.append(np.column_stack([np.tile(f, (ray.size, 1)), dist]))
+            T.append(phi)
+    return np.concatenate(X).astype(np.float32), np.concatenate(T).astype(np.float32)
+
+
+def make_dataset(n_batches=5, per_batch=96, steps=6000, seed=0):
+    X, T, nprof, status = [], [], 0, []
+    for bi in range(n_batches):
+        specs = droplet_set(per_batch, seed * 100 + bi, r_range=(12.0, 50.0), tr_range=(0.6, 0.95), lmax=160)
+        ps, rs = _tanh_batch(specs)
+        b = lbm.Batch(ps, rs)
+        st, _, _ = b.run(steps, check_every=100, tol=1e-10, chunk=2000, progress=_progress(f"data batch {bi}"))
+        ok = [i for i in range(len(specs)) if st[i] != lbm.DIVERGED]
+        status += list(st)
+        x, t = profiles([b.instance(i) for i in ok], [specs[i] for i in ok])
+        X.append(x); T.append(t)
+        nprof += 4 * len(ok)
+        b.close()
+    return np.concatenate(X), np.concatenate(T), nprof, status
+
+
+def evaluate(net: Net, n=64, seed=7, max_steps=30000, check_every=100, tol=1e-10, chunk=2000):
+    """Held-out droplets from the tanh start and from the learned start (same
+    mass); steps to |U(t) - U(t-100)| < tol and the final state of both."""
+    import torch
+    specs = droplet_set(n, 50 + seed)
+    ps, rs = _tanh_batch(specs)
+    learned, fallback = [], 0
+    log(f"eval: building {len(specs)} learned initial states")
+    for p, r, d in zip(ps, rs, specs):
+        g, l = lbm.coexistence(d["Tr"])
+        rho, _ = mass_matched_field(net, p, d["R"], d["Tr"], d["k"], d["scheme"], g, l, float(r.sum()))
+        if rho is None or not bool(torch.isfinite(rho).all()):
+            fallback += 1
+            learned.append(r)
+        else:
+            learned.append(rho.cpu().numpy().reshape(r.shape))
+    out = {}
+    for name, rhos in (("tanh", rs), ("learned", learned)):
+        b = lbm.Batch(ps, rhos)
+        t0 = time.perf_counter()
+        st, steps, U = b.run(max_steps, check_every=check_every, tol=tol, chunk=chunk, progress=_progress(name))
+        wall = time.perf_counter() - t0
+        dens = []
+        for i, d in enumerate(specs):
+            if st[i] == lbm.DIVERGED:
+                dens.append((np.nan, np.nan))
+                continue
+            rr = b.instance(i).macros()[0]
+            dens.append((float(rr[d["L"] // 2, d["L"] // 2]), float(rr[0, 0])))
+        out[name] = dict(status=st.tolist(), steps=steps.tolist(), U=U.tolist(), dens=dens, wall_s=wall)
+        b.close()
+    both = [i for i in range(n) if out["tanh"]["status"][i] == lbm.CONVERGED and
+            out["learned"]["status"][i] == lbm.CONVERGED]
+    ratio = [out["learned"]["steps"][i] / out["tanh"]["steps"][i] for i in both]
+    du = [abs(out["learned"]["U"][i] - out["tanh"]["U"][i]) / max(abs(out["tanh"]["U"][i]), 1e-300) for i in both]
+    dl = [abs(out["learned"]["dens"][i][0] - out["tanh"]["dens"][i][0]) / out["tanh"]["dens"][i][0] for i in both]
+    dg = [abs(out["learned"]["dens"][i][1] - out["tanh"]["dens"][i][1]) / out["tanh"]["dens"][i][1] for i in both]
+    summary = dict(n=n, fallback=fallback, both_converged=len(both),
+                   steps_ratio_median=float(np.median(ratio)) if ratio else None,
+                   steps_ratio_quartiles=[float(np.percentile(ratio, q)) for q in (25, 75)] if ratio else None,
+                   learned_fewer_steps=int(sum(1 for x in ratio if x < 1)),
+                   U_reldiff_max=float(max(du)) if du else None, rho_l_reldiff_max=float(max(dl)) if dl else None,
+                   rho_g_reldiff_max=float(max(dg)) if dg else None,
+                   tanh_counts={k: out["tanh"]["status"].count(v) for k, v in
+                                (("running", 0), ("converged", 1), ("diverged", 2))},
+                   learned_counts={k: out["learned"]["status"].count(v) for k, v in
+                                   (("running", 0), ("converged", 1), ("diverged", 2))})
+    return summary, out
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--batches", type=int, default=5)
+    ap.add_argument("--data-steps", type=int, default=6000)
+    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--eval", type=int, default=64)
+    ap.add_argument("--max-steps", type=int, default=30000)
+    ap.add_argument("--save", default="")
+    a = ap.parse_args()
+    t0 = time.perf_counter()
+    X, T, nprof, st = make_dataset(a.batches, steps=a.data_steps)
+    t1 = time.perf_counter()
+    import torch
+    net = Net(0)
+    hist = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), iters=a.iters)
+    t2 = time.perf_counter()
+    summary, _ = evaluate(net, n=a.eval, max_steps=a.max_steps)
+    t3 = time.perf_counter()
+    if a.save:
+        np.save(a.save, net.state())
+    print(json.dumps(dict(profiles=nprof, samples=int(X.shape[0]), data_diverged=int(sum(1 for s in st if s == 2)),
+                          train_history=hist, eval=summary,
+                          seconds=dict(data=t1 - t0, train=t2 - t1, eval=t3 - t2))))
+
+
+if __name__ == "__main__":
+    main()

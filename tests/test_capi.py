@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_symbols():
     text = open(os.path.join(ROOT, "include", "lbm.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:lbm|mlp)_[a-z_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():

@@ -1,0 +1,103 @@
+"""FP32 network kernels of the learned initialiser against the FP64 CPU
+reference (forward, backpropagated gradients, Adam, field inference)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_09186_amd import lbm, learned
+    from oracle import mlp
+    lbm.lib()
+    return torch, lbm, learned, mlp
+
+
+def _data(B, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((B, 4)).astype(np.float32)
+    T = rng.uniform(0, 1, B).astype(np.float32)
+    return X, T
+
+
+def test_forward_matches_reference(env):
+    torch, lbm, learned, mlp = env
+    net = learned.Net(1)
+    theta = net.state().astype(np.float64)
+    X, _ = _data(1000, 0)
+    y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    yr, _ = mlp.forward(theta, X.astype(np.float64))
+    assert np.abs(y - yr).max() <= 1e-5 * (1 + np.abs(yr).max())
+
+
+@pytest.mark.parametrize("B", [64, 200, 4096])
+def test_gradient_matches_fp64_backprop(env, B):
+    torch, lbm, learned, mlp = env
+    net = learned.Net(2)
+    theta = net.state().astype(np.float64)
+    X, T = _data(B, B)
+    lp, g = net.grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    gr = mlp.grad(theta, X.astype(np.float64), T.astype(np.float64))
+    assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
+    # per-layer norms too (a wrong small layer would hide in the total)
+    offs = [0, 256, 320, 4416, 4480, 8576, 8640, 8704, 8705]
+    for a, b in zip(offs[:-1], offs[1:]):
+        assert np.linalg.norm(g[a:b] - gr[a:b]) <= 1e-4 * np.linalg.norm(gr[a:b]) + 1e-7, (a, b)
+    assert float(lp.sum().item()) / B == pytest.approx(mlp.loss(theta, X.astype(np.float64), T.astype(np.float64)),
+                                                       rel=1e-5)
+    # deterministic reduction
+    _, g2 = net.grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    assert np.array_equal(g2.cpu().numpy(), g.astype(np.float32))
+
+
+def test_adam_step(env):
+    torch, lbm, learned, mlp = env
+    net = learned.Net(3)
+    p0 = net.state().astype(np.float64)
+    rng = np.random.default_rng(5)
+    m = np.zeros_like(p0); v = np.zeros_like(p0); p = p0.copy()
+    for step in range(1, 4):
+        g = rng.standard_normal(p0.size).astype(np.float32)
+        net.adam(torch.from_numpy(g).cuda(), lr=1e-2)
+        gd = g.astype(np.float64)
+        m = 0.9 * m + 0.1 * gd; v = 0.999 * v + 0.001 * gd * gd
+        p = p - 1e-2 * (m / (1 - 0.9 ** step)) / (np.sqrt(v / (1 - 0.999 ** step)) + 1e-8)
+    assert np.abs(net.state() - p).max() < 1e-5
+
+
+def test_field_inference_matches_reference(env):
+    torch, lbm, learned, mlp = env
+    net = learned.Net(4)
+    theta = net.state().astype(np.float64)
+    p = lbm.Params(lattice=lbm.D2Q9, nx=40, ny=30, Tr=0.8, k=0.2, scheme=lbm.CD6)
+    g, l = 0.2, 7.2
+    rho = net.field(p, 9.5, 0.8, 0.2, lbm.CD6, g, l).cpu().numpy().reshape(30, 40)
+    f = learned.features(0.8, 0.2, lbm.CD6)
+    ys, xs = np.mgrid[0:30, 0:40]
+    d = (np.sqrt((xs - 20.0) ** 2 + (ys - 15.0) ** 2) - 9.5) / learned.NORM[6]
+    X = np.column_stack([np.tile(f, (d.size, 1)), d.ravel()]).astype(np.float32)
+    y, _ = mlp.forward(theta, X.astype(np.float64))
+    ref = g + np.clip(y, 0, 1) * (l - g)
+    assert np.abs(rho.ravel() - ref).max() < 1e-4
+
+
+def test_training_reduces_loss(env):
+    torch, lbm, learned, mlp = env
+    rng = np.random.default_rng(9)
+    n = 20000
+    Tr = rng.uniform(0.6, 0.95, n); k = rng.uniform(0.1, 0.25, n); s = rng.integers(0, 6, n)
+    d = rng.uniform(-3, 3, n)
+    width = 0.5 + 2.0 * (0.95 - Tr)                    # a smooth synthetic target family
+    t = 0.5 - 0.5 * np.tanh(2.0 * d / width)
+    X = np.column_stack([(Tr - 0.75) / 0.15, (k - 0.175) / 0.05, (s - 2.5) / 1.7, d]).astype(np.float32)
+    net = learned.Net(0)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(t.astype(np.float32)).cuda()
+    l0 = float(net.grad(Xd, Td)[0].sum().item()) / n
+    hist = net.train(Xd, Td, iters=600, batch=2048, lr=3e-3, log_every=100)
+    l1 = float(net.grad(Xd, Td)[0].sum().item()) / n
+    assert l1 < 0.02 * l0, (l0, l1, hist)
