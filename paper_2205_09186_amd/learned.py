@@ -215,9 +215,14 @@ def profiles(batch_views, specs):
         rays = [r[c, c:], r[c, c::-1], r[c:, c], r[c::-1, c]]
         for ray in rays:
             ray = np.asarray(ray[: L // 2])
+            # keep only droplets that are still droplets: liquid at the centre,
+            # gas at the edge (a small droplet can dissolve into the vapour)
+            phi0, phi1 = (ray[0] - g) / (l - g), (ray[-1] - g) / (l - g)
+            if not (phi0 > 0.8 and phi1 < 0.2):
+                continue
             mid = 0.5 * (ray[0] + ray[-1])
             below = np.nonzero(ray < mid)[0]
-            if below.size == 0 or below[0] == 0:
+            if below.size == 0 or below[0] < 4:
                 continue
             j = below[0]
             Req = (j - 1) + (ray[j - 1] - mid) / (ray[j - 1] - ray[j])
@@ -303,15 +308,25 @@ def main():
     ap.add_argument("--eval", type=int, default=64)
     ap.add_argument("--max-steps", type=int, default=30000)
     ap.add_argument("--save", default="")
+    ap.add_argument("--dump", default="", help="directory for the dataset and per-instance results")
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--batch", type=int, default=4096)
     a = ap.parse_args()
     t0 = time.perf_counter()
     X, T, nprof, st = make_dataset(a.batches, steps=a.data_steps)
     t1 = time.perf_counter()
+    import os
     import torch
+    if a.dump:
+        os.makedirs(a.dump, exist_ok=True)
+        np.save(os.path.join(a.dump, "X.npy"), X)
+        np.save(os.path.join(a.dump, "T.npy"), T)
     net = Net(0)
-    hist = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), iters=a.iters)
+    hist = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), iters=a.iters, lr=a.lr, batch=a.batch)
     t2 = time.perf_counter()
-    summary, _ = evaluate(net, n=a.eval, max_steps=a.max_steps)
+    summary, full = evaluate(net, n=a.eval, max_steps=a.max_steps)
+    if a.dump:
+        json.dump(full, open(os.path.join(a.dump, "eval_full.json"), "w"))
     t3 = time.perf_counter()
     if a.save:
         np.save(a.save, net.state())
