@@ -85,7 +85,7 @@ __device__ void b_moments(const BInst& I, const double* S, long long n, int x, i
     r = jx = jy = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        f[i] = S[(long long)i * I.g.N + nb.at(-L::ex(i), -L::ey(i), 0)];
+        f[i] = S[(long long)i * I.g.ps + nb.at(-L::ex(i), -L::ey(i), 0)];
         r += f[i];
         jx += L::ex(i) * f[i];
         jy += L::ey(i) * f[i];
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
                 b_force_any(I, n, x, y, r, Fx, Fy, Fz);
                 collide<0>(f, r, jx, jy, 0.0, Fx, Fy, Fz, I.one_m_omega, out);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) Sn[(long long)i * I.g.N + n] = out[i];
+                for (int i = 0; i < 9; ++i) Sn[(long long)i * I.g.ps + n] = out[i];
             }
         }
         bar(gg);

@@ -31,6 +31,15 @@ struct TileGeom {
     int ntx, nty, nsz;   // tiles along x, y and z segments
 };
 
+inline TileGeom fused_tiles(int ty, const Grid& g, bool three_d)
+{
+    TileGeom t;
+    t.ntx = (g.nx + FX - 1) / FX;
+    t.nty = (g.ny + ty - 1) / ty;
+    t.nsz = three_d ? (g.nz + FZ - 1) / FZ : 1;
+    return t;
+}
+
 // LDS slot of direction i for the post-collision exchange (-1: direction with
 // no in-plane shift, kept in registers).  D2Q9: the eight moving directions;
 // D3Q19: all but the rest and the two pure z links (i = 5, 6).
@@ -38,6 +47,19 @@ template <int LAT>
 __host__ __device__ constexpr int xcls_of(int i)
 {
     return LAT == 0 ? i - 1 : (i == 0 || i == 5 || i == 6) ? -1 : (i <= 4 ? i - 1 : i - 3);
+}
+
+// Load / store at a 32-bit element index from a base pointer the whole
+// workgroup shares: the zero-extended byte offset lets the compiler use the
+// scalar-base + 32-bit vector-offset addressing form (one VGPR per access
+// instead of a 64-bit address).  Requires fewer than 2^29 nodes per buffer.
+__device__ __forceinline__ double ld32(const double* base, unsigned idx)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + (size_t)(idx * 8u));
+}
+__device__ __forceinline__ void st32(double* base, unsigned idx, double v)
+{
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (size_t)(idx * 8u)) = v;
 }
 
 __device__ __forceinline__ int pwrap(int a, int n)
@@ -51,7 +73,9 @@ __device__ __forceinline__ int pwrap(int a, int n)
 // plane of the march the workgroup stages rho and mu_hat of the plane (tile,
 // ring and an R-wide halo) in LDS for the in-plane stencil arms; the z arms
 // come from per-thread register queues of the thread's own column.
-template <int LAT, int SCH, int TY, int OCC, bool PIPE>
+// FULL: tau = 1 (one_m_omega == 0), where f* = feq(rho, u + du) exactly and
+// the pulled populations are dead once the moments are formed.
+template <int LAT, int SCH, int TY, int OCC, bool PIPE, bool FULL>
 __global__ void __launch_bounds__((FX + 2) * (TY + 2), OCC)
 k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ rho,
         const double* __restrict__ mu, double* __restrict__ rho_next, Grid g, TileGeom tg, double one_m_omega)
@@ -120,7 +144,7 @@ k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __r
             const int ox = L::ex(i) == 1 ? xm : L::ex(i) == -1 ? xp : x;
             const int oy = L::ey(i) == 1 ? ym : L::ey(i) == -1 ? yp : yc;
             const int oz = L::ez(i) == 1 ? zmo : L::ez(i) == -1 ? zpo : zo;
-            f[i] = S[(long long)i * N + (oz + oy + ox)];
+            f[i] = ld32(S + (long long)i * g.ps, (unsigned)(oz + oy + ox));
         }
     };
 
@@ -145,17 +169,17 @@ k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __r
         // stage the plane (tile + ring + R halo) of rho and mu_hat
         for (int idx = lid; idx < HR * WR; idx += NTH) {
             const int hy = idx / WR, hx = idx - hy * WR;
-            const int o = zo + pwrap(y0 - 1 - R + hy, ny) * nx + pwrap(x0 - 1 - R + hx, nx);
-            rp[idx] = rho[o];
-            mp[idx] = mu[o];
+            const unsigned o = (unsigned)(zo + pwrap(y0 - 1 - R + hy, ny) * nx + pwrap(x0 - 1 - R + hx, nx));
+            rp[idx] = ld32(rho, o);
+            mp[idx] = ld32(mu, o);
         }
         if constexpr (LAT == 1) {
 #pragma unroll
             for (int k = 0; k < QZ - 1; ++k) { qr[k] = qr[k + 1]; qm[k] = qm[k + 1]; }
             if (active) {
-                const int zz = pwrap(zr + R, nz) * nxy + yc + x;
-                qr[QZ - 1] = rho[zz];
-                qm[QZ - 1] = mu[zz];
+                const unsigned zz = (unsigned)(pwrap(zr + R, nz) * nxy + yc + x);
+                qr[QZ - 1] = ld32(rho, zz);
+                qm[QZ - 1] = ld32(mu, zz);
             }
         }
         __syncthreads();
@@ -201,8 +225,9 @@ k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __r
                 const double ev = L::ex(i) * vx + L::ey(i) * vy + L::ez(i) * vz;
                 const double fe = wr * (uu + eu * (3.0 + 4.5 * eu));
                 const double fv = wr * (vv + ev * (3.0 + 4.5 * ev));
-                const double o = fv + one_m_omega * (f[i] - fe);
-                if (store) Sn[(long long)i * N + n] = o;
+                const double o = FULL ? fv : fv + one_m_omega * (f[i] - fe);
+                (void)fe;
+                if (store) st32(Sn + (long long)i * g.ps, (unsigned)n, o);
                 if (xcls_of<LAT>(i) >= 0) xs[xcls_of<LAT>(i)][lid] = o;
                 else if (L::ez(i) == -1) own_m1 = o;
                 else if (L::ez(i) == 0) own_0 = o;
@@ -220,7 +245,7 @@ k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __r
             }
             if constexpr (LAT == 1) {
                 acc_m1 += a_m1;
-                if (zr - 1 >= z0 && zr - 1 < z1) rho_next[(zr - 1) * nxy + yc + x] = acc_m1;
+                if (zr - 1 >= z0 && zr - 1 < z1) st32(rho_next, (unsigned)((zr - 1) * nxy + yc + x), acc_m1);
                 acc_m1 = acc_0 + a_0;
                 acc_0 = a_p1;
             } else {
@@ -230,25 +255,351 @@ k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __r
     }
 }
 
-// The fused path covers the per-axis explicit schemes on grids whose node
-// count fits 32-bit offsets.
-template <int LAT, int SCH>
-inline bool fused_available(const Grid& g) { return (SCH == CD2 || SCH == CD4 || SCH == CD6) && g.N < (1LL << 31); }
+// ---------------------------------------------------------------------------
+// Stencil marches over 64 x 8 tiles for the per-axis explicit schemes.  Per
+// plane, the tile plus its R-wide in-plane halo of each input field is staged
+// in LDS (double-buffered: one barrier per plane); the z arms come from a
+// per-thread register queue of the own column.  The global loads of the next
+// plane are issued before the current plane is computed, so their latency
+// overlaps the barrier and the arithmetic.  Per node: one HBM read of each
+// input and one write of each output; the halo re-reads hit L2.
+//   NF = 1: mu_hat = k^2 psi'(rho) - kappa_hat lap(rho) (Eq 15, Eq 16), with
+//           the summation order of lap_at.
+//   NF = 2: F = -rho grad(mu_hat) + cs^2 grad(rho) (Eq 12), gradients summed
+//           as in grad_at; F stored as three (two in 2D) planes of N.
+// ---------------------------------------------------------------------------
+constexpr int MX = 64, MY = 8, MZ = 32;
 
-// Launch variants of the fused kernel (tile height, waves per SIMD the register
-// allocation must allow).  The tuner times them on the actual grid.
-struct FusedVariant { int ty, occ, pipe; };
-constexpr FusedVariant kFusedVariants[] = { {8, 2, 0}, {4, 3, 0}, {6, 3, 0}, {4, 2, 1}, {5, 2, 1}, {3, 2, 1} };
-constexpr int kNumFusedVariants = 6;
-
-inline TileGeom fused_tiles(int ty, const Grid& g, bool three_d)
+inline TileGeom march_tiles(const Grid& g, bool three_d)
 {
     TileGeom t;
-    t.ntx = (g.nx + FX - 1) / FX;
+    t.ntx = (g.nx + MX - 1) / MX;
+    t.nty = (g.ny + MY - 1) / MY;
+    t.nsz = three_d ? (g.nz + MZ - 1) / MZ : 1;
+    return t;
+}
+
+template <int DIM, int SCH, int NF>
+__global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rho, const double* __restrict__ mu,
+                                                   double* __restrict__ out, Grid g, TileGeom tg, Eos e)
+{
+    constexpr int R = radius(SCH);
+    constexpr int WR = MX + 2 * R, HR = MY + 2 * R, CELLS = WR * HR, NTH = MX * MY;
+    constexpr int SPT = (CELLS + NTH - 1) / NTH;
+    constexpr int QZ = DIM == 3 ? 2 * R + 1 : 1;
+    constexpr double cs2 = 1.0 / 3.0;
+    __shared__ double sp[2][NF][CELLS];
+
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nxy = (int)g.nxy;
+    const unsigned N = (unsigned)g.N;
+    int b = blockIdx.x;
+    {
+        const int nb = gridDim.x, per = nb / 8;
+        if (b < per * 8) b = (b % 8) * per + b / 8;
+    }
+    const int tx = b % tg.ntx;
+    const int ty = (b / tg.ntx) % tg.nty;
+    const int sz = b / (tg.ntx * tg.nty);
+    const int x0 = tx * MX, y0 = ty * MY;
+    const int lid = threadIdx.x;
+    const int lx = lid % MX, ly = lid / MX;
+    const bool in = lx < min(MX, nx - x0) && ly < min(MY, ny - y0);
+    const int col = in ? (y0 + ly) * nx + x0 + lx : 0;
+    const int z0 = DIM == 3 ? sz * MZ : 0;
+    const int z1 = DIM == 3 ? min(z0 + MZ, nz) : 1;
+    const int c0 = (ly + R) * WR + (lx + R);
+    const double* src[2] = { rho, mu };
+
+    // in-plane offsets of the staged cells this thread loads (fixed over the march)
+    unsigned off[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int idx = lid + k * NTH;
+        const int hy = idx / WR, hx = idx - hy * WR;
+        off[k] = idx < CELLS ? (unsigned)(pwrap(y0 - R + hy, ny) * nx + pwrap(x0 - R + hx, nx)) : 0u;
+    }
+    // z queues of the own column: index k <-> plane z-R+k
+    double q[NF][QZ];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int k = 0; k < QZ; ++k) q[f][k] = 0.0;
+    if constexpr (DIM == 3) {
+        if (in) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int k = 0; k < 2 * R; ++k) q[f][k + 1] = ld32(src[f], (unsigned)(pwrap(z0 - R + k, nz) * nxy + col));
+        }
+    }
+    double sv[NF][SPT], qn[NF];
+    auto fetch = [&](int z) {
+        const unsigned zo = (unsigned)(z * nxy);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int k = 0; k < SPT; ++k)
+                if (lid + k * NTH < CELLS) sv[f][k] = ld32(src[f], zo + off[k]);
+            if constexpr (DIM == 3) {
+                if (in) qn[f] = ld32(src[f], (unsigned)(pwrap(z + R, nz) * nxy + col));
+            }
+        }
+    };
+    fetch(z0);
+    for (int z = z0; z < z1; ++z) {
+        double (*s)[CELLS] = sp[(z - z0) & 1];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int k = 0; k < SPT; ++k)
+                if (lid + k * NTH < CELLS) s[f][lid + k * NTH] = sv[f][k];
+            if constexpr (DIM == 3) {
+#pragma unroll
+                for (int k = 0; k < QZ - 1; ++k) q[f][k] = q[f][k + 1];
+                q[f][QZ - 1] = qn[f];
+            }
+        }
+        if (z + 1 < z1) fetch(z + 1);
+        __syncthreads();
+        if (!in) continue;
+        const unsigned n = (unsigned)(z * nxy + col);
+        if constexpr (NF == 1) {
+            const double f0 = s[0][c0];
+            double acc = DIM * d2(SCH, 0) * f0;
+#pragma unroll
+            for (int m = 1; m <= R; ++m) {
+                const double c = d2(SCH, m);
+                acc += c * (s[0][c0 + m] + s[0][c0 - m]);
+                acc += c * (s[0][c0 + m * WR] + s[0][c0 - m * WR]);
+                if constexpr (DIM == 3) acc += c * (q[0][R + m] + q[0][R - m]);
+            }
+            st32(out, n, mu_bulk(f0, e) - e.kappa * acc);
+        } else {
+            double grx = 0.0, gry = 0.0, grz = 0.0, gmx = 0.0, gmy = 0.0, gmz = 0.0;
+#pragma unroll
+            for (int m = 1; m <= R; ++m) {
+                const double c = d1(SCH, m);
+                grx += c * (s[0][c0 + m] - s[0][c0 - m]);
+                gry += c * (s[0][c0 + m * WR] - s[0][c0 - m * WR]);
+                gmx += c * (s[1][c0 + m] - s[1][c0 - m]);
+                gmy += c * (s[1][c0 + m * WR] - s[1][c0 - m * WR]);
+                if constexpr (DIM == 3) {
+                    grz += c * (q[0][R + m] - q[0][R - m]);
+                    gmz += c * (q[1][R + m] - q[1][R - m]);
+                }
+            }
+            const double r = s[0][c0];
+            st32(out, n, -r * gmx + cs2 * grx);
+            st32(out + N, n, -r * gmy + cs2 * gry);
+            if constexpr (DIM == 3) st32(out + 2 * (size_t)N, n, -r * gmz + cs2 * grz);
+        }
+    }
+}
+
+template <int DIM, int SCH>
+inline void launch_mu_march(const double* rho, double* mu, const Grid& g, const Eos& e, hipStream_t st)
+{
+    const TileGeom t = march_tiles(g, DIM == 3);
+    const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
+    hipLaunchKernelGGL((k_march<DIM, SCH, 1>), dim3(nb), dim3(MX * MY), 0, st, rho, nullptr, mu, g, t, e);
+}
+
+template <int DIM, int SCH>
+inline void launch_force_march(const double* rho, const double* mu, double* F, const Grid& g, const Eos& e,
+                               hipStream_t st)
+{
+    const TileGeom t = march_tiles(g, DIM == 3);
+    const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
+    hipLaunchKernelGGL((k_march<DIM, SCH, 2>), dim3(nb), dim3(MX * MY), 0, st, rho, mu, F, g, t, e);
+}
+
+// ---------------------------------------------------------------------------
+// Ring collide with a precomputed force: the same tile + ring scheme as
+// k_fused, but the force field comes from k_march (three loads per node), so
+// the kernel holds no stencil state.  The next plane's pulls are issued right
+// after the gather of the current plane, overlapping the second barrier.
+// ---------------------------------------------------------------------------
+template <int LAT, int TX, int TY, int OCC, bool FULL>
+__global__ void __launch_bounds__((TX + 2) * (TY + 2), OCC)
+k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ F,
+       double* __restrict__ rho_next, Grid g, TileGeom tg, double one_m_omega)
+{
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q;
+    constexpr int W = TX + 2, H = TY + 2, NTH = W * H;
+    constexpr int NCL = LAT == 1 ? 16 : 8;
+    __shared__ double xs[NCL][NTH];
+
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nxy = (int)g.nxy, N = (int)g.N;
+    int b = blockIdx.x;
+    {
+        const int nb = gridDim.x, per = nb / 8;
+        if (b < per * 8) b = (b % 8) * per + b / 8;
+    }
+    const int tx = b % tg.ntx;
+    const int ty = (b / tg.ntx) % tg.nty;
+    const int sz = b / (tg.ntx * tg.nty);
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int wx = min(TX, nx - x0), wy = min(TY, ny - y0);
+    // Tile nodes first, one row of TX per TX lanes (rows start on wave
+    // boundaries when TX = 64, so the tile's loads and stores are aligned),
+    // then the ring: bottom row, top row, left column, right column.
+    const int lid = threadIdx.x;
+    int lx, ly;
+    if (lid < TX * TY) {
+        lx = 1 + lid % TX; ly = 1 + lid / TX;
+    } else {
+        const int r = lid - TX * TY;
+        if (r < W) { lx = r; ly = 0; }
+        else if (r < 2 * W) { lx = r - W; ly = H - 1; }
+        else if (r < 2 * W + TY) { lx = 0; ly = 1 + r - 2 * W; }
+        else { lx = W - 1; ly = 1 + r - 2 * W - TY; }
+    }
+    const int slot = ly * W + lx;   // LDS exchange position
+    const bool active = lx <= wx + 1 && ly <= wy + 1;
+    const bool inner = lx >= 1 && lx <= wx && ly >= 1 && ly <= wy;
+    const int x = active ? wrapc(x0 - 1 + lx, nx) : 0;
+    const int y = active ? wrapc(y0 - 1 + ly, ny) : 0;
+    const int xm = wrapc(x - 1, nx), xp = wrapc(x + 1, nx);
+    const int yc = y * nx, ym = wrapc(y - 1, ny) * nx, yp = wrapc(y + 1, ny) * nx;
+    const int z0 = LAT == 1 ? sz * FZ : 0;
+    const int z1 = LAT == 1 ? min(z0 + FZ, nz) : 1;
+
+    double f[Q], Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    auto pull_plane = [&](int z) {
+        const int zo = z * nxy;
+        const int zmo = LAT == 1 ? wrapc(z - 1, nz) * nxy : 0;
+        const int zpo = LAT == 1 ? wrapc(z + 1, nz) * nxy : 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ox = L::ex(i) == 1 ? xm : L::ex(i) == -1 ? xp : x;
+            const int oy = L::ey(i) == 1 ? ym : L::ey(i) == -1 ? yp : yc;
+            const int oz = L::ez(i) == 1 ? zmo : L::ez(i) == -1 ? zpo : zo;
+            f[i] = ld32(S + (long long)i * g.ps, (unsigned)(oz + oy + ox));
+        }
+        const unsigned n = (unsigned)(zo + yc + x);
+        Fx = ld32(F, n);
+        Fy = ld32(F + N, n);
+        if constexpr (LAT == 1) Fz = ld32(F + 2LL * N, n);
+    };
+
+    double acc_m1 = 0.0, acc_0 = 0.0;
+    const int zb = LAT == 1 ? z0 - 1 : 0, ze = LAT == 1 ? z1 : 0;
+    if (active) pull_plane(LAT == 1 ? pwrap(zb, nz) : 0);
+    for (int zr = zb; zr <= ze; ++zr) {
+        const int z = LAT == 1 ? pwrap(zr, nz) : 0;
+        double own_m1 = 0.0, own_0 = 0.0, own_p1 = 0.0;   // post-collision values without in-plane shift
+        if (active) {
+            double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                r += f[i];
+                jx += L::ex(i) * f[i]; jy += L::ey(i) * f[i]; jz += L::ez(i) * f[i];
+            }
+            // collision (Eq 1 SRT, Eq 6, Eq 8), each value stored as soon as formed
+            const double ir = 1.0 / r;
+            const double ux = jx * ir, uy = jy * ir, uz = jz * ir;
+            const double vx = ux + Fx * ir, vy = uy + Fy * ir, vz = uz + Fz * ir;
+            const double uu = 1.0 - 1.5 * (ux * ux + uy * uy + uz * uz);
+            const double vv = 1.0 - 1.5 * (vx * vx + vy * vy + vz * vz);
+            const bool store = inner && zr >= z0 && zr < z1;
+            const int n = z * nxy + yc + x;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double wr = L::w(i) * r;
+                const double ev = L::ex(i) * vx + L::ey(i) * vy + L::ez(i) * vz;
+                const double fv = wr * (vv + ev * (3.0 + 4.5 * ev));
+                double o = fv;
+                if constexpr (!FULL) {
+                    const double eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
+                    const double fe = wr * (uu + eu * (3.0 + 4.5 * eu));
+                    o = fv + one_m_omega * (f[i] - fe);
+                }
+                if (store) st32(Sn + (long long)i * g.ps, (unsigned)n, o);
+                if (xcls_of<LAT>(i) >= 0) xs[xcls_of<LAT>(i)][slot] = o;
+                else if (L::ez(i) == -1) own_m1 = o;
+                else if (L::ez(i) == 0) own_0 = o;
+                else own_p1 = o;
+            }
+        }
+        __syncthreads();
+        double a_m1 = own_m1, a_0 = own_0, a_p1 = own_p1;
+        if (inner) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (xcls_of<LAT>(i) < 0) continue;
+                const double v = xs[xcls_of<LAT>(i)][(ly - L::ey(i)) * W + (lx - L::ex(i))];
+                if (L::ez(i) == -1) a_m1 += v; else if (L::ez(i) == 0) a_0 += v; else a_p1 += v;
+            }
+        }
+        if (active && zr < ze) pull_plane(pwrap(zr + 1, nz));
+        __syncthreads();
+        if (inner) {
+            if constexpr (LAT == 1) {
+                acc_m1 += a_m1;
+                if (zr - 1 >= z0 && zr - 1 < z1) st32(rho_next, (unsigned)((zr - 1) * nxy + yc + x), acc_m1);
+                acc_m1 = acc_0 + a_0;
+                acc_0 = a_p1;
+            } else {
+                rho_next[yc + x] = a_0;
+            }
+        }
+    }
+}
+
+struct RingVariant { int tx, ty, occ; };
+constexpr RingVariant kRingVariants[] = { {64, 8, 3}, {32, 16, 2}, {32, 24, 1}, {32, 28, 1}, {48, 16, 1}, {64, 13, 2} };
+constexpr int kNumRingVariants = 6;
+
+inline TileGeom ring_tiles(int tx, int ty, const Grid& g, bool three_d)
+{
+    TileGeom t;
+    t.ntx = (g.nx + tx - 1) / tx;
     t.nty = (g.ny + ty - 1) / ty;
     t.nsz = three_d ? (g.nz + FZ - 1) / FZ : 1;
     return t;
 }
+
+template <int LAT, int TX, int TY, int OCC>
+inline void launch_ring_v(const double* S, double* Sn, const double* F, double* rho_next, const Grid& g,
+                          double one_m_omega, hipStream_t st)
+{
+    const TileGeom t = ring_tiles(TX, TY, g, LAT == 1);
+    const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
+    if (one_m_omega == 0.0)
+        hipLaunchKernelGGL((k_ring<LAT, TX, TY, OCC, true>), dim3(nb), dim3((TX + 2) * (TY + 2)), 0, st, S, Sn, F,
+                           rho_next, g, t, one_m_omega);
+    else
+        hipLaunchKernelGGL((k_ring<LAT, TX, TY, OCC, false>), dim3(nb), dim3((TX + 2) * (TY + 2)), 0, st, S, Sn, F,
+                           rho_next, g, t, one_m_omega);
+}
+
+template <int LAT>
+inline void launch_ring_collide(int variant, const double* S, double* Sn, const double* F, double* rho_next,
+                                const Grid& g, double one_m_omega, hipStream_t st)
+{
+    switch (variant) {
+    case 1: launch_ring_v<LAT, 32, 16, 2>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 2: launch_ring_v<LAT, 32, 24, 1>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 3: launch_ring_v<LAT, 32, 28, 1>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 4: launch_ring_v<LAT, 48, 16, 1>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 5: launch_ring_v<LAT, 64, 13, 2>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    default: launch_ring_v<LAT, 64, 8, 3>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    }
+}
+
+// The fused path covers the per-axis explicit schemes on grids whose node
+// count fits 32-bit offsets.
+template <int LAT, int SCH>
+inline bool fused_available(const Grid& g) { return (SCH == CD2 || SCH == CD4 || SCH == CD6) && g.N < (1LL << 29); }
+
+// Launch variants of the fused kernel (tile height, waves per SIMD the register
+// allocation must allow).  The tuner times them on the actual grid.
+struct FusedVariant { int ty, occ, pipe; };
+constexpr FusedVariant kFusedVariants[] = { {8, 2, 0}, {4, 3, 0}, {6, 3, 0}, {4, 2, 1}, {5, 2, 1}, {3, 2, 1}, {4, 4, 0} };
+constexpr int kNumFusedVariants = 7;
 
 template <int LAT, int SCH, int TY, int OCC, bool PIPE>
 inline void launch_fused_v(const double* S, double* Sn, const double* rho, const double* mu, double* rho_next,
@@ -256,8 +607,12 @@ inline void launch_fused_v(const double* S, double* Sn, const double* rho, const
 {
     const TileGeom t = fused_tiles(TY, g, LAT == 1);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
-    hipLaunchKernelGGL((k_fused<LAT, SCH, TY, OCC, PIPE>), dim3(nb), dim3((FX + 2) * (TY + 2)), 0, st, S, Sn, rho, mu,
-                       rho_next, g, t, one_m_omega);
+    if (one_m_omega == 0.0)
+        hipLaunchKernelGGL((k_fused<LAT, SCH, TY, OCC, PIPE, true>), dim3(nb), dim3((FX + 2) * (TY + 2)), 0, st, S,
+                           Sn, rho, mu, rho_next, g, t, one_m_omega);
+    else
+        hipLaunchKernelGGL((k_fused<LAT, SCH, TY, OCC, PIPE, false>), dim3(nb), dim3((FX + 2) * (TY + 2)), 0, st, S,
+                           Sn, rho, mu, rho_next, g, t, one_m_omega);
 }
 
 template <int LAT, int SCH>
@@ -270,6 +625,7 @@ inline void launch_fused_collide(int variant, const double* S, double* Sn, const
     case 3: launch_fused_v<LAT, SCH, 4, 2, true>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
     case 4: launch_fused_v<LAT, SCH, 5, 2, true>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
     case 5: launch_fused_v<LAT, SCH, 3, 2, true>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
+    case 6: launch_fused_v<LAT, SCH, 4, 4, false>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
     default: launch_fused_v<LAT, SCH, 8, 2, false>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
     }
 }

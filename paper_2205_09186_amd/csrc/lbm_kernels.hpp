@@ -13,6 +13,7 @@ struct Grid {
     int nx, ny, nz;
     long long N;     // nx*ny*nz
     long long nxy;   // nx*ny
+    long long ps;    // element stride between population arrays (>= N)
 };
 
 __device__ __forceinline__ int wrapc(int a, int n)
@@ -135,7 +136,7 @@ __global__ void __launch_bounds__(256) k_init(const double* __restrict__ rho0, d
     Nbr<1, L::DIM> nb(x, y, z, g);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        S[(long long)i * g.N + n] = L::w(i) * rho0[nb.at(L::ex(i), L::ey(i), L::ez(i))];
+        S[(long long)i * g.ps + n] = L::w(i) * rho0[nb.at(L::ex(i), L::ey(i), L::ez(i))];
 }
 
 // Pull the Q populations of node n: f_i(x) = S_i(x - e_i).
@@ -147,7 +148,7 @@ __device__ __forceinline__ void pull(const double* __restrict__ S, const Grid& g
     (void)n;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        f[i] = S[(long long)i * g.N + nb.at(-L::ex(i), -L::ey(i), -L::ez(i))];
+        f[i] = S[(long long)i * g.ps + nb.at(-L::ex(i), -L::ey(i), -L::ez(i))];
 }
 
 // Post-streaming populations of the stored state, f_i(x) = S_i(x - e_i).
@@ -254,7 +255,7 @@ __global__ void __launch_bounds__(256) k_collide(const double* __restrict__ S, d
     force_at<LAT, SCH>(rho_f, mu_f, grho, gmu, g, n, x, y, z, r, Fx, Fy, Fz);
     collide<LAT>(f, r, jx, jy, jz, Fx, Fy, Fz, one_m_omega, out);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) Sn[(long long)i * g.N + n] = out[i];
+    for (int i = 0; i < L::Q; ++i) Sn[(long long)i * g.ps + n] = out[i];
 }
 
 // NaN-propagating maximum.

@@ -92,6 +92,17 @@ def test_small_3d_all_schemes(L, orc, scheme):
     _compare(sim, o)
 
 
+@pytest.mark.parametrize("lat,shape,scheme,tau", [(1, (18, 20, 22), "CD6", 0.8), (1, (20, 17, 24), "CD4", 1.3),
+                                                   (0, (45, 70), "CD6", 0.75), (0, (45, 70), "E8", 1.2),
+                                                   (1, (16, 18, 20), "OCFDS4", 0.9)])
+def test_relaxation_time_not_one(L, orc, lat, shape, scheme, tau):
+    """tau != 1 keeps the (1 - 1/tau)(f - feq) term of the collision, which
+    tau = 1 drops exactly; both forms against the oracle."""
+    R = 6 if lat == 1 else 12
+    sim, o = _run_pair(L, orc, lat, shape, L.SCHEMES[scheme], 60, Tr=0.9, W=4.0, R=R, tau=tau)
+    _compare(sim, o)
+
+
 def test_slab_thin_axis(L, orc):
     """8 x H slabs (the batched sweep's shape) with the widest explicit stencil."""
     g, l = orc.maxwell(0.7)
@@ -144,10 +155,11 @@ def test_deterministic_repeat(L, orc):
     assert a.spurious_max()[:2] == b.spurious_max()[:2]
 
 
+@pytest.mark.parametrize("variant", [0, -1])
 @pytest.mark.parametrize("lat,shape,scheme", [(0, (70, 130), "CD6"), (0, (45, 64), "CD4"), (0, (8, 200), "CD2"),
                                               (1, (33, 20, 70), "CD6"), (1, (10, 13, 9), "CD4"),
                                               (1, (40, 8, 66), "CD2"), (1, (70, 4, 5), "CD6")])
-def test_fused_equals_unfused(L, orc, lat, shape, scheme, monkeypatch):
+def test_fused_equals_unfused(L, orc, lat, shape, scheme, variant, monkeypatch):
     """The fused collide kernel (tile + recomputed ring, LDS exchange for the
     next density) against the plain node-parallel kernels: same state to
     rounding, on grids with ragged tiles in every direction."""
@@ -156,6 +168,7 @@ def test_fused_equals_unfused(L, orc, lat, shape, scheme, monkeypatch):
     nz, ny, nx = ((1,) + shape) if lat == 0 else shape
     p = L.Params(lattice=lat, nx=nx, ny=ny, nz=nz, Tr=0.9, scheme=L.SCHEMES[scheme])
     a = L.Simulation(p, rho0)
+    a.set_variant(variant % a.num_variants)
     monkeypatch.setenv("LBM_NO_FUSED", "1")
     b = L.Simulation(p, rho0)
     monkeypatch.delenv("LBM_NO_FUSED")
@@ -170,30 +183,35 @@ def test_step_timed_phases(L, orc):
     p = L.Params(lattice=1, nx=24, ny=24, nz=24, Tr=0.8, scheme=L.CD4)
     s = L.Simulation(p, rho0)
     ph = s.step_timed(3)
-    assert [n for n, _ in ph] == ["k_mu", "k_fused"]
+    assert [n for n, _ in ph] == ["k_mu_march", "k_force_march", "k_ring"]
     assert all(t > 0 for _, t in ph)
     assert s.steps_done == 3
 
 
-@pytest.mark.parametrize("lat,shape", [(1, (37, 21, 70)), (0, (50, 131))])
-def test_launch_variants_identical(L, orc, lat, shape):
-    """Every launch variant of the fused step (tile height, register budget)
-    computes the same node arithmetic in the same order: bitwise equal."""
+@pytest.mark.parametrize("lat,shape,tau", [(1, (37, 21, 70), 1.0), (0, (50, 131), 1.0), (1, (37, 21, 70), 0.85)])
+def test_launch_variants_identical(L, orc, lat, shape, tau):
+    """Launch variants of one kernel design (tile height, register budget)
+    compute the same node arithmetic in the same order: bitwise equal.  The
+    designs differ only in where the force is formed (inside the collide
+    kernel or in its own pass), which moves rounding only."""
     g, l = orc.maxwell(0.8)
     rho0 = inputs.droplet(shape, min(shape) / 4, 4.0, g, l)
     nz, ny, nx = ((1,) + shape) if lat == 0 else shape
-    p = L.Params(lattice=lat, nx=nx, ny=ny, nz=nz, Tr=0.8, scheme=L.CD6)
-    ref = None
+    p = L.Params(lattice=lat, nx=nx, ny=ny, nz=nz, Tr=0.8, scheme=L.CD6, tau=tau)
+    ref = {}
     for v in range(L.Simulation(p, rho0).num_variants):
         s = L.Simulation(p, rho0)
         s.set_variant(v)
-        s.step(7)
+        design = tuple(n for n, _ in s.step_timed(1))
+        s.step(6)
         f = s.populations()
-        if ref is None:
-            ref = f
+        if design not in ref:
+            ref[design] = f
         else:
-            assert np.array_equal(f, ref), v
-    assert ref is not None
+            assert np.array_equal(f, ref[design]), (v, design)
+    assert len(ref) == 2, list(ref)
+    a, b = ref.values()
+    assert np.abs(a - b).max() < 1e-13
 
 
 @pytest.mark.parametrize("lat,shape,scheme", [(0, (100, 100), "CD4"), (1, (20, 24, 28), "CD6"),
