@@ -29,6 +29,7 @@ constexpr int FTH2 = (FX + 2) * (FY2 + 2);   // 396 threads
 
 struct TileGeom {
     int ntx, nty, nsz;   // tiles along x, y and z segments
+    int mz;              // planes per z segment (marching stencil kernels)
 };
 
 inline TileGeom fused_tiles(int ty, const Grid& g, bool three_d)
@@ -37,6 +38,7 @@ inline TileGeom fused_tiles(int ty, const Grid& g, bool three_d)
     t.ntx = (g.nx + FX - 1) / FX;
     t.nty = (g.ny + ty - 1) / ty;
     t.nsz = three_d ? (g.nz + FZ - 1) / FZ : 1;
+    t.mz = FZ;
     return t;
 }
 
@@ -270,12 +272,13 @@ k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __r
 // ---------------------------------------------------------------------------
 constexpr int MX = 64, MY = 8, MZ = 32;
 
-inline TileGeom march_tiles(const Grid& g, bool three_d)
+inline TileGeom march_tiles(const Grid& g, bool three_d, int mz)
 {
     TileGeom t;
     t.ntx = (g.nx + MX - 1) / MX;
     t.nty = (g.ny + MY - 1) / MY;
-    t.nsz = three_d ? (g.nz + MZ - 1) / MZ : 1;
+    t.mz = mz;
+    t.nsz = three_d ? (g.nz + mz - 1) / mz : 1;
     return t;
 }
 
@@ -286,9 +289,19 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
     constexpr int R = radius(SCH);
     constexpr int WR = MX + 2 * R, HR = MY + 2 * R, CELLS = WR * HR, NTH = MX * MY;
     constexpr int SPT = (CELLS + NTH - 1) / NTH;
+    // Two ways to feed the z arms.  NF = 1 (mu_hat, arithmetic-bound): the
+    // own column's plane p + R comes from global memory with the prefetch and
+    // plane p is computed from a double-buffered stage.  NF = 2 (force, two
+    // fields): every plane is loaded once, staged when it enters the march,
+    // and the own column is pushed from LDS; plane p - R is computed from its
+    // slot, and R + 2 slots keep each read ahead of the overwrite that follows
+    // the next barrier.
+    constexpr bool SLOTS = DIM == 3 && NF == 2;
+    constexpr int LAG = SLOTS ? R : 0;
+    constexpr int NS = SLOTS ? R + 2 : 2;
     constexpr int QZ = DIM == 3 ? 2 * R + 1 : 1;
     constexpr double cs2 = 1.0 / 3.0;
-    __shared__ double sp[2][NF][CELLS];
+    __shared__ double sp[NS][NF][CELLS];
 
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int nxy = (int)g.nxy;
@@ -306,8 +319,8 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
     const int lx = lid % MX, ly = lid / MX;
     const bool in = lx < min(MX, nx - x0) && ly < min(MY, ny - y0);
     const int col = in ? (y0 + ly) * nx + x0 + lx : 0;
-    const int z0 = DIM == 3 ? sz * MZ : 0;
-    const int z1 = DIM == 3 ? min(z0 + MZ, nz) : 1;
+    const int z0 = DIM == 3 ? sz * tg.mz : 0;
+    const int z1 = DIM == 3 ? min(z0 + tg.mz, nz) : 1;
     const int c0 = (ly + R) * WR + (lx + R);
     const double* src[2] = { rho, mu };
 
@@ -319,7 +332,8 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
         const int hy = idx / WR, hx = idx - hy * WR;
         off[k] = idx < CELLS ? (unsigned)(pwrap(y0 - R + hy, ny) * nx + pwrap(x0 - R + hx, nx)) : 0u;
     }
-    // z queues of the own column: index k <-> plane z-R+k
+    // z queue of the own column, index k <-> plane z - R + k for the plane z
+    // computed next.  Planes before the first staged one are loaded here.
     double q[NF][QZ];
 #pragma unroll
     for (int f = 0; f < NF; ++f)
@@ -330,66 +344,80 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
 #pragma unroll
             for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int k = 0; k < 2 * R; ++k) q[f][k + 1] = ld32(src[f], (unsigned)(pwrap(z0 - R + k, nz) * nxy + col));
+                for (int k = SLOTS ? R : 0; k < 2 * R; ++k)
+                    q[f][k + 1] = ld32(src[f], (unsigned)(pwrap(z0 - R - LAG + k, nz) * nxy + col));
         }
     }
     double sv[NF][SPT], qn[NF];
-    auto fetch = [&](int z) {
-        const unsigned zo = (unsigned)(z * nxy);
+    auto fetch = [&](int p) {
+        const unsigned zo = (unsigned)(pwrap(p, nz) * nxy);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
             for (int k = 0; k < SPT; ++k)
                 if (lid + k * NTH < CELLS) sv[f][k] = ld32(src[f], zo + off[k]);
-            if constexpr (DIM == 3) {
-                if (in) qn[f] = ld32(src[f], (unsigned)(pwrap(z + R, nz) * nxy + col));
+            if constexpr (DIM == 3 && !SLOTS) {
+                if (in) qn[f] = ld32(src[f], (unsigned)(pwrap(p + R, nz) * nxy + col));
             }
         }
     };
+    const int pe = z1 - 1 + LAG;   // last plane staged
     fetch(z0);
-    for (int z = z0; z < z1; ++z) {
-        double (*s)[CELLS] = sp[(z - z0) & 1];
+    for (int p = z0; p <= pe; ++p) {
+        double (*s)[CELLS] = sp[(p - z0) % NS];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int k = 0; k < SPT; ++k)
                 if (lid + k * NTH < CELLS) s[f][lid + k * NTH] = sv[f][k];
-            if constexpr (DIM == 3) {
+        if constexpr (DIM == 3 && !SLOTS) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
 #pragma unroll
                 for (int k = 0; k < QZ - 1; ++k) q[f][k] = q[f][k + 1];
                 q[f][QZ - 1] = qn[f];
             }
         }
-        if (z + 1 < z1) fetch(z + 1);
+        if (p < pe) fetch(p + 1);
         __syncthreads();
-        if (!in) continue;
+        if constexpr (SLOTS) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+#pragma unroll
+                for (int k = 0; k < QZ - 1; ++k) q[f][k] = q[f][k + 1];
+                q[f][QZ - 1] = s[f][c0];
+            }
+        }
+        if (p < z0 + LAG || !in) continue;
+        const int z = p - LAG;
+        double (*c)[CELLS] = sp[(z - z0) % NS];
         const unsigned n = (unsigned)(z * nxy + col);
         if constexpr (NF == 1) {
-            const double f0 = s[0][c0];
+            const double f0 = c[0][c0];
             double acc = DIM * d2(SCH, 0) * f0;
 #pragma unroll
             for (int m = 1; m <= R; ++m) {
-                const double c = d2(SCH, m);
-                acc += c * (s[0][c0 + m] + s[0][c0 - m]);
-                acc += c * (s[0][c0 + m * WR] + s[0][c0 - m * WR]);
-                if constexpr (DIM == 3) acc += c * (q[0][R + m] + q[0][R - m]);
+                const double w = d2(SCH, m);
+                acc += w * (c[0][c0 + m] + c[0][c0 - m]);
+                acc += w * (c[0][c0 + m * WR] + c[0][c0 - m * WR]);
+                if constexpr (DIM == 3) acc += w * (q[0][R + m] + q[0][R - m]);
             }
             st32(out, n, mu_bulk(f0, e) - e.kappa * acc);
         } else {
             double grx = 0.0, gry = 0.0, grz = 0.0, gmx = 0.0, gmy = 0.0, gmz = 0.0;
 #pragma unroll
             for (int m = 1; m <= R; ++m) {
-                const double c = d1(SCH, m);
-                grx += c * (s[0][c0 + m] - s[0][c0 - m]);
-                gry += c * (s[0][c0 + m * WR] - s[0][c0 - m * WR]);
-                gmx += c * (s[1][c0 + m] - s[1][c0 - m]);
-                gmy += c * (s[1][c0 + m * WR] - s[1][c0 - m * WR]);
+                const double w = d1(SCH, m);
+                grx += w * (c[0][c0 + m] - c[0][c0 - m]);
+                gry += w * (c[0][c0 + m * WR] - c[0][c0 - m * WR]);
+                gmx += w * (c[1][c0 + m] - c[1][c0 - m]);
+                gmy += w * (c[1][c0 + m * WR] - c[1][c0 - m * WR]);
                 if constexpr (DIM == 3) {
-                    grz += c * (q[0][R + m] - q[0][R - m]);
-                    gmz += c * (q[1][R + m] - q[1][R - m]);
+                    grz += w * (q[0][R + m] - q[0][R - m]);
+                    gmz += w * (q[1][R + m] - q[1][R - m]);
                 }
             }
-            const double r = s[0][c0];
+            const double r = c[0][c0];
             st32(out, n, -r * gmx + cs2 * grx);
             st32(out + N, n, -r * gmy + cs2 * gry);
             if constexpr (DIM == 3) st32(out + 2 * (size_t)N, n, -r * gmz + cs2 * grz);
@@ -400,7 +428,7 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
 template <int DIM, int SCH>
 inline void launch_mu_march(const double* rho, double* mu, const Grid& g, const Eos& e, hipStream_t st)
 {
-    const TileGeom t = march_tiles(g, DIM == 3);
+    const TileGeom t = march_tiles(g, DIM == 3, MZ);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
     hipLaunchKernelGGL((k_march<DIM, SCH, 1>), dim3(nb), dim3(MX * MY), 0, st, rho, nullptr, mu, g, t, e);
 }
@@ -409,7 +437,7 @@ template <int DIM, int SCH>
 inline void launch_force_march(const double* rho, const double* mu, double* F, const Grid& g, const Eos& e,
                                hipStream_t st)
 {
-    const TileGeom t = march_tiles(g, DIM == 3);
+    const TileGeom t = march_tiles(g, DIM == 3, 2 * MZ);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
     hipLaunchKernelGGL((k_march<DIM, SCH, 2>), dim3(nb), dim3(MX * MY), 0, st, rho, mu, F, g, t, e);
 }
@@ -420,7 +448,7 @@ inline void launch_force_march(const double* rho, const double* mu, double* F, c
 // the kernel holds no stencil state.  The next plane's pulls are issued right
 // after the gather of the current plane, overlapping the second barrier.
 // ---------------------------------------------------------------------------
-template <int LAT, int TX, int TY, int OCC, bool FULL>
+template <int LAT, int TX, int TY, int OCC, bool PF, bool FULL>
 __global__ void __launch_bounds__((TX + 2) * (TY + 2), OCC)
 k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ F,
        double* __restrict__ rho_next, Grid g, TileGeom tg, double one_m_omega)
@@ -468,7 +496,8 @@ k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
     const int z1 = LAT == 1 ? min(z0 + FZ, nz) : 1;
 
     double f[Q], Fx = 0.0, Fy = 0.0, Fz = 0.0;
-    auto pull_plane = [&](int z) {
+    double fn[PF ? Q : 1], Fxn = 0.0, Fyn = 0.0, Fzn = 0.0;
+    auto pull_plane = [&](int z, double (&f)[Q], double& Fx, double& Fy, double& Fz) {
         const int zo = z * nxy;
         const int zmo = LAT == 1 ? wrapc(z - 1, nz) * nxy : 0;
         const int zpo = LAT == 1 ? wrapc(z + 1, nz) * nxy : 0;
@@ -487,9 +516,14 @@ k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
 
     double acc_m1 = 0.0, acc_0 = 0.0;
     const int zb = LAT == 1 ? z0 - 1 : 0, ze = LAT == 1 ? z1 : 0;
-    if (active) pull_plane(LAT == 1 ? pwrap(zb, nz) : 0);
+    if (active) pull_plane(LAT == 1 ? pwrap(zb, nz) : 0, f, Fx, Fy, Fz);
     for (int zr = zb; zr <= ze; ++zr) {
         const int z = LAT == 1 ? pwrap(zr, nz) : 0;
+        // PF: the next plane's loads go out a whole plane ahead (registers
+        // double-buffered); otherwise they are issued after the gather
+        if constexpr (PF) {
+            if (active && zr < ze) pull_plane(pwrap(zr + 1, nz), fn, Fxn, Fyn, Fzn);
+        }
         double own_m1 = 0.0, own_0 = 0.0, own_p1 = 0.0;   // post-collision values without in-plane shift
         if (active) {
             double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
@@ -534,7 +568,9 @@ k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
                 if (L::ez(i) == -1) a_m1 += v; else if (L::ez(i) == 0) a_0 += v; else a_p1 += v;
             }
         }
-        if (active && zr < ze) pull_plane(pwrap(zr + 1, nz));
+        if constexpr (!PF) {
+            if (active && zr < ze) pull_plane(pwrap(zr + 1, nz), f, Fx, Fy, Fz);
+        }
         __syncthreads();
         if (inner) {
             if constexpr (LAT == 1) {
@@ -546,11 +582,17 @@ k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
                 rho_next[yc + x] = a_0;
             }
         }
+        if constexpr (PF) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[i] = fn[i];
+            Fx = Fxn; Fy = Fyn; Fz = Fzn;
+        }
     }
 }
 
-struct RingVariant { int tx, ty, occ; };
-constexpr RingVariant kRingVariants[] = { {64, 8, 3}, {32, 16, 2}, {32, 24, 1}, {32, 28, 1}, {48, 16, 1}, {64, 13, 2} };
+struct RingVariant { int tx, ty, occ, pf; };
+constexpr RingVariant kRingVariants[] = { {64, 8, 3, 0}, {64, 8, 3, 1}, {64, 9, 3, 1}, {64, 7, 3, 1}, {64, 13, 2, 0},
+                                          {32, 16, 2, 0} };
 constexpr int kNumRingVariants = 6;
 
 inline TileGeom ring_tiles(int tx, int ty, const Grid& g, bool three_d)
@@ -559,20 +601,21 @@ inline TileGeom ring_tiles(int tx, int ty, const Grid& g, bool three_d)
     t.ntx = (g.nx + tx - 1) / tx;
     t.nty = (g.ny + ty - 1) / ty;
     t.nsz = three_d ? (g.nz + FZ - 1) / FZ : 1;
+    t.mz = FZ;
     return t;
 }
 
-template <int LAT, int TX, int TY, int OCC>
+template <int LAT, int TX, int TY, int OCC, bool PF>
 inline void launch_ring_v(const double* S, double* Sn, const double* F, double* rho_next, const Grid& g,
                           double one_m_omega, hipStream_t st)
 {
     const TileGeom t = ring_tiles(TX, TY, g, LAT == 1);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
     if (one_m_omega == 0.0)
-        hipLaunchKernelGGL((k_ring<LAT, TX, TY, OCC, true>), dim3(nb), dim3((TX + 2) * (TY + 2)), 0, st, S, Sn, F,
+        hipLaunchKernelGGL((k_ring<LAT, TX, TY, OCC, PF, true>), dim3(nb), dim3((TX + 2) * (TY + 2)), 0, st, S, Sn, F,
                            rho_next, g, t, one_m_omega);
     else
-        hipLaunchKernelGGL((k_ring<LAT, TX, TY, OCC, false>), dim3(nb), dim3((TX + 2) * (TY + 2)), 0, st, S, Sn, F,
+        hipLaunchKernelGGL((k_ring<LAT, TX, TY, OCC, PF, false>), dim3(nb), dim3((TX + 2) * (TY + 2)), 0, st, S, Sn, F,
                            rho_next, g, t, one_m_omega);
 }
 
@@ -581,12 +624,12 @@ inline void launch_ring_collide(int variant, const double* S, double* Sn, const 
                                 const Grid& g, double one_m_omega, hipStream_t st)
 {
     switch (variant) {
-    case 1: launch_ring_v<LAT, 32, 16, 2>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    case 2: launch_ring_v<LAT, 32, 24, 1>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    case 3: launch_ring_v<LAT, 32, 28, 1>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    case 4: launch_ring_v<LAT, 48, 16, 1>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    case 5: launch_ring_v<LAT, 64, 13, 2>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    default: launch_ring_v<LAT, 64, 8, 3>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 1: launch_ring_v<LAT, 64, 8, 3, true>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 2: launch_ring_v<LAT, 64, 9, 3, true>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 3: launch_ring_v<LAT, 64, 7, 3, true>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 4: launch_ring_v<LAT, 64, 13, 2, false>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 5: launch_ring_v<LAT, 32, 16, 2, false>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    default: launch_ring_v<LAT, 64, 8, 3, false>(S, Sn, F, rho_next, g, one_m_omega, st); break;
     }
 }
 

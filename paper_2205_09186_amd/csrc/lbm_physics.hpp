@@ -93,6 +93,37 @@ struct Eos {
     double kappa;    // kappa-hat
 };
 
+// Natural logarithm of a positive normal double by the classic argument
+// reduction x = m 2^e, m in [1/sqrt2, sqrt2), and the odd series
+//   ln m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...),  s = (m - 1)/(m + 1),
+// |s| <= 0.1716, summed to s^21 (the first omitted term is below 2^-59
+// relative), then e ln2 added with ln2 split into a 42-bit head (e * head is
+// exact) and a tail.  About a third of the instructions of the library log,
+// within a few ulp of it; the chemical potential evaluates two per node.
+__host__ __device__ __forceinline__ double log_pos(double x)
+{
+    int ex;
+    double m = frexp(x, &ex);   // m in [0.5, 1)
+    if (m < 0.70710678118654752440) { m += m; ex -= 1; }
+    const double f = m - 1.0;   // exact
+    const double s = f / (m + 1.0);
+    const double t = s * s;
+    double p = 2.0 / 21.0;
+    p = fma(p, t, 2.0 / 19.0);
+    p = fma(p, t, 2.0 / 17.0);
+    p = fma(p, t, 2.0 / 15.0);
+    p = fma(p, t, 2.0 / 13.0);
+    p = fma(p, t, 2.0 / 11.0);
+    p = fma(p, t, 2.0 / 9.0);
+    p = fma(p, t, 2.0 / 7.0);
+    p = fma(p, t, 2.0 / 5.0);
+    p = fma(p, t, 2.0 / 3.0);
+    const double r = fma(s * t, p, s + s);
+    const double ln2_hi = 0x1.62e42fefa3800p-1, ln2_lo = 0x1.ef35793c76730p-45;
+    const double de = (double)ex;
+    return fma(de, ln2_hi, fma(de, ln2_lo, r));
+}
+
 __host__ __device__ __forceinline__ double mu_bulk(double rho, const Eos& e)
 {
     const double s2 = 1.4142135623730951;
@@ -102,7 +133,7 @@ __host__ __device__ __forceinline__ double mu_bulk(double rho, const Eos& e)
     const double inv_g = (A * B) * inv;
     const double inv_B = (g * A) * inv;
     const double inv_AB = g * inv;
-    return e.k2RT * (log(rho * inv_g) + inv_g) - e.k2c * log(A * inv_B) - e.k2aa * rho * inv_AB;
+    return e.k2RT * (log_pos(rho * inv_g) + inv_g) - e.k2c * log_pos(A * inv_B) - e.k2aa * rho * inv_AB;
 }
 
 }  // namespace lbm
