@@ -53,7 +53,8 @@ def run(args):
                    kappa=args.kappa, scheme=lbm.SCHEMES[args.scheme])
     g, l = lbm.coexistence(args.Tr)
     sim = lbm.Simulation(p, torch.from_numpy(inputs.droplet(shape, 0.25 * n, 10.0, g, l).reshape(-1)).cuda())
-    sim.set_variant(args.variant)
+    if args.variant is not None:
+        sim.set_variant(args.variant)
     sim.step(args.steps)
     torch.cuda.synchronize()
     print(f"profiled {workload_name(args.lattice, n, args.Tr, args.scheme, args.k)} variant {args.variant} "
@@ -153,13 +154,13 @@ def main():
     r.add_argument("--k", type=float, default=0.1)
     r.add_argument("--kappa", type=float, default=0.004)
     r.add_argument("--steps", type=int, default=5)
-    r.add_argument("--variant", type=int, default=0)
+    r.add_argument("--variant", type=int, default=None, help="launch variant (default: the library's)")
     s = sub.add_parser("summarize")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
     s.add_argument("--trace", required=True)
     s.add_argument("--workload", required=True)
-    s.add_argument("--kernel", default="k_fused")
+    s.add_argument("--kernel", default="k_ring")
     s.add_argument("--commands", default="")
     s.add_argument("--out", required=True)
     a = ap.parse_args()
