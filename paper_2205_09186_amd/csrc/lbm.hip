@@ -167,6 +167,15 @@ void compact_deriv(lbm_ctx* c, const double* in, double* out, int d, bool accumu
 {
     const LineGeom& lg = c->lines[d];
     const Compact cc = compact_scheme(c->p.scheme);
+    if (d == 0 && lg.n <= 8192 && lg.K <= kScanWarm) {
+        // whole rows, one wavefront each, forward results of the row in LDS
+        const int waves = lg.n <= 2048 ? 4 : 1;
+        const long long rows = (long long)lg.n1 * lg.n2;
+        hipLaunchKernelGGL(k_compact_x, dim3((unsigned)((rows + waves - 1) / waves)), dim3(64 * waves),
+                           sizeof(double) * waves * lg.n, c->stream, in, out, lg.n, rows, cc, c->z, c->zscale,
+                           accumulate ? 1 : 0);
+        return;
+    }
     const long long items = (long long)lg.n1 * lg.n2 * lg.nch;
     hipLaunchKernelGGL(k_compact_fwd, dim3(blocks_for(items, 256)), dim3(256), 0, c->stream,
                        in, c->wtmp, lg, cc, c->z);
@@ -275,7 +284,10 @@ void set_lines(lbm_ctx* c)
         lg.n = n[d]; lg.sa = st[d];
         lg.n1 = n[o1]; lg.s1 = st[o1];
         lg.n2 = n[o2]; lg.s2 = st[o2];
-        lg.C = 64;
+        // chunk length: long chunks waste less on the K-point warm-up, short
+        // ones give more threads; aim at ~2^18 threads per axis, C in [16, 128]
+        const long long pts = (long long)lg.n * lg.n1 * lg.n2;
+        lg.C = (int)std::max(16LL, std::min(128LL, pts >> 18));
         lg.nch = (lg.n + lg.C - 1) / lg.C;
         lg.K = 0;
     }

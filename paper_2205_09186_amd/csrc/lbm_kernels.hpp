@@ -357,6 +357,11 @@ __device__ __forceinline__ int pmod(long long i, int n)
     return (int)(r < 0 ? r + n : r);
 }
 
+// Forward recursion w_i = v_i + z w_{i-1} along lines of a non-unit-stride
+// axis, v_i the right-hand side of Eq 21.  One thread per (line, chunk of C);
+// the recursion starts K points early, where |z|^K < 1e-18.  Lanes run along x,
+// so every load is coalesced; a seven-point register window leaves one new
+// load per point.
 __global__ void __launch_bounds__(256) k_compact_fwd(const double* __restrict__ f, double* __restrict__ w,
                                                      LineGeom lg, Compact c, double z)
 {
@@ -368,20 +373,32 @@ __global__ void __launch_bounds__(256) k_compact_fwd(const double* __restrict__ 
     const int o2 = (int)(rest % lg.n2);
     const int ch = (int)(rest / lg.n2);
     const long long base = o1 * lg.s1 + o2 * lg.s2;
+    const int n = lg.n;
+    const long long sa = lg.sa;
     const int start = ch * lg.C;
-    const int end = min(start + lg.C, lg.n);
+    const int end = min(start + lg.C, n);
     const double ha = 0.5 * c.ca, hb = 0.25 * c.cb, hc = c.cc / 6.0;
+    const int i0 = start - lg.K;
+    double r[7];   // f at i-3 .. i+3
+#pragma unroll
+    for (int k = 0; k < 7; ++k) r[k] = f[base + pmod((long long)i0 - 3 + k, n) * sa];
+    int jn = pmod((long long)i0 + 4, n);   // next point entering the window
+    int im = pmod(i0, n);                  // current point
     double acc = 0.0;
-    for (long long i = (long long)start - lg.K; i < end; ++i) {
-        const int im = pmod(i, lg.n);
-        const double v = ha * (f[base + pmod(i + 1, lg.n) * lg.sa] - f[base + pmod(i - 1, lg.n) * lg.sa])
-                       + hb * (f[base + pmod(i + 2, lg.n) * lg.sa] - f[base + pmod(i - 2, lg.n) * lg.sa])
-                       + hc * (f[base + pmod(i + 3, lg.n) * lg.sa] - f[base + pmod(i - 3, lg.n) * lg.sa]);
+#pragma unroll 4
+    for (int i = i0; i < end; ++i) {
+        const double v = ha * (r[4] - r[2]) + hb * (r[5] - r[1]) + hc * (r[6] - r[0]);
         acc = v + z * acc;
-        if (i >= start) w[base + im * lg.sa] = acc;
+        if (i >= start) w[base + im * sa] = acc;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) r[k] = r[k + 1];
+        r[6] = f[base + jn * sa];
+        jn = jn + 1 == n ? 0 : jn + 1;
+        im = im + 1 == n ? 0 : im + 1;
     }
 }
 
+// Backward recursion y_i = w_i + z y_{i+1}, out = scale * y (or += ).
 __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ w, double* __restrict__ out,
                                                      LineGeom lg, double z, double scale, int accumulate)
 {
@@ -393,15 +410,89 @@ __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ 
     const int o2 = (int)(rest % lg.n2);
     const int ch = (int)(rest / lg.n2);
     const long long base = o1 * lg.s1 + o2 * lg.s2;
+    const int n = lg.n;
+    const long long sa = lg.sa;
     const int start = ch * lg.C;
-    const int end = min(start + lg.C, lg.n);
+    const int end = min(start + lg.C, n);
+    const int i0 = end - 1 + lg.K;
+    int im = pmod(i0, n);
     double acc = 0.0;
-    for (long long i = (long long)end - 1 + lg.K; i >= start; --i) {
-        const int im = pmod(i, lg.n);
-        acc = w[base + im * lg.sa] + z * acc;
+#pragma unroll 4
+    for (int i = i0; i >= start; --i) {
+        acc = w[base + im * sa] + z * acc;
         if (i < end) {
-            const long long o = base + im * lg.sa;
+            const long long o = base + im * sa;
             out[o] = accumulate ? out[o] + scale * acc : scale * acc;
+        }
+        im = im == 0 ? n - 1 : im - 1;
+    }
+}
+
+// Compact derivative along x (unit stride) of whole rows: one wavefront per
+// row, lanes along x.  Both recursions run as wavefront-wide scans over chunks
+// of 64 consecutive points (the recursion a_i = v_i + z a_{i-1} in log2(64)
+// shuffle steps, plus z^(lane+1) times the carry from the previous chunk), so
+// every load and store is coalesced.  The sweep starts W >= K points early
+// (periodic positions), the forward results of the row sit in LDS for the
+// backward sweep.  zp[k] = z^(k+1), k < 64.
+constexpr int kScanWarm = 128;
+
+__global__ void __launch_bounds__(256) k_compact_x(const double* __restrict__ f, double* __restrict__ out, int nx,
+                                                   long long nrows, Compact c, double z, double scale, int accumulate)
+{
+    extern __shared__ double wrow[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const long long row = (long long)blockIdx.x * (blockDim.x >> 6) + wv;
+    if (row >= nrows) return;   // whole wavefront leaves; no block barrier below
+    double* wb = wrow + (size_t)wv * nx;
+    const double* fr = f + row * nx;
+    const double ha = 0.5 * c.ca, hb = 0.25 * c.cb, hc = c.cc / 6.0;
+    double zs[7];    // z^(2^s)
+    zs[0] = z;
+#pragma unroll
+    for (int s = 1; s < 7; ++s) zs[s] = zs[s - 1] * zs[s - 1];
+    double zl = 1.0;  // z^(lane+1) from the binary digits of lane+1
+#pragma unroll
+    for (int s = 0; s < 7; ++s)
+        if ((lane + 1) >> s & 1) zl *= zs[s];
+    auto scan = [&](double a, double carry) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const double t = __shfl_up(a, 1u << s, 64);
+            if (lane >= (1 << s)) a += zs[s] * t;
+        }
+        return a + zl * carry;
+    };
+    // forward sweep over positions -W .. nx-1
+    double carry = 0.0;
+    for (int p0 = -kScanWarm; p0 < nx; p0 += 64) {
+        const int p = p0 + lane;
+        const bool valid = p < nx;
+        double v = 0.0;
+        int x = 0;
+        if (valid) {
+            x = pmod(p, nx);
+            const int x1 = wrapc(x + 1, nx), x_1 = wrapc(x - 1, nx);
+            const int x2 = pmod(x + 2, nx), x_2 = pmod(x - 2, nx);
+            const int x3 = pmod(x + 3, nx), x_3 = pmod(x - 3, nx);
+            v = ha * (fr[x1] - fr[x_1]) + hb * (fr[x2] - fr[x_2]) + hc * (fr[x3] - fr[x_3]);
+        }
+        const double a = scan(v, carry);
+        carry = __shfl(a, 63, 64);
+        if (valid && p >= 0) wb[x] = a;
+    }
+    // backward sweep over positions nx-1+W .. 0 (lane order = descending)
+    carry = 0.0;
+    for (int q0 = nx - 1 + kScanWarm; q0 >= 0; q0 -= 64) {
+        const int q = q0 - lane;
+        const bool valid = q >= 0;
+        const int x = valid ? pmod(q, nx) : 0;
+        const double a = scan(valid ? wb[x] : 0.0, carry);
+        carry = __shfl(a, 63, 64);
+        if (valid && q < nx) {
+            double* o = out + row * nx + x;
+            *o = accumulate ? *o + scale * a : scale * a;
         }
     }
 }
