@@ -81,7 +81,7 @@ Layout layout_of(const lbm_params* p)
     L.rho0 = take(sizeof(double) * N);
     L.rho1 = take(sizeof(double) * N);
     L.mu = take(sizeof(double) * N);
-    if (p->scheme <= LBM_CD6 && N < (1LL << 29)) L.force = take(sizeof(double) * dim * N);
+    if (N < (1LL << 29)) L.force = take(sizeof(double) * dim * N);
     if (compact) {
         L.grho = take(sizeof(double) * dim * N);
         L.gmu = take(sizeof(double) * dim * N);
@@ -113,7 +113,7 @@ struct lbm_ctx {
     // compact-scheme line geometry per axis
     LineGeom lines[3];
     double z, zscale;
-    bool fused;     // explicit schemes: fused collide + next-density kernel
+    bool fused;     // fast path: the collide kernel also forms the next density
     int variant = 0;  // launch variant of the fused kernel
     // two-step launch graph replayed by lbm_step (captured on a private stream,
     // launched on the context's stream); graph_cur is the state parity it
@@ -162,8 +162,16 @@ void launch_init(lbm_ctx* c, const double* rho0)
                        rho0, c->S[c->cur], c->g);
 }
 
-// Compact derivative of field `in` along axis d into `out` (optionally added).
-void compact_deriv(lbm_ctx* c, const double* in, double* out, int d, bool accumulate)
+// Compact derivative of field `in` along axis d, delivered to `sink` (stored,
+// added, or turned into the force component of Eq 12).
+CompactSink sink_of(double* out, int mode, const double* rho = nullptr, const double* grad = nullptr)
+{
+    CompactSink k;
+    k.out = out; k.mode = mode; k.rho = rho; k.grad = grad;
+    return k;
+}
+
+void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
 {
     const LineGeom& lg = c->lines[d];
     const Compact cc = compact_scheme(c->p.scheme);
@@ -172,32 +180,42 @@ void compact_deriv(lbm_ctx* c, const double* in, double* out, int d, bool accumu
         const int waves = lg.n <= 2048 ? 4 : 1;
         const long long rows = (long long)lg.n1 * lg.n2;
         hipLaunchKernelGGL(k_compact_x, dim3((unsigned)((rows + waves - 1) / waves)), dim3(64 * waves),
-                           sizeof(double) * waves * lg.n, c->stream, in, out, lg.n, rows, cc, c->z, c->zscale,
-                           accumulate ? 1 : 0);
+                           sizeof(double) * waves * lg.n, c->stream, in, sink, lg.n, rows, cc, c->z, c->zscale);
         return;
     }
     const long long items = (long long)lg.n1 * lg.n2 * lg.nch;
     hipLaunchKernelGGL(k_compact_fwd, dim3(blocks_for(items, 256)), dim3(256), 0, c->stream,
                        in, c->wtmp, lg, cc, c->z);
     hipLaunchKernelGGL(k_compact_bwd, dim3(blocks_for(items, 256)), dim3(256), 0, c->stream,
-                       c->wtmp, out, lg, c->z, c->zscale, accumulate ? 1 : 0);
+                       c->wtmp, sink, lg, c->z, c->zscale);
+}
+
+// Compact schemes: G[rho] into grho, the Laplacian D(D rho) summed over the
+// axes, then mu_hat.
+void compact_mu(lbm_ctx* c, const double* rho, int dim)
+{
+    for (int d = 0; d < dim; ++d) compact_deriv(c, rho, sink_of(c->grho + d * c->g.N, C_STORE), d);
+    for (int d = 0; d < dim; ++d)
+        compact_deriv(c, c->grho + d * c->g.N, sink_of(c->lap, d > 0 ? C_ADD : C_STORE), d);
+    hipLaunchKernelGGL(k_mu_lap, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                       rho, c->lap, c->mu, c->g.N, c->eos);
 }
 
 // rho of the current state, then the chemical potential and (compact schemes)
-// the gradient fields that the force needs.
+// the gradient fields that the force needs.  On the fast path rho is already
+// in rhob[cur] (formed by the last collide) and is left as it is, so that an
+// observation does not perturb the state.
 template <int LAT, int SCH>
 void launch_fields(lbm_ctx* c)
 {
     constexpr int DIM = Lat<LAT>::DIM;
     const double* S = c->S[c->cur];
     double* rho = c->rhob[c->cur];
-    hipLaunchKernelGGL(k_rho<LAT>, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream, S, rho, c->g);
+    if (!c->fused)
+        hipLaunchKernelGGL(k_rho<LAT>, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream, S, rho, c->g);
     if constexpr (is_compact(SCH)) {
-        for (int d = 0; d < DIM; ++d) compact_deriv(c, rho, c->grho + d * c->g.N, d, false);
-        for (int d = 0; d < DIM; ++d) compact_deriv(c, c->grho + d * c->g.N, c->lap, d, d > 0);
-        hipLaunchKernelGGL(k_mu_lap, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
-                           rho, c->lap, c->mu, c->g.N, c->eos);
-        for (int d = 0; d < DIM; ++d) compact_deriv(c, c->mu, c->gmu + d * c->g.N, d, false);
+        compact_mu(c, rho, DIM);
+        for (int d = 0; d < DIM; ++d) compact_deriv(c, c->mu, sink_of(c->gmu + d * c->g.N, C_STORE), d);
     } else {
         hipLaunchKernelGGL((k_mu<DIM, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
                            rho, c->mu, c->g, c->eos);
@@ -207,28 +225,43 @@ void launch_fields(lbm_ctx* c)
 template <int LAT, int SCH>
 void launch_step(lbm_ctx* c)
 {
-    if constexpr (SCH == CD2 || SCH == CD4 || SCH == CD6) {
-        if (c->fused) {
-            // rho of the current state is already in rhob[cur] (written by the
-            // previous fused step or at initialisation)
-            constexpr int DIM = Lat<LAT>::DIM;
+    if (c->fused) {
+        // rho of the current state is already in rhob[cur] (written by the
+        // previous step's collide or at initialisation); the force pass for
+        // the scheme, then the ring collide (or, for the explicit CD schemes,
+        // the collide that forms the force itself)
+        constexpr int DIM = Lat<LAT>::DIM;
+        const double* rho = c->rhob[c->cur];
+        constexpr bool CD = SCH == CD2 || SCH == CD4 || SCH == CD6;
+        if constexpr (!is_compact(SCH)) {
             mark(c, "k_mu_march");
-            launch_mu_march<DIM, SCH>(c->rhob[c->cur], c->mu, c->g, c->eos, c->stream);
-            if (c->variant >= kNumFusedVariants) {
-                mark(c, "k_force_march");
-                launch_force_march<DIM, SCH>(c->rhob[c->cur], c->mu, c->force, c->g, c->eos, c->stream);
-                mark(c, "k_ring");
-                launch_ring_collide<LAT>(c->variant - kNumFusedVariants, c->S[c->cur], c->S[1 - c->cur], c->force,
-                                         c->rhob[1 - c->cur], c->g, c->one_m_omega, c->stream);
-            } else {
-                mark(c, "k_fused");
-                launch_fused_collide<LAT, SCH>(c->variant, c->S[c->cur], c->S[1 - c->cur], c->rhob[c->cur], c->mu,
-                                               c->rhob[1 - c->cur], c->g, c->one_m_omega, c->stream);
-            }
-            mark(c, nullptr);
-            c->cur = 1 - c->cur;
-            return;
+            launch_mu_march<DIM, SCH>(rho, c->mu, c->g, c->eos, c->stream);
         }
+        if constexpr (CD) {
+            if (c->variant < kNumFusedVariants) {
+                mark(c, "k_fused");
+                launch_fused_collide<LAT, SCH>(c->variant, c->S[c->cur], c->S[1 - c->cur], rho, c->mu,
+                                               c->rhob[1 - c->cur], c->g, c->one_m_omega, c->stream);
+                mark(c, nullptr);
+                c->cur = 1 - c->cur;
+                return;
+            }
+        }
+        if constexpr (!is_compact(SCH)) {
+            mark(c, "k_force_march");
+            launch_force_march<DIM, SCH>(rho, c->mu, c->force, c->g, c->eos, c->stream);
+        } else {
+            mark(c, "compact derivatives+mu+force");
+            compact_mu(c, rho, DIM);
+            for (int d = 0; d < DIM; ++d)
+                compact_deriv(c, c->mu, sink_of(c->force + d * c->g.N, C_FORCE, rho, c->grho + d * c->g.N), d);
+        }
+        mark(c, "k_ring");
+        launch_ring_collide<LAT>(CD ? c->variant - kNumFusedVariants : c->variant, c->S[c->cur], c->S[1 - c->cur],
+                                 c->force, c->rhob[1 - c->cur], c->g, c->one_m_omega, c->stream);
+        mark(c, nullptr);
+        c->cur = 1 - c->cur;
+        return;
     }
     mark(c, is_compact(SCH) ? "rho+compact derivatives+mu" : "k_rho+k_mu");
     launch_fields<LAT, SCH>(c);
@@ -343,7 +376,7 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->rhob[0] = reinterpret_cast<double*>(c->ws + L.rho0);
     c->rhob[1] = reinterpret_cast<double*>(c->ws + L.rho1);
     c->mu = reinterpret_cast<double*>(c->ws + L.mu);
-    c->force = (p->scheme <= LBM_CD6 && c->g.N < (1LL << 29)) ? reinterpret_cast<double*>(c->ws + L.force) : nullptr;
+    c->force = c->g.N < (1LL << 29) ? reinterpret_cast<double*>(c->ws + L.force) : nullptr;
     const bool compact = p->scheme >= LBM_OCFDS4;
     c->grho = compact ? reinterpret_cast<double*>(c->ws + L.grho) : nullptr;
     c->gmu = compact ? reinterpret_cast<double*>(c->ws + L.gmu) : nullptr;
@@ -354,11 +387,11 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->cur = 0;
     c->steps = 0;
     c->one_m_omega = 1.0 - 1.0 / p->tau;
-    c->fused = p->scheme <= LBM_CD6 && c->g.N < (1LL << 29) && std::getenv("LBM_NO_FUSED") == nullptr;
-    // untuned default: the ring collide with its own force pass in 3D, the
-    // collide that forms the force itself in 2D (fastest of each on 256^3
-    // and 1024^2)
-    c->variant = p->lattice == LBM_D3Q19 ? kNumFusedVariants : 0;
+    c->fused = c->g.N < (1LL << 29) && std::getenv("LBM_NO_FUSED") == nullptr;
+    // untuned default for the CD schemes: the ring collide with its own force
+    // pass in 3D, the collide that forms the force itself in 2D (fastest of
+    // each on 256^3 and 1024^2); the other schemes have only ring variants
+    c->variant = (p->lattice == LBM_D3Q19 && p->scheme <= LBM_CD6) ? kNumFusedVariants : 0;
     c->use_graph = std::getenv("LBM_NO_GRAPH") == nullptr;
     set_lines(c);
 
@@ -585,7 +618,8 @@ int lbm_step_timed(lbm_ctx* c, long nsteps, double* ms, int cap, int* nphases)
 
 int lbm_num_variants(const lbm_ctx* c)
 {
-    return (c && c->fused) ? kNumFusedVariants + kNumRingVariants : 1;
+    if (!c || !c->fused) return 1;
+    return c->p.scheme <= LBM_CD6 ? kNumFusedVariants + kNumRingVariants : kNumRingVariants;
 }
 
 int lbm_set_variant(lbm_ctx* c, int v)
@@ -647,9 +681,8 @@ struct lbm_batch {
     BInst* d_inst = nullptr;
     BState* d_st = nullptr;
     int* d_blk_inst = nullptr;
-    int* d_line_inst[2] = { nullptr, nullptr };
     double* d_partial = nullptr;
-    int nblk_total = 0, nline_total[2] = { 0, 0 };
+    int nblk_total = 0;
     int has_compact = 0;
     int grid = 0;          // workgroups of the cooperative launch (0: all resident)
     int max_grid = 0;
@@ -682,14 +715,14 @@ int compact_conv(int scheme, double* c)
 struct BatchLayout {
     std::vector<size_t> inst_off;
     size_t tables, total;
-    int nblk, nline[2];
+    int nblk;
 };
 
 bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
 {
     size_t off = 0;
     B.inst_off.resize(n);
-    B.nblk = 0; B.nline[0] = B.nline[1] = 0;
+    B.nblk = 0;
     for (int i = 0; i < n; ++i) {
         if (const char* w = validate(&ps[i])) { *why = w; return false; }
         if (ps[i].lattice != LBM_D2Q9) { *why = "the batched sweep runs D2Q9 instances"; return false; }
@@ -697,15 +730,11 @@ bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
         off = align_up(off + layout_of(&ps[i]).total);
         const long long N = (long long)ps[i].nx * ps[i].ny;
         B.nblk += (int)((N + BNODES - 1) / BNODES);
-        B.nline[0] += ps[i].ny * ((ps[i].nx + 63) / 64);
-        B.nline[1] += ps[i].nx * ((ps[i].ny + 63) / 64);
     }
     B.tables = off;
     off = align_up(off + sizeof(BInst) * n);
     off = align_up(off + sizeof(BState) * n);
     off = align_up(off + sizeof(int) * B.nblk);
-    off = align_up(off + sizeof(int) * B.nline[0]);
-    off = align_up(off + sizeof(int) * B.nline[1]);
     off = align_up(off + sizeof(double) * B.nblk);
     off = align_up(off + sizeof(double) * 4 * kConvMax);
     B.total = off;
@@ -751,7 +780,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     b->ws = static_cast<char*>(d_workspace);
     b->ctx.assign(n, nullptr);
     b->inst.resize(n);
-    std::vector<int> blk_inst, line_inst[2];
+    std::vector<int> blk_inst;
     int rc = LBM_OK;
     for (int i = 0; i < n && rc == LBM_OK; ++i) {
         lbm_ctx* c = nullptr;
@@ -768,18 +797,12 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         I.S[0] = c->S[0]; I.S[1] = c->S[1];
         I.rho = c->rhob[0]; I.mu = c->mu;
         I.grho = c->grho; I.gmu = c->gmu; I.lap = c->lap; I.wtmp = c->wtmp;
-        I.lines[0] = c->lines[0]; I.lines[1] = c->lines[1];
         I.cc = compact_scheme(ps[i].scheme);
         I.z = c->z; I.zscale = c->zscale;
         I.blk0 = (int)blk_inst.size();
         I.nblk = (int)((c->g.N + BNODES - 1) / BNODES);
         for (int k = 0; k < I.nblk; ++k) blk_inst.push_back(i);
         I.part0 = I.blk0;
-        for (int d = 0; d < 2; ++d) {
-            I.line0[d] = (int)line_inst[d].size();
-            I.nline[d] = c->lines[d].n1 * c->lines[d].n2 * c->lines[d].nch;
-            for (int k = 0; k < I.nline[d]; ++k) line_inst[d].push_back(i);
-        }
         if (ps[i].scheme >= LBM_OCFDS4) b->has_compact = 1;
     }
     if (rc != LBM_OK) { std::string e = b->err; lbm_batch_free(b); return bfail(nullptr, rc, e); }
@@ -787,8 +810,6 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     b->d_inst = reinterpret_cast<BInst*>(b->ws + off); off = align_up(off + sizeof(BInst) * n);
     b->d_st = reinterpret_cast<BState*>(b->ws + off); off = align_up(off + sizeof(BState) * n);
     b->d_blk_inst = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nblk);
-    b->d_line_inst[0] = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nline[0]);
-    b->d_line_inst[1] = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nline[1]);
     b->d_partial = reinterpret_cast<double*>(b->ws + off); off = align_up(off + sizeof(double) * B.nblk);
     double* d_conv = reinterpret_cast<double*>(b->ws + off);
     std::vector<double> conv(4 * kConvMax, 0.0);
@@ -805,8 +826,6 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         }
     }
     b->nblk_total = (int)blk_inst.size();
-    b->nline_total[0] = (int)line_inst[0].size();
-    b->nline_total[1] = (int)line_inst[1].size();
     std::vector<BState> st(n);
     for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.U = 0.0; x.U_prev = 0.0; }
     hipError_t e = hipMemcpyAsync(d_conv, conv.data(), sizeof(double) * conv.size(), hipMemcpyHostToDevice, b->stream);
@@ -814,9 +833,6 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_st, st.data(), sizeof(BState) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_blk_inst, blk_inst.data(), sizeof(int) * blk_inst.size(),
                                             hipMemcpyHostToDevice, b->stream);
-    for (int d = 0; d < 2 && e == hipSuccess; ++d)
-        e = hipMemcpyAsync(b->d_line_inst[d], line_inst[d].data(), sizeof(int) * line_inst[d].size(),
-                           hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     int per_cu = 0, dev = 0, ncu = 0;
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BNODES, 0);
@@ -855,9 +871,7 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
         BatchArgs a;
         a.inst = b->d_inst; a.st = b->d_st; a.ninst = b->n;
         a.nblk_total = b->nblk_total;
-        a.nline_total[0] = b->nline_total[0]; a.nline_total[1] = b->nline_total[1];
         a.blk_inst = b->d_blk_inst;
-        a.line_inst[0] = b->d_line_inst[0]; a.line_inst[1] = b->d_line_inst[1];
         a.partial = b->d_partial;
         a.has_compact = b->has_compact;
         a.nsteps = (int)todo;

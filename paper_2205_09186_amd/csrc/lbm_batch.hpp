@@ -29,13 +29,11 @@ struct BInst {
     double one_m_omega;
     Eos eos;
     double *S[2], *rho, *mu, *grho, *gmu, *lap, *wtmp;
-    LineGeom lines[2];
     Compact cc;
     double z, zscale;
     const double* cconv;    // compact derivative as a periodic convolution: c_1..c_M
     int M;
     int blk0, nblk;         // node-block items [blk0, blk0 + nblk)
-    int line0[2], nline[2]; // line-chunk items per axis
     int part0;              // first partial slot of its node blocks
 };
 
@@ -97,9 +95,7 @@ struct BatchArgs {
     BState* st;
     int ninst;
     int nblk_total;           // node-block items over all instances
-    int nline_total[2];       // line-chunk items per axis over all instances
     int* blk_inst;            // node-block item -> instance
-    int* line_inst[2];        // line item -> instance
     double* partial;          // one max |v| per node-block item
     int has_compact;
     int nsteps;

@@ -296,9 +296,13 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
     // and the own column is pushed from LDS; plane p - R is computed from its
     // slot, and R + 2 slots keep each read ahead of the overwrite that follows
     // the next barrier.
-    constexpr bool SLOTS = DIM == 3 && NF == 2;
+    // The isotropic schemes (Eq 25) reach diagonal neighbours in z as well:
+    // all 2R + 1 planes of the stencil are staged (2R + 2 slots), the march
+    // starts R planes early and every arm is read from LDS.
+    constexpr bool ISO = is_iso(SCH);
+    constexpr bool SLOTS = DIM == 3 && (NF == 2 || ISO);
     constexpr int LAG = SLOTS ? R : 0;
-    constexpr int NS = SLOTS ? R + 2 : 2;
+    constexpr int NS = SLOTS ? (ISO ? 2 * R + 2 : R + 2) : 2;
     constexpr int QZ = DIM == 3 ? 2 * R + 1 : 1;
     constexpr double cs2 = 1.0 / 3.0;
     __shared__ double sp[NS][NF][CELLS];
@@ -339,7 +343,7 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
     for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int k = 0; k < QZ; ++k) q[f][k] = 0.0;
-    if constexpr (DIM == 3) {
+    if constexpr (DIM == 3 && !ISO) {
         if (in) {
 #pragma unroll
             for (int f = 0; f < NF; ++f)
@@ -361,10 +365,11 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
             }
         }
     };
-    const int pe = z1 - 1 + LAG;   // last plane staged
-    fetch(z0);
-    for (int p = z0; p <= pe; ++p) {
-        double (*s)[CELLS] = sp[(p - z0) % NS];
+    const int pe = z1 - 1 + LAG;                        // last plane staged
+    const int pb = DIM == 3 && ISO ? z0 - R : z0;       // first plane staged
+    fetch(pb);
+    for (int p = pb; p <= pe; ++p) {
+        double (*s)[CELLS] = sp[(p - pb) % NS];
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -380,7 +385,7 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
         }
         if (p < pe) fetch(p + 1);
         __syncthreads();
-        if constexpr (SLOTS) {
+        if constexpr (SLOTS && !ISO) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
 #pragma unroll
@@ -390,9 +395,52 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
         }
         if (p < z0 + LAG || !in) continue;
         const int z = p - LAG;
-        double (*c)[CELLS] = sp[(z - z0) % NS];
+        double (*c)[CELLS] = sp[(z - pb) % NS];
         const unsigned n = (unsigned)(z * nxy + col);
-        if constexpr (NF == 1) {
+        if constexpr (ISO) {
+            // the stencil of lap_at / grad_at (Eq 25), shell weights by |e|^2,
+            // planes z - R .. z + R from their slots
+            constexpr int RZ = DIM == 3 ? R : 0;
+            auto at = [&](int f, int dx, int dy, int dz) -> double {
+                return sp[(z + dz - pb) % NS][f][c0 + dy * WR + dx];
+            };
+            if constexpr (NF == 1) {
+                const double f0 = c[0][c0];
+                double acc = 0.0;
+#pragma unroll
+                for (int dz = -RZ; dz <= RZ; ++dz)
+#pragma unroll
+                    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+                        for (int dx = -R; dx <= R; ++dx) {
+                            const int sh = dx * dx + dy * dy + dz * dz;
+                            const double w = iso_w(DIM, SCH, sh);
+                            if (sh == 0 || w == 0.0) continue;
+                            acc += w * (at(0, dx, dy, dz) - f0);
+                        }
+                st32(out, n, mu_bulk(f0, e) - e.kappa * (2.0 * acc));
+            } else {
+                double grx = 0.0, gry = 0.0, grz = 0.0, gmx = 0.0, gmy = 0.0, gmz = 0.0;
+#pragma unroll
+                for (int dz = -RZ; dz <= RZ; ++dz)
+#pragma unroll
+                    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+                        for (int dx = -R; dx <= R; ++dx) {
+                            const int sh = dx * dx + dy * dy + dz * dz;
+                            const double w = iso_w(DIM, SCH, sh);
+                            if (sh == 0 || w == 0.0) continue;
+                            const double vr = w * at(0, dx, dy, dz), vm = w * at(1, dx, dy, dz);
+                            if (dx) { grx += dx * vr; gmx += dx * vm; }
+                            if (dy) { gry += dy * vr; gmy += dy * vm; }
+                            if (dz) { grz += dz * vr; gmz += dz * vm; }
+                        }
+                const double r = c[0][c0];
+                st32(out, n, -r * gmx + cs2 * grx);
+                st32(out + N, n, -r * gmy + cs2 * gry);
+                if constexpr (DIM == 3) st32(out + 2 * (size_t)N, n, -r * gmz + cs2 * grz);
+            }
+        } else if constexpr (NF == 1) {
             const double f0 = c[0][c0];
             double acc = DIM * d2(SCH, 0) * f0;
 #pragma unroll

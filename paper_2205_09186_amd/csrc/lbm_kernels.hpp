@@ -398,9 +398,24 @@ __global__ void __launch_bounds__(256) k_compact_fwd(const double* __restrict__ 
     }
 }
 
-// Backward recursion y_i = w_i + z y_{i+1}, out = scale * y (or += ).
-__global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ w, double* __restrict__ out,
-                                                     LineGeom lg, double z, double scale, int accumulate)
+// What the last pass of a compact derivative D g writes at node o.
+enum CompactOut { C_STORE = 0, C_ADD = 1, C_FORCE = 2 };
+struct CompactSink {
+    double* out;
+    int mode;             // C_STORE: out = D g; C_ADD: out += D g;
+    const double* rho;    // C_FORCE: out = -rho D mu_hat + cs^2 G[rho] (Eq 12), g = mu_hat,
+    const double* grad;   //          grad = the same component of G[rho]
+    __device__ __forceinline__ void put(long long o, double d) const
+    {
+        if (mode == C_FORCE) out[o] = -rho[o] * d + (1.0 / 3.0) * grad[o];
+        else if (mode == C_ADD) out[o] += d;
+        else out[o] = d;
+    }
+};
+
+// Backward recursion y_i = w_i + z y_{i+1}; the sink receives scale * y.
+__global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ w, CompactSink sink,
+                                                     LineGeom lg, double z, double scale)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nl = (long long)lg.n1 * lg.n2;
@@ -420,10 +435,7 @@ __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ 
 #pragma unroll 4
     for (int i = i0; i >= start; --i) {
         acc = w[base + im * sa] + z * acc;
-        if (i < end) {
-            const long long o = base + im * sa;
-            out[o] = accumulate ? out[o] + scale * acc : scale * acc;
-        }
+        if (i < end) sink.put(base + im * sa, scale * acc);
         im = im == 0 ? n - 1 : im - 1;
     }
 }
@@ -437,8 +449,8 @@ __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ 
 // backward sweep.  zp[k] = z^(k+1), k < 64.
 constexpr int kScanWarm = 128;
 
-__global__ void __launch_bounds__(256) k_compact_x(const double* __restrict__ f, double* __restrict__ out, int nx,
-                                                   long long nrows, Compact c, double z, double scale, int accumulate)
+__global__ void __launch_bounds__(256) k_compact_x(const double* __restrict__ f, CompactSink sink, int nx,
+                                                   long long nrows, Compact c, double z, double scale)
 {
     extern __shared__ double wrow[];
     const int lane = threadIdx.x & 63;
@@ -490,10 +502,7 @@ __global__ void __launch_bounds__(256) k_compact_x(const double* __restrict__ f,
         const int x = valid ? pmod(q, nx) : 0;
         const double a = scan(valid ? wb[x] : 0.0, carry);
         carry = __shfl(a, 63, 64);
-        if (valid && q < nx) {
-            double* o = out + row * nx + x;
-            *o = accumulate ? *o + scale * a : scale * a;
-        }
+        if (valid && q < nx) sink.put(row * nx + x, scale * a);
     }
 }
 

@@ -158,7 +158,10 @@ def test_deterministic_repeat(L, orc):
 @pytest.mark.parametrize("variant", [0, -1])
 @pytest.mark.parametrize("lat,shape,scheme", [(0, (70, 130), "CD6"), (0, (45, 64), "CD4"), (0, (8, 200), "CD2"),
                                               (1, (33, 20, 70), "CD6"), (1, (10, 13, 9), "CD4"),
-                                              (1, (40, 8, 66), "CD2"), (1, (70, 4, 5), "CD6")])
+                                              (1, (40, 8, 66), "CD2"), (1, (70, 4, 5), "CD6"),
+                                              (0, (45, 64), "E8"), (1, (20, 22, 18), "E4"), (1, (12, 9, 11), "E8"),
+                                              (0, (50, 44), "OCFDS4"), (1, (18, 20, 22), "CFDS6"),
+                                              (1, (9, 12, 70), "OCFDS4")])
 def test_fused_equals_unfused(L, orc, lat, shape, scheme, variant, monkeypatch):
     """The fused collide kernel (tile + recomputed ring, LDS exchange for the
     next density) against the plain node-parallel kernels: same state to
@@ -188,8 +191,11 @@ def test_step_timed_phases(L, orc):
     assert s.steps_done == 3
 
 
-@pytest.mark.parametrize("lat,shape,tau", [(1, (37, 21, 70), 1.0), (0, (50, 131), 1.0), (1, (37, 21, 70), 0.85)])
-def test_launch_variants_identical(L, orc, lat, shape, tau):
+@pytest.mark.parametrize("lat,shape,tau,scheme,designs", [(1, (37, 21, 70), 1.0, "CD6", 2), (0, (50, 131), 1.0, "CD6", 2),
+                                                           (1, (37, 21, 70), 0.85, "CD6", 2),
+                                                           (1, (21, 17, 70), 1.0, "OCFDS4", 1),
+                                                           (0, (50, 131), 0.9, "E8", 1)])
+def test_launch_variants_identical(L, orc, lat, shape, tau, scheme, designs):
     """Launch variants of one kernel design (tile height, register budget)
     compute the same node arithmetic in the same order: bitwise equal.  The
     designs differ only in where the force is formed (inside the collide
@@ -197,7 +203,7 @@ def test_launch_variants_identical(L, orc, lat, shape, tau):
     g, l = orc.maxwell(0.8)
     rho0 = inputs.droplet(shape, min(shape) / 4, 4.0, g, l)
     nz, ny, nx = ((1,) + shape) if lat == 0 else shape
-    p = L.Params(lattice=lat, nx=nx, ny=ny, nz=nz, Tr=0.8, scheme=L.CD6, tau=tau)
+    p = L.Params(lattice=lat, nx=nx, ny=ny, nz=nz, Tr=0.8, scheme=L.SCHEMES[scheme], tau=tau)
     ref = {}
     for v in range(L.Simulation(p, rho0).num_variants):
         s = L.Simulation(p, rho0)
@@ -209,9 +215,10 @@ def test_launch_variants_identical(L, orc, lat, shape, tau):
             ref[design] = f
         else:
             assert np.array_equal(f, ref[design]), (v, design)
-    assert len(ref) == 2, list(ref)
-    a, b = ref.values()
-    assert np.abs(a - b).max() < 1e-13
+    assert len(ref) == designs, list(ref)
+    if designs == 2:
+        a, b = ref.values()
+        assert np.abs(a - b).max() < 1e-13
 
 
 @pytest.mark.parametrize("lat,shape,scheme", [(0, (100, 100), "CD4"), (1, (20, 24, 28), "CD6"),
