@@ -175,12 +175,13 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
 {
     const LineGeom& lg = c->lines[d];
     const Compact cc = compact_scheme(c->p.scheme);
-    if (d == 0 && lg.n <= 8192 && lg.K <= kScanWarm) {
-        // whole rows, one wavefront each, forward results of the row in LDS
-        const int waves = lg.n <= 2048 ? 4 : 1;
+    if (d == 0 && lg.n <= 4096 && lg.K <= kScanWarm) {
+        // whole rows, one wavefront each, the row and its forward results in
+        // LDS (2 nx doubles per wavefront, at most 64 KiB per workgroup)
+        const int waves = lg.n <= 1024 ? 4 : 1;
         const long long rows = (long long)lg.n1 * lg.n2;
         hipLaunchKernelGGL(k_compact_x, dim3((unsigned)((rows + waves - 1) / waves)), dim3(64 * waves),
-                           sizeof(double) * waves * lg.n, c->stream, in, sink, lg.n, rows, cc, c->z, c->zscale);
+                           sizeof(double) * waves * 2 * lg.n, c->stream, in, sink, lg.n, rows, cc, c->z, c->zscale);
         return;
     }
     const long long items = (long long)lg.n1 * lg.n2 * lg.nch;

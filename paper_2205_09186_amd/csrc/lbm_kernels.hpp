@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(256) k_compact_fwd(const double* __restrict__ 
     int jn = pmod((long long)i0 + 4, n);   // next point entering the window
     int im = pmod(i0, n);                  // current point
     double acc = 0.0;
-#pragma unroll 4
+#pragma unroll 8
     for (int i = i0; i < end; ++i) {
         const double v = ha * (r[4] - r[2]) + hb * (r[5] - r[1]) + hc * (r[6] - r[0]);
         acc = v + z * acc;
@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ 
     const int i0 = end - 1 + lg.K;
     int im = pmod(i0, n);
     double acc = 0.0;
-#pragma unroll 4
+#pragma unroll 8
     for (int i = i0; i >= start; --i) {
         acc = w[base + im * sa] + z * acc;
         if (i < end) sink.put(base + im * sa, scale * acc);
@@ -441,12 +441,12 @@ __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ 
 }
 
 // Compact derivative along x (unit stride) of whole rows: one wavefront per
-// row, lanes along x.  Both recursions run as wavefront-wide scans over chunks
-// of 64 consecutive points (the recursion a_i = v_i + z a_{i-1} in log2(64)
-// shuffle steps, plus z^(lane+1) times the carry from the previous chunk), so
-// every load and store is coalesced.  The sweep starts W >= K points early
-// (periodic positions), the forward results of the row sit in LDS for the
-// backward sweep.  zp[k] = z^(k+1), k < 64.
+// row, lanes along x.  The row is first staged in LDS (all its loads in
+// flight at once).  Both recursions then run as wavefront-wide scans over
+// chunks of 64 consecutive points (a_i = v_i + z a_{i-1} in log2(64) shuffle
+// steps, plus z^(lane+1) times the carry from the previous chunk).  The sweep
+// starts W >= K points early (periodic positions); the forward results of the
+// row replace nothing and sit in a second LDS row for the backward sweep.
 constexpr int kScanWarm = 128;
 
 __global__ void __launch_bounds__(256) k_compact_x(const double* __restrict__ f, CompactSink sink, int nx,
@@ -457,8 +457,12 @@ __global__ void __launch_bounds__(256) k_compact_x(const double* __restrict__ f,
     const int wv = threadIdx.x >> 6;
     const long long row = (long long)blockIdx.x * (blockDim.x >> 6) + wv;
     if (row >= nrows) return;   // whole wavefront leaves; no block barrier below
-    double* wb = wrow + (size_t)wv * nx;
-    const double* fr = f + row * nx;
+    double* fr = wrow + (size_t)wv * 2 * nx;   // the row of f
+    double* wb = fr + nx;                       // forward results
+    for (int x = lane; x < nx; x += 64) fr[x] = f[row * nx + x];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const double ha = 0.5 * c.ca, hb = 0.25 * c.cb, hc = c.cc / 6.0;
     double zs[7];    // z^(2^s)
     zs[0] = z;
