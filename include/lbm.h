@@ -7,9 +7,12 @@
  *   2. mu_hat = k^2 psi'(rho) - kappa_hat lap(rho), Peng-Robinson psi'  (Eq 14-16)
  *   3. F = -rho grad(mu_hat) + cs^2 grad(rho)                           (Eq 12)
  *      with grad/lap from the chosen difference scheme                  (Sec 2.3)
- *   4. SRT collision with exact-difference forcing, du = F / rho:
+ *   4. collision with exact-difference forcing, du = F / rho, either SRT
  *      f*_i = f_i - (f_i - feq_i(rho,u))/tau + feq_i(rho,u+du) - feq_i(rho,u)
  *                                                          (Eq 1 with s_i = 1/tau, Eq 6, Eq 8)
+ *      or, for D2Q9, the MRT form of Eq 1 with the moment basis M of Eq 3
+ *      and the diagonal S of Eq 5:
+ *      f* = f - M^-1 S (M f - M feq(rho,u)) + feq(rho,u+du) - feq(rho,u)
  *   5. streaming f_i(x + e_i, t + 1) = f*_i(x, t), all axes periodic    (Eq 1)
  * Observables use the actual fluid velocity v = u + F/(2 rho) (after Eq 8);
  * the spurious current is max |v| over the domain (Sec 3.3).
@@ -55,6 +58,9 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
 enum { LBM_CD2 = 0, LBM_CD4 = 1, LBM_CD6 = 2, LBM_E4 = 3, LBM_E8 = 4,
        LBM_OCFDS4 = 5, LBM_CFDS4 = 6, LBM_CFDS6 = 7, LBM_CFDS8 = 8 };
 
+/* Collision operators of Eq 1. */
+enum { LBM_SRT = 0, LBM_MRT = 1 };
+
 enum { LBM_OK = 0, LBM_EINVAL = -1, LBM_ENOSPC = -2, LBM_EHIP = -3,
        LBM_ENONFINITE = -4, LBM_ESTATE = -5 };
 
@@ -68,6 +74,11 @@ typedef struct {
     int    scheme;           /* LBM_CD2 .. LBM_CFDS8 */
     double a, b, R, omega;   /* Peng-Robinson constants of Eq 14; 0 selects the
                                 paper's a = 2/49, b = 2/21, R = 1, omega = 0.344 */
+    int    collision;        /* LBM_SRT (0) or LBM_MRT (D2Q9 only) */
+    double s_e, s_eps, s_q;  /* MRT rates of the energy, energy-square and heat-flux
+                                moments, each in (0, 2); 0 selects Sec 2.1's 1.64,
+                                1.54 and 1.7.  Density and momentum relax with 1,
+                                the stresses with 1/tau. */
 } lbm_params;
 
 /* Bytes of device workspace lbm_init() needs for these parameters (0 if the

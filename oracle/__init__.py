@@ -46,7 +46,8 @@ class _Params(C.Structure):
                 ("tau", C.c_double), ("Tr", C.c_double), ("k", C.c_double),
                 ("kappa", C.c_double), ("scheme", C.c_int),
                 ("a", C.c_double), ("b", C.c_double), ("R", C.c_double),
-                ("omega", C.c_double)]
+                ("omega", C.c_double), ("collision", C.c_int), ("s_e", C.c_double),
+                ("s_eps", C.c_double), ("s_q", C.c_double)]
 
 
 _lib = None
@@ -66,6 +67,8 @@ def lib():
         L.orc_lattice_info.argtypes = [C.c_int, ip, dp]
         L.orc_lattice_info.restype = C.c_int
         L.orc_collide_node.argtypes = [C.c_int, D, dp, D, D, D, dp]
+        L.orc_collide_node_mrt.argtypes = [D, D, D, D, dp, D, D, D, dp]
+        L.orc_mrt_matrix.argtypes = [dp, dp]
         L.orc_pr_alpha.argtypes = [D, D]; L.orc_pr_alpha.restype = D
         L.orc_pr_p0.argtypes = [D, D, D, D, D]; L.orc_pr_p0.restype = D
         L.orc_pr_mub.argtypes = [D, D, D, D, D]; L.orc_pr_mub.restype = D
@@ -125,6 +128,24 @@ def collide_node(lat: int, tau: float, f, F) -> np.ndarray:
     Fx, Fy, Fz = (list(F) + [0.0, 0.0, 0.0])[:3]
     lib().orc_collide_node(lat, tau, f, Fx, Fy, Fz, out)
     return out
+
+
+def collide_node_mrt(tau: float, f, F, s_e: float = 0.0, s_eps: float = 0.0, s_q: float = 0.0) -> np.ndarray:
+    """D2Q9 MRT collision with EDM forcing at one node (Eq 1, 3, 4, 5, 8);
+    rates 0 select the values of Sec 2.1."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    Fx, Fy = (list(F) + [0.0, 0.0])[:2]
+    lib().orc_collide_node_mrt(tau, s_e or 1.64, s_eps or 1.54, s_q or 1.7, f, Fx, Fy, 0.0, out)
+    return out
+
+
+def mrt_matrix():
+    """(M of Eq 3, the oracle's numerical inverse of it)."""
+    M = np.zeros(81)
+    Mi = np.zeros(81)
+    lib().orc_mrt_matrix(M, Mi)
+    return M.reshape(9, 9), Mi.reshape(9, 9)
 
 
 def pr_alpha(Tr: float, omega: float = PR_OMEGA) -> float:
@@ -229,6 +250,10 @@ class Params:
     b: float = PR_B
     R: float = PR_R
     omega: float = PR_OMEGA
+    collision: int = 0          # 0 SRT, 1 MRT (D2Q9)
+    s_e: float = 0.0
+    s_eps: float = 0.0
+    s_q: float = 0.0
 
     @property
     def q(self) -> int:
@@ -240,7 +265,8 @@ class Params:
 
     def c(self) -> _Params:
         return _Params(self.lattice, self.nx, self.ny, self.nz, self.tau, self.Tr, self.k,
-                       self.kappa, self.scheme, self.a, self.b, self.R, self.omega)
+                       self.kappa, self.scheme, self.a, self.b, self.R, self.omega, self.collision,
+                       self.s_e, self.s_eps, self.s_q)
 
 
 class Sim:

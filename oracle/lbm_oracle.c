@@ -15,7 +15,10 @@
  *   - the state f is the post-streaming distribution at time t.
  *
  * Readings where the paper is silent (each listed in the design notes):
- *   - collision is the SRT (BGK) reduction of Eq 1 with every s_i = 1/tau;
+ *   - collision is either the SRT (BGK) reduction of Eq 1 with every
+ *     s_i = 1/tau, or (D2Q9 only) the MRT form of Eq 1 with the M of Eq 3 and
+ *     the rates of Sec 2.1 (s_e = 1.64, s_eps = 1.54, s_q = 1.7, s_nu = 1/tau,
+ *     rate 1 on the conserved moments);
  *   - force is Eq 12 in full, F = -rho grad(mu) + cs^2 grad(rho);
  *   - k enters only through k^2 psi'(rho) (Eq 16); kappa-hat is a parameter;
  *   - Laplacian of the explicit central schemes is the matched-order central
@@ -60,6 +63,9 @@ typedef struct {
     double kappa;           /* kappa-hat of Eq 16 */
     int scheme;             /* ORC_CD2 ... */
     double a, b, R, omega;  /* Peng-Robinson constants (Sec 2.2) */
+    int collision;          /* 0: SRT; 1: MRT (D2Q9, Eq 1, 3, 5) */
+    double s_e, s_eps, s_q; /* MRT rates of the energy, energy-square and heat-flux
+                               moments; 0 selects the values of Sec 2.1 */
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -176,6 +182,103 @@ void orc_collide_node(int lattice, double tau, const double *f,
     orc_lattice L; get_lattice(lattice, &L);
     double F[3] = { Fx, Fy, Fz };
     collide_node(&L, tau, f, F, fout);
+}
+
+/* ------------------------------------------------------------------------- */
+/* MRT collision of Eq 1 for D2Q9                                              */
+/* ------------------------------------------------------------------------- */
+
+/* The transformation matrix of Eq 3, rows = moments (rho, e, eps, j_x, q_x,
+ * j_y, q_y, p_xx, p_xy), columns = the directions of Eq 2. */
+static const double MRT_M[9][9] = {
+    {  1,  1,  1,  1,  1,  1,  1,  1,  1 },
+    { -4, -1, -1, -1, -1,  2,  2,  2,  2 },
+    {  4, -2, -2, -2, -2,  1,  1,  1,  1 },
+    {  0,  1,  0, -1,  0,  1, -1, -1,  1 },
+    {  0, -2,  0,  2,  0,  1, -1, -1,  1 },
+    {  0,  0,  1,  0, -1,  1,  1, -1, -1 },
+    {  0,  0, -2,  0,  2,  1,  1, -1, -1 },
+    {  0,  1, -1,  1, -1,  0,  0,  0,  0 },
+    {  0,  0,  0,  0,  0,  1, -1,  1, -1 },
+};
+
+/* M^-1 by Gauss-Jordan elimination with partial pivoting (computed once). */
+static double MRT_MINV[9][9];
+static int mrt_ready = 0;
+
+static void mrt_setup(void)
+{
+    double a[9][18];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 18; ++c) a[r][c] = c < 9 ? MRT_M[r][c] : (c - 9 == r ? 1.0 : 0.0);
+    for (int col = 0; col < 9; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 9; ++r) if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+        for (int c = 0; c < 18; ++c) { double t = a[col][c]; a[col][c] = a[piv][c]; a[piv][c] = t; }
+        double d = a[col][col];
+        for (int c = 0; c < 18; ++c) a[col][c] /= d;
+        for (int r = 0; r < 9; ++r) {
+            if (r == col) continue;
+            double m = a[r][col];
+            for (int c = 0; c < 18; ++c) a[r][c] -= m * a[col][c];
+        }
+    }
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) MRT_MINV[r][c] = a[r][c + 9];
+    mrt_ready = 1;
+}
+
+/* The diagonal S of Eq 5 in the row order of M: s_1 = s_4 = s_6 = 1 (rho and
+ * j, whose non-equilibrium parts vanish), s_2 = s_e, s_3 = s_eps,
+ * s_5 = s_7 = s_q, s_8 = s_9 = 1/tau (Sec 2.1). */
+static void mrt_rates(double tau, double s_e, double s_eps, double s_q, double S[9])
+{
+    S[0] = 1.0; S[1] = s_e; S[2] = s_eps; S[3] = 1.0; S[4] = s_q;
+    S[5] = 1.0; S[6] = s_q; S[7] = 1.0 / tau; S[8] = 1.0 / tau;
+}
+
+/* One node:  m = M f,  m_eq = M f_eq(rho, u)  (Eq 4),
+ *   f* = f - M^-1 S (m - m_eq) + [feq(rho, u + du) - feq(rho, u)]   (Eq 1, 8). */
+static void collide_node_mrt(const orc_lattice *L, const double S[9], const double *f,
+                             const double F[3], double *fout)
+{
+    if (!mrt_ready) mrt_setup();
+    double rho = 0.0, j[3] = { 0.0, 0.0, 0.0 };
+    for (int i = 0; i < 9; ++i) {
+        rho += f[i];
+        for (int d = 0; d < 3; ++d) j[d] += L->e[i][d] * f[i];
+    }
+    double u[3], up[3], fe[9], fs[9];
+    for (int d = 0; d < 3; ++d) { u[d] = j[d] / rho; up[d] = u[d] + F[d] / rho; }
+    for (int i = 0; i < 9; ++i) { fe[i] = feq_i(L, i, rho, u); fs[i] = feq_i(L, i, rho, up); }
+    double m[9], meq[9], r[9];
+    for (int k = 0; k < 9; ++k) {
+        m[k] = 0.0; meq[k] = 0.0;
+        for (int i = 0; i < 9; ++i) { m[k] += MRT_M[k][i] * f[i]; meq[k] += MRT_M[k][i] * fe[i]; }
+        r[k] = S[k] * (m[k] - meq[k]);
+    }
+    for (int i = 0; i < 9; ++i) {
+        double back = 0.0;
+        for (int k = 0; k < 9; ++k) back += MRT_MINV[i][k] * r[k];
+        fout[i] = f[i] - back + (fs[i] - fe[i]);
+    }
+}
+
+void orc_collide_node_mrt(double tau, double s_e, double s_eps, double s_q, const double *f,
+                          double Fx, double Fy, double Fz, double *fout)
+{
+    orc_lattice L; get_lattice(ORC_D2Q9, &L);
+    double F[3] = { Fx, Fy, Fz }, S[9];
+    mrt_rates(tau, s_e, s_eps, s_q, S);
+    collide_node_mrt(&L, S, f, F, fout);
+}
+
+/* The matrix of Eq 3 and the inverse used above, for the tests. */
+void orc_mrt_matrix(double *M, double *Minv)
+{
+    if (!mrt_ready) mrt_setup();
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) { M[9 * r + c] = MRT_M[r][c]; Minv[9 * r + c] = MRT_MINV[r][c]; }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -743,7 +846,15 @@ static int check_params(const orc_params *p)
     if (!(p->Tr > 0.0 && p->Tr < 1.0)) return -1;
     if (!(p->k > 0.0) || !(p->kappa > 0.0)) return -1;
     if (p->scheme < 0 || p->scheme >= ORC_NSCHEMES) return -1;
+    if (p->collision != 0 && p->collision != 1) return -1;
+    if (p->collision == 1 && p->lattice != ORC_D2Q9) return -1;
     return 0;
+}
+
+static void rates_of(const orc_params *p, double S[9])
+{
+    mrt_rates(p->tau, p->s_e > 0.0 ? p->s_e : 1.64, p->s_eps > 0.0 ? p->s_eps : 1.54,
+              p->s_q > 0.0 ? p->s_q : 1.7, S);
 }
 
 typedef struct {
@@ -828,6 +939,9 @@ int orc_step(const orc_params *p, const double *f, double *fout)
     double *j = (double *)malloc(sizeof(double) * 3 * N);
     double *F = (double *)malloc(sizeof(double) * 3 * N);
     if (force_fields(p, &L, f, rho, j, F)) { free(rho); free(j); free(F); return -1; }
+    double S[9];
+    rates_of(p, S);
+    if (p->collision == 1 && !mrt_ready) mrt_setup();
     /* 6. collision, 7. streaming f_i(x + e_i, t+1) = f*_i(x, t) */
     #pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < G.nz; ++z)
@@ -837,7 +951,8 @@ int orc_step(const orc_params *p, const double *f, double *fout)
                 double fl[19], fs[19];
                 for (int i = 0; i < L.q; ++i) fl[i] = f[(long)i * N + n];
                 double Fn[3] = { F[n], F[N + n], F[2 * N + n] };
-                collide_node(&L, p->tau, fl, Fn, fs);
+                if (p->collision == 1) collide_node_mrt(&L, S, fl, Fn, fs);
+                else collide_node(&L, p->tau, fl, Fn, fs);
                 for (int i = 0; i < L.q; ++i)
                     fout[(long)i * N + gidx(&G, x + L.e[i][0], y + L.e[i][1], z + L.e[i][2])] = fs[i];
             }

@@ -57,7 +57,25 @@ const char* validate(const lbm_params* p)
     if (!(p->kappa > 0.0) || !std::isfinite(p->kappa)) return "kappa must be > 0";
     if (p->scheme < LBM_CD2 || p->scheme > LBM_CFDS8) return "unknown scheme";
     if (p->a < 0.0 || p->b < 0.0 || p->R < 0.0 || p->omega < 0.0) return "negative EOS constant";
+    if (p->collision != LBM_SRT && p->collision != LBM_MRT) return "unknown collision operator";
+    if (p->collision == LBM_MRT && p->lattice != LBM_D2Q9) return "the MRT collision is defined for D2Q9 (Eq 3)";
+    for (double s : { p->s_e, p->s_eps, p->s_q })
+        if (!(s == 0.0 || (s > 0.0 && s < 2.0))) return "MRT rates must lie in (0, 2) (0 selects the default)";
     return nullptr;
+}
+
+// Relaxation rates of Eq 1: SRT 1/tau; MRT the diagonal S of Eq 5 with the
+// values of Sec 2.1 unless given, divided by the squared row norms of M.
+Relax relax_of(const lbm_params* p)
+{
+    Relax r{};
+    r.omo = 1.0 - 1.0 / p->tau;
+    r.mrt = p->collision == LBM_MRT ? 1 : 0;
+    const double se = p->s_e > 0.0 ? p->s_e : 1.64, seps = p->s_eps > 0.0 ? p->s_eps : 1.54;
+    const double sq = p->s_q > 0.0 ? p->s_q : 1.7, snu = 1.0 / p->tau;
+    const double S[9] = { 1.0, se, seps, 1.0, sq, 1.0, sq, snu, snu };
+    for (int k = 0; k < 9; ++k) r.sd[k] = S[k] / kMrtNorm2[k];
+    return r;
 }
 
 // Element stride between the Q population arrays: N rounded up to 512 bytes
@@ -102,7 +120,7 @@ struct lbm_ctx {
     Grid g;
     Eos eos;
     int Q, dim;
-    double one_m_omega;
+    Relax rx;        // collision of Eq 1 (SRT or D2Q9 MRT)
     hipStream_t stream;
     char* ws;
     Layout L;
@@ -242,7 +260,7 @@ void launch_step(lbm_ctx* c)
             if (c->variant < kNumFusedVariants) {
                 mark(c, "k_fused");
                 launch_fused_collide<LAT, SCH>(c->variant, c->S[c->cur], c->S[1 - c->cur], rho, c->mu,
-                                               c->rhob[1 - c->cur], c->g, c->one_m_omega, c->stream);
+                                               c->rhob[1 - c->cur], c->g, c->rx, c->stream);
                 mark(c, nullptr);
                 c->cur = 1 - c->cur;
                 return;
@@ -259,7 +277,7 @@ void launch_step(lbm_ctx* c)
         }
         mark(c, "k_ring");
         launch_ring_collide<LAT>(CD ? c->variant - kNumFusedVariants : c->variant, c->S[c->cur], c->S[1 - c->cur],
-                                 c->force, c->rhob[1 - c->cur], c->g, c->one_m_omega, c->stream);
+                                 c->force, c->rhob[1 - c->cur], c->g, c->rx, c->stream);
         mark(c, nullptr);
         c->cur = 1 - c->cur;
         return;
@@ -269,7 +287,7 @@ void launch_step(lbm_ctx* c)
     mark(c, "k_collide");
     hipLaunchKernelGGL((k_collide<LAT, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
                        c->S[c->cur], c->S[1 - c->cur], c->rhob[c->cur], c->mu, c->grho, c->gmu, c->g,
-                       c->one_m_omega);
+                       c->rx);
     mark(c, nullptr);
     c->cur = 1 - c->cur;
 }
@@ -387,7 +405,7 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->result = reinterpret_cast<double*>(c->ws + L.result);
     c->cur = 0;
     c->steps = 0;
-    c->one_m_omega = 1.0 - 1.0 / p->tau;
+    c->rx = relax_of(p);
     c->fused = c->g.N < (1LL << 29) && std::getenv("LBM_NO_FUSED") == nullptr;
     // untuned default for the CD schemes: the ring collide with its own force
     // pass in 3D, the collide that forms the force itself in 2D (fastest of
@@ -793,7 +811,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         BInst& I = b->inst[i];
         I.g = c->g;
         I.scheme = ps[i].scheme;
-        I.one_m_omega = c->one_m_omega;
+        I.rx = c->rx;
         I.eos = c->eos;
         I.S[0] = c->S[0]; I.S[1] = c->S[1];
         I.rho = c->rhob[0]; I.mu = c->mu;

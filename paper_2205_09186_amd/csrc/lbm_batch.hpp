@@ -26,7 +26,7 @@ enum BatchStatus { B_RUNNING = 0, B_CONVERGED = 1, B_DIVERGED = 2 };
 struct BInst {
     Grid g;
     int scheme;
-    double one_m_omega;
+    Relax rx;
     Eos eos;
     double *S[2], *rho, *mu, *grho, *gmu, *lap, *wtmp;
     Compact cc;
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
                 double f[9], r, jx, jy, Fx, Fy, Fz, out[9];
                 b_moments(I, Sc, n, x, y, f, r, jx, jy);
                 b_force_any(I, n, x, y, r, Fx, Fy, Fz);
-                collide<0>(f, r, jx, jy, 0.0, Fx, Fy, Fz, I.one_m_omega, out);
+                collide<0>(f, r, jx, jy, 0.0, Fx, Fy, Fz, I.rx, out);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) Sn[(long long)i * I.g.ps + n] = out[i];
             }

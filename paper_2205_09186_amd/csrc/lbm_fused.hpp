@@ -75,13 +75,14 @@ __device__ __forceinline__ int pwrap(int a, int n)
 // plane of the march the workgroup stages rho and mu_hat of the plane (tile,
 // ring and an R-wide halo) in LDS for the in-plane stencil arms; the z arms
 // come from per-thread register queues of the thread's own column.
-// FULL: tau = 1 (one_m_omega == 0), where f* = feq(rho, u + du) exactly and
+// FULL: SRT with tau = 1 (one_m_omega == 0), where f* = feq(rho, u + du) exactly and
 // the pulled populations are dead once the moments are formed.
 template <int LAT, int SCH, int TY, int OCC, bool PIPE, bool FULL>
 __global__ void __launch_bounds__((FX + 2) * (TY + 2), OCC)
 k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ rho,
-        const double* __restrict__ mu, double* __restrict__ rho_next, Grid g, TileGeom tg, double one_m_omega)
+        const double* __restrict__ mu, double* __restrict__ rho_next, Grid g, TileGeom tg, Relax rx)
 {
+    const double one_m_omega = rx.omo;
     using L = Lat<LAT>;
     constexpr int Q = L::Q;
     constexpr int R = radius(SCH);
@@ -220,6 +221,21 @@ k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __r
             const double vv = 1.0 - 1.5 * (vx * vx + vy * vy + vz * vz);
             const bool store = inner && zr >= z0 && zr < z1;
             const int n = zo + yc + x;
+            double om[LAT == 0 ? 9 : 1];   // MRT post-collision values (D2Q9)
+            if constexpr (LAT == 0 && !FULL) {
+                if (rx.mrt) {
+                    double fe[9], fv[9];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const double wr = L::w(i) * r;
+                        const double eu = L::ex(i) * ux + L::ey(i) * uy;
+                        const double ev = L::ex(i) * vx + L::ey(i) * vy;
+                        fe[i] = wr * (uu + eu * (3.0 + 4.5 * eu));
+                        fv[i] = wr * (vv + ev * (3.0 + 4.5 * ev));
+                    }
+                    mrt_post(f, fe, fv, rx, om);
+                }
+            }
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const double wr = L::w(i) * r;
@@ -227,7 +243,10 @@ k_fused(const double* __restrict__ S, double* __restrict__ Sn, const double* __r
                 const double ev = L::ex(i) * vx + L::ey(i) * vy + L::ez(i) * vz;
                 const double fe = wr * (uu + eu * (3.0 + 4.5 * eu));
                 const double fv = wr * (vv + ev * (3.0 + 4.5 * ev));
-                const double o = FULL ? fv : fv + one_m_omega * (f[i] - fe);
+                double o = FULL ? fv : fv + one_m_omega * (f[i] - fe);
+                if constexpr (LAT == 0 && !FULL) {
+                    if (rx.mrt) o = om[i];
+                }
                 (void)fe;
                 if (store) st32(Sn + (long long)i * g.ps, (unsigned)n, o);
                 if (xcls_of<LAT>(i) >= 0) xs[xcls_of<LAT>(i)][lid] = o;
@@ -499,8 +518,9 @@ inline void launch_force_march(const double* rho, const double* mu, double* F, c
 template <int LAT, int TX, int TY, int OCC, bool PF, bool FULL>
 __global__ void __launch_bounds__((TX + 2) * (TY + 2), OCC)
 k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ F,
-       double* __restrict__ rho_next, Grid g, TileGeom tg, double one_m_omega)
+       double* __restrict__ rho_next, Grid g, TileGeom tg, Relax rx)
 {
+    const double one_m_omega = rx.omo;
     using L = Lat<LAT>;
     constexpr int Q = L::Q;
     constexpr int W = TX + 2, H = TY + 2, NTH = W * H;
@@ -588,6 +608,21 @@ k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
             const double vv = 1.0 - 1.5 * (vx * vx + vy * vy + vz * vz);
             const bool store = inner && zr >= z0 && zr < z1;
             const int n = z * nxy + yc + x;
+            double om[LAT == 0 ? 9 : 1];   // MRT post-collision values (D2Q9)
+            if constexpr (LAT == 0 && !FULL) {
+                if (rx.mrt) {
+                    double fe[9], fv[9];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const double wr = L::w(i) * r;
+                        const double eu = L::ex(i) * ux + L::ey(i) * uy;
+                        const double ev = L::ex(i) * vx + L::ey(i) * vy;
+                        fe[i] = wr * (uu + eu * (3.0 + 4.5 * eu));
+                        fv[i] = wr * (vv + ev * (3.0 + 4.5 * ev));
+                    }
+                    mrt_post(f, fe, fv, rx, om);
+                }
+            }
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const double wr = L::w(i) * r;
@@ -598,6 +633,9 @@ k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
                     const double eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
                     const double fe = wr * (uu + eu * (3.0 + 4.5 * eu));
                     o = fv + one_m_omega * (f[i] - fe);
+                    if constexpr (LAT == 0) {
+                        if (rx.mrt) o = om[i];
+                    }
                 }
                 if (store) st32(Sn + (long long)i * g.ps, (unsigned)n, o);
                 if (xcls_of<LAT>(i) >= 0) xs[xcls_of<LAT>(i)][slot] = o;
@@ -655,29 +693,29 @@ inline TileGeom ring_tiles(int tx, int ty, const Grid& g, bool three_d)
 
 template <int LAT, int TX, int TY, int OCC, bool PF>
 inline void launch_ring_v(const double* S, double* Sn, const double* F, double* rho_next, const Grid& g,
-                          double one_m_omega, hipStream_t st)
+                          const Relax& rx, hipStream_t st)
 {
     const TileGeom t = ring_tiles(TX, TY, g, LAT == 1);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
-    if (one_m_omega == 0.0)
+    if (rx.omo == 0.0 && !rx.mrt)
         hipLaunchKernelGGL((k_ring<LAT, TX, TY, OCC, PF, true>), dim3(nb), dim3((TX + 2) * (TY + 2)), 0, st, S, Sn, F,
-                           rho_next, g, t, one_m_omega);
+                           rho_next, g, t, rx);
     else
         hipLaunchKernelGGL((k_ring<LAT, TX, TY, OCC, PF, false>), dim3(nb), dim3((TX + 2) * (TY + 2)), 0, st, S, Sn, F,
-                           rho_next, g, t, one_m_omega);
+                           rho_next, g, t, rx);
 }
 
 template <int LAT>
 inline void launch_ring_collide(int variant, const double* S, double* Sn, const double* F, double* rho_next,
-                                const Grid& g, double one_m_omega, hipStream_t st)
+                                const Grid& g, const Relax& rx, hipStream_t st)
 {
     switch (variant) {
-    case 1: launch_ring_v<LAT, 64, 8, 3, true>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    case 2: launch_ring_v<LAT, 64, 9, 3, true>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    case 3: launch_ring_v<LAT, 64, 7, 3, true>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    case 4: launch_ring_v<LAT, 64, 13, 2, false>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    case 5: launch_ring_v<LAT, 32, 16, 2, false>(S, Sn, F, rho_next, g, one_m_omega, st); break;
-    default: launch_ring_v<LAT, 64, 8, 3, false>(S, Sn, F, rho_next, g, one_m_omega, st); break;
+    case 1: launch_ring_v<LAT, 64, 8, 3, true>(S, Sn, F, rho_next, g, rx, st); break;
+    case 2: launch_ring_v<LAT, 64, 9, 3, true>(S, Sn, F, rho_next, g, rx, st); break;
+    case 3: launch_ring_v<LAT, 64, 7, 3, true>(S, Sn, F, rho_next, g, rx, st); break;
+    case 4: launch_ring_v<LAT, 64, 13, 2, false>(S, Sn, F, rho_next, g, rx, st); break;
+    case 5: launch_ring_v<LAT, 32, 16, 2, false>(S, Sn, F, rho_next, g, rx, st); break;
+    default: launch_ring_v<LAT, 64, 8, 3, false>(S, Sn, F, rho_next, g, rx, st); break;
     }
 }
 
@@ -694,30 +732,30 @@ constexpr int kNumFusedVariants = 7;
 
 template <int LAT, int SCH, int TY, int OCC, bool PIPE>
 inline void launch_fused_v(const double* S, double* Sn, const double* rho, const double* mu, double* rho_next,
-                           const Grid& g, double one_m_omega, hipStream_t st)
+                           const Grid& g, const Relax& rx, hipStream_t st)
 {
     const TileGeom t = fused_tiles(TY, g, LAT == 1);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
-    if (one_m_omega == 0.0)
+    if (rx.omo == 0.0 && !rx.mrt)
         hipLaunchKernelGGL((k_fused<LAT, SCH, TY, OCC, PIPE, true>), dim3(nb), dim3((FX + 2) * (TY + 2)), 0, st, S,
-                           Sn, rho, mu, rho_next, g, t, one_m_omega);
+                           Sn, rho, mu, rho_next, g, t, rx);
     else
         hipLaunchKernelGGL((k_fused<LAT, SCH, TY, OCC, PIPE, false>), dim3(nb), dim3((FX + 2) * (TY + 2)), 0, st, S,
-                           Sn, rho, mu, rho_next, g, t, one_m_omega);
+                           Sn, rho, mu, rho_next, g, t, rx);
 }
 
 template <int LAT, int SCH>
 inline void launch_fused_collide(int variant, const double* S, double* Sn, const double* rho, const double* mu,
-                                 double* rho_next, const Grid& g, double one_m_omega, hipStream_t st)
+                                 double* rho_next, const Grid& g, const Relax& rx, hipStream_t st)
 {
     switch (variant) {
-    case 1: launch_fused_v<LAT, SCH, 4, 3, false>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
-    case 2: launch_fused_v<LAT, SCH, 6, 3, false>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
-    case 3: launch_fused_v<LAT, SCH, 4, 2, true>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
-    case 4: launch_fused_v<LAT, SCH, 5, 2, true>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
-    case 5: launch_fused_v<LAT, SCH, 3, 2, true>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
-    case 6: launch_fused_v<LAT, SCH, 4, 4, false>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
-    default: launch_fused_v<LAT, SCH, 8, 2, false>(S, Sn, rho, mu, rho_next, g, one_m_omega, st); break;
+    case 1: launch_fused_v<LAT, SCH, 4, 3, false>(S, Sn, rho, mu, rho_next, g, rx, st); break;
+    case 2: launch_fused_v<LAT, SCH, 6, 3, false>(S, Sn, rho, mu, rho_next, g, rx, st); break;
+    case 3: launch_fused_v<LAT, SCH, 4, 2, true>(S, Sn, rho, mu, rho_next, g, rx, st); break;
+    case 4: launch_fused_v<LAT, SCH, 5, 2, true>(S, Sn, rho, mu, rho_next, g, rx, st); break;
+    case 5: launch_fused_v<LAT, SCH, 3, 2, true>(S, Sn, rho, mu, rho_next, g, rx, st); break;
+    case 6: launch_fused_v<LAT, SCH, 4, 4, false>(S, Sn, rho, mu, rho_next, g, rx, st); break;
+    default: launch_fused_v<LAT, SCH, 8, 2, false>(S, Sn, rho, mu, rho_next, g, rx, st); break;
     }
 }
 

@@ -235,7 +235,7 @@ template <int LAT, int SCH>
 __global__ void __launch_bounds__(256) k_collide(const double* __restrict__ S, double* __restrict__ Sn,
                                                  const double* __restrict__ rho_f, const double* __restrict__ mu_f,
                                                  const double* __restrict__ grho, const double* __restrict__ gmu,
-                                                 Grid g, double one_m_omega)
+                                                 Grid g, Relax rx)
 {
     using L = Lat<LAT>;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(256) k_collide(const double* __restrict__ S, d
     }
     double Fx, Fy, Fz;
     force_at<LAT, SCH>(rho_f, mu_f, grho, gmu, g, n, x, y, z, r, Fx, Fy, Fz);
-    collide<LAT>(f, r, jx, jy, jz, Fx, Fy, Fz, one_m_omega, out);
+    collide<LAT>(f, r, jx, jy, jz, Fx, Fy, Fz, rx, out);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) Sn[(long long)i * g.ps + n] = out[i];
 }

@@ -55,10 +55,62 @@ template <> struct Lat<1> {
 // (Eq 8), equilibrium of Eq 6 with cs^2 = 1/3:
 //   f*_i = feq_i(rho, u + du) + (1 - 1/tau) (f_i - feq_i(rho, u)),  du = F/rho.
 // ---------------------------------------------------------------------------
+// D2Q9 moment basis of Eq 3: rows rho, e, eps, j_x, q_x, j_y, q_y, p_xx,
+// p_xy; columns the directions of Eq 2.  The rows are orthogonal with squared
+// norms 9, 36, 36, 6, 12, 6, 12, 4, 4, so M^-1 = M^T diag(1 / |row|^2).
+__host__ __device__ constexpr int mrt_m(int k, int i)
+{
+    constexpr signed char T[9][9] = {
+        {  1,  1,  1,  1,  1,  1,  1,  1,  1 },
+        { -4, -1, -1, -1, -1,  2,  2,  2,  2 },
+        {  4, -2, -2, -2, -2,  1,  1,  1,  1 },
+        {  0,  1,  0, -1,  0,  1, -1, -1,  1 },
+        {  0, -2,  0,  2,  0,  1, -1, -1,  1 },
+        {  0,  0,  1,  0, -1,  1,  1, -1, -1 },
+        {  0,  0, -2,  0,  2,  1,  1, -1, -1 },
+        {  0,  1, -1,  1, -1,  0,  0,  0,  0 },
+        {  0,  0,  0,  0,  0,  1, -1,  1, -1 },
+    };
+    return T[k][i];
+}
+constexpr double kMrtNorm2[9] = { 9, 36, 36, 6, 12, 6, 12, 4, 4 };
+
+// Relaxation of Eq 1.  SRT: every rate 1/tau.  MRT (D2Q9): S of Eq 5 with
+// s_1 = s_4 = s_6 = 1, s_2 = s_e, s_3 = s_eps, s_5 = s_7 = s_q,
+// s_8 = s_9 = 1/tau; sd[k] = s_k / |row k|^2 folds M^-1's row scaling in.
+struct Relax {
+    double omo;      // 1 - 1/tau
+    int mrt;         // nonzero: MRT
+    double sd[9];
+};
+
+// MRT post-collision values at one D2Q9 node (Eq 1, 4, 8), given the
+// equilibria at u and at u + du:
+//   o = f - M^-1 S M (f - feq(rho,u)) + feq(rho,u+du) - feq(rho,u).
+__device__ __forceinline__ void mrt_post(const double (&f)[9], const double (&fe)[9], const double (&fv)[9],
+                                         const Relax& rx, double (&o)[9])
+{
+    double c[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        double m = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) m += mrt_m(k, i) * (f[i] - fe[i]);
+        c[k] = rx.sd[k] * m;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        double b = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) b += mrt_m(k, i) * c[k];
+        o[i] = f[i] - b + (fv[i] - fe[i]);
+    }
+}
+
 template <int LAT>
 __device__ __forceinline__ void collide(const double (&f)[Lat<LAT>::Q], double rho,
                                         double jx, double jy, double jz,
-                                        double Fx, double Fy, double Fz, double one_m_omega,
+                                        double Fx, double Fy, double Fz, const Relax& rx,
                                         double (&out)[Lat<LAT>::Q])
 {
     using L = Lat<LAT>;
@@ -74,7 +126,21 @@ __device__ __forceinline__ void collide(const double (&f)[Lat<LAT>::Q], double r
         const double ev = L::ex(i) * vx + L::ey(i) * vy + L::ez(i) * vz;
         const double fe = wr * (uu + eu * (3.0 + 4.5 * eu));
         const double fv = wr * (vv + ev * (3.0 + 4.5 * ev));
-        out[i] = fv + one_m_omega * (f[i] - fe);
+        out[i] = fv + rx.omo * (f[i] - fe);
+    }
+    if constexpr (LAT == 0) {
+        if (rx.mrt) {
+            double fe[9], fv[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const double wr = L::w(i) * rho;
+                const double eu = L::ex(i) * ux + L::ey(i) * uy;
+                const double ev = L::ex(i) * vx + L::ey(i) * vy;
+                fe[i] = wr * (uu + eu * (3.0 + 4.5 * eu));
+                fv[i] = wr * (vv + ev * (3.0 + 4.5 * ev));
+            }
+            mrt_post(f, fe, fv, rx, out);
+        }
     }
 }
 

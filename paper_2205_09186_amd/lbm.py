@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 D2Q9, D3Q19 = 0, 1
+SRT, MRT = 0, 1
 CD2, CD4, CD6, E4, E8, OCFDS4, CFDS4, CFDS6, CFDS8 = range(9)
 SCHEMES = {"CD2": CD2, "CD4": CD4, "CD6": CD6, "E4": E4, "E8": E8, "OCFDS4": OCFDS4,
            "CFDS4": CFDS4, "CFDS6": CFDS6, "CFDS8": CFDS8}
@@ -32,7 +33,8 @@ class lbm_params(C.Structure):
     _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("tau", C.c_double), ("Tr", C.c_double), ("k", C.c_double), ("kappa", C.c_double),
                 ("scheme", C.c_int), ("a", C.c_double), ("b", C.c_double), ("R", C.c_double),
-                ("omega", C.c_double)]
+                ("omega", C.c_double), ("collision", C.c_int), ("s_e", C.c_double), ("s_eps", C.c_double),
+                ("s_q", C.c_double)]
 
 
 _lib = None
@@ -123,10 +125,15 @@ class Params:
     b: float = 0.0
     R: float = 0.0
     omega: float = 0.0
+    collision: int = SRT       # SRT or MRT (D2Q9, Eq 1, 3, 5)
+    s_e: float = 0.0           # MRT rates; 0 selects the values of Sec 2.1
+    s_eps: float = 0.0
+    s_q: float = 0.0
 
     def c(self) -> lbm_params:
         return lbm_params(self.lattice, self.nx, self.ny, self.nz, self.tau, self.Tr, self.k, self.kappa,
-                          self.scheme, self.a, self.b, self.R, self.omega)
+                          self.scheme, self.a, self.b, self.R, self.omega, self.collision, self.s_e, self.s_eps,
+                          self.s_q)
 
     @property
     def n(self) -> int:

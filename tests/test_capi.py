@@ -32,12 +32,15 @@ def test_workspace_validation():
     nb = lbm.workspace_bytes(ok)
     assert nb >= 2 * 19 * 16 ** 3 * 8
     bad = [dict(tau=0.5), dict(Tr=1.0), dict(Tr=0.0), dict(k=0.0), dict(kappa=-1.0), dict(scheme=9),
-           dict(nz=1), dict(nx=3), dict(lattice=2)]
+           dict(nz=1), dict(nx=3), dict(lattice=2), dict(collision=2), dict(collision=lbm.MRT),
+           dict(collision=lbm.MRT, s_e=2.0), dict(s_q=-1.0)]
     for b in bad:
         q = lbm.Params(**{**ok.__dict__, **b})
         assert lbm.workspace_bytes(q) == 0, b
     q2 = lbm.Params(lattice=lbm.D2Q9, nx=16, ny=16, nz=2)
     assert lbm.workspace_bytes(q2) == 0
+    # MRT is defined for D2Q9 (Eq 3)
+    assert lbm.workspace_bytes(lbm.Params(lattice=lbm.D2Q9, nx=16, ny=16, collision=lbm.MRT)) > 0
     # compact schemes need the gradient fields as well
     assert lbm.workspace_bytes(lbm.Params(**{**ok.__dict__, "scheme": lbm.OCFDS4})) > nb
 
