@@ -150,6 +150,26 @@ int lbm_critical(const lbm_params* p, double* Tc, double* rho_c, double* p_c);
  * (Sec 3.4), host computation.  LBM_EINVAL outside 0 < Tr < 1. */
 int lbm_coexistence(const lbm_params* p, double* rho_g, double* rho_l);
 
+/* Peng-Robinson pressure p0 (Eq 14) and bulk chemical potential psi'(rho)
+ * (Eq 15 without the gradient term, integration constant 0), not scaled by
+ * k, at T = p->Tr Tc, for n host densities in (0, 1/b).  p0 or mu may be NULL.
+ * Host computation; the inputs of the flat-interface profile of Eq 29. */
+int lbm_eos(const lbm_params* p, const double* rho, long n, double* p0, double* mu);
+
+/* Diagnostics of the current state (the density the next step reads), with
+ * the context's difference scheme:
+ *   mu_hat = k^2 psi'(rho) - kappa_hat lap(rho)        (Eq 15, 16)
+ *   F      = -rho grad(mu_hat) + cs^2 grad(rho)         (Eq 12)
+ * F receives dim planes of N (x, y[, z] components), mu N values; either may
+ * be NULL.  Host or device arrays per out_on_device; synchronises. */
+int lbm_force(lbm_ctx* c, double* F, double* mu, int out_on_device);
+
+/* Gradient (dim planes of N) and Laplacian (N) of a device field d_in with the
+ * context's difference scheme (Sec 2.3: Eq 18-20 explicit, Eq 21-24 compact
+ * with D(D) as Laplacian, Eq 25 isotropic).  d_lap may be NULL.  Enqueued on
+ * the context's stream; d_in must not alias the outputs. */
+int lbm_gradient(lbm_ctx* c, const double* d_in, double* d_grad, double* d_lap);
+
 /* ------------------------------------------------------------------------
  * Batched sweep: many uneven D2Q9 instances (droplets, flat slabs; any
  * temperature, radius and scheme) stepped together by one cooperative

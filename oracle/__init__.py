@@ -69,6 +69,7 @@ def lib():
         L.orc_collide_node.argtypes = [C.c_int, D, dp, D, D, D, dp]
         L.orc_collide_node_mrt.argtypes = [D, D, D, D, dp, D, D, D, dp]
         L.orc_mrt_matrix.argtypes = [dp, dp]
+        L.orc_force.argtypes = [P, dp, dp, dp]
         L.orc_pr_alpha.argtypes = [D, D]; L.orc_pr_alpha.restype = D
         L.orc_pr_p0.argtypes = [D, D, D, D, D]; L.orc_pr_p0.restype = D
         L.orc_pr_mub.argtypes = [D, D, D, D, D]; L.orc_pr_mub.restype = D
@@ -138,6 +139,19 @@ def collide_node_mrt(tau: float, f, F, s_e: float = 0.0, s_eps: float = 0.0, s_q
     Fx, Fy = (list(F) + [0.0, 0.0])[:2]
     lib().orc_collide_node_mrt(tau, s_e or 1.64, s_eps or 1.54, s_q or 1.7, f, Fx, Fy, 0.0, out)
     return out
+
+
+def force(p: "Params", rho):
+    """(F[dim, ...], mu_hat) of a density field (Eq 12, 15, 16) with p's scheme."""
+    cp = p.c()
+    r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+    mu = np.zeros_like(r)
+    F = np.zeros(3 * r.size)
+    if lib().orc_force(C.byref(cp), r, mu, F):
+        raise ValueError("invalid parameters")
+    dim = 2 if p.lattice == D2Q9 else 3
+    shape = np.shape(rho)
+    return F[: dim * r.size].reshape((dim,) + shape), mu.reshape(shape)
 
 
 def mrt_matrix():

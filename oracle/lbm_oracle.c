@@ -877,6 +877,28 @@ static int eos_of(const orc_params *p, eos_t *E)
 /* Steps 1-5 of the step on the post-streaming state f: rho, j, and the force
  * F = -rho grad(mu_hat) + cs^2 grad(rho), with
  * mu_hat = k^2 psi'(rho) - kappa_hat lap(rho) (Eq 12, 16). */
+static void force_of_rho(const orc_params *p, const grid *G, const eos_t *E, const double *rho,
+                         double *mu, double *F)
+{
+    long N = (long)G->nx * G->ny * G->nz;
+    double *lap = (double *)malloc(sizeof(double) * N);
+    double *grho = (double *)calloc(3 * N, sizeof(double));
+    double *gmu = (double *)calloc(3 * N, sizeof(double));
+    /* 2-3. chemical potential in mesh units */
+    lap_field(G, p->scheme, rho, lap);
+    #pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n)
+        mu[n] = p->k * p->k * orc_pr_mub(rho[n], E->T, E->aa, E->b, E->R) - p->kappa * lap[n];
+    /* 4. gradients */
+    grad_field(G, p->scheme, rho, grho);
+    grad_field(G, p->scheme, mu, gmu);
+    /* 5. force */
+    for (int d = 0; d < 3; ++d)
+        for (long n = 0; n < N; ++n)
+            F[d * N + n] = (d < G->dim) ? (-rho[n] * gmu[d * N + n] + CS2 * grho[d * N + n]) : 0.0;
+    free(lap); free(grho); free(gmu);
+}
+
 static int force_fields(const orc_params *p, const orc_lattice *L, const double *f,
                         double *rho, double *j /* 3N */, double *F /* 3N */)
 {
@@ -894,23 +916,21 @@ static int force_fields(const orc_params *p, const orc_lattice *L, const double 
         }
         rho[n] = r; j[n] = jx; j[N + n] = jy; j[2 * N + n] = jz;
     }
-    double *lap = (double *)malloc(sizeof(double) * N);
     double *mu = (double *)malloc(sizeof(double) * N);
-    double *grho = (double *)calloc(3 * N, sizeof(double));
-    double *gmu = (double *)calloc(3 * N, sizeof(double));
-    /* 2-3. chemical potential in mesh units */
-    lap_field(&G, p->scheme, rho, lap);
-    #pragma omp parallel for schedule(static)
-    for (long n = 0; n < N; ++n)
-        mu[n] = p->k * p->k * orc_pr_mub(rho[n], E.T, E.aa, E.b, E.R) - p->kappa * lap[n];
-    /* 4. gradients */
-    grad_field(&G, p->scheme, rho, grho);
-    grad_field(&G, p->scheme, mu, gmu);
-    /* 5. force */
-    for (int d = 0; d < 3; ++d)
-        for (long n = 0; n < N; ++n)
-            F[d * N + n] = (d < G.dim) ? (-rho[n] * gmu[d * N + n] + CS2 * grho[d * N + n]) : 0.0;
-    free(lap); free(mu); free(grho); free(gmu);
+    force_of_rho(p, &G, &E, rho, mu, F);
+    free(mu);
+    return 0;
+}
+
+/* 2-5 of the step for a given density field: mu_hat (Eq 15, 16) and
+ * F = -rho grad(mu_hat) + cs^2 grad(rho) (Eq 12); F is 3N (zero beyond dim). */
+int orc_force(const orc_params *p, const double *rho, double *mu, double *F)
+{
+    if (check_params(p)) return -1;
+    grid G = { p->nx, p->ny, p->nz, p->lattice == ORC_D2Q9 ? 2 : 3 };
+    eos_t E;
+    if (eos_of(p, &E)) return -1;
+    force_of_rho(p, &G, &E, rho, mu, F);
     return 0;
 }
 

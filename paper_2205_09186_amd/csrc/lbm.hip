@@ -322,6 +322,35 @@ void dispatch(int lat, int sch, A... a)
 }
 
 template <int LAT, int SCH> struct StepOp { static void run(lbm_ctx* c) { launch_step<LAT, SCH>(c); } };
+// mu_hat (and compact gradient fields) of the current state, then the force.
+template <int LAT, int SCH>
+void launch_force(lbm_ctx* c, double* F)
+{
+    launch_fields<LAT, SCH>(c);
+    hipLaunchKernelGGL((k_force_node<LAT, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                       c->rhob[c->cur], c->mu, c->grho, c->gmu, c->g, F);
+}
+
+template <int LAT, int SCH>
+void launch_gradient(lbm_ctx* c, const double* in, double* grad, double* lap)
+{
+    constexpr int DIM = Lat<LAT>::DIM;
+    if constexpr (is_compact(SCH)) {
+        for (int d = 0; d < DIM; ++d) compact_deriv(c, in, sink_of(grad + d * c->g.N, C_STORE), d);
+        if (lap)
+            for (int d = 0; d < DIM; ++d)
+                compact_deriv(c, grad + d * c->g.N, sink_of(lap, d > 0 ? C_ADD : C_STORE), d);
+    } else {
+        hipLaunchKernelGGL((k_gradlap<DIM, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                           in, grad, lap, c->g);
+    }
+}
+
+template <int LAT, int SCH> struct ForceOp { static void run(lbm_ctx* c, double* F) { launch_force<LAT, SCH>(c, F); } };
+template <int LAT, int SCH> struct GradOp {
+    static void run(lbm_ctx* c, const double* in, double* g, double* l) { launch_gradient<LAT, SCH>(c, in, g, l); }
+};
+
 template <int LAT, int SCH> struct MacrosOp {
     static void run(lbm_ctx* c, double* r, double* x, double* y, double* z) { launch_macros<LAT, SCH>(c, r, x, y, z); }
 };
@@ -562,6 +591,31 @@ int lbm_macros(lbm_ctx* c, double* rho, double* vx, double* vy, double* vz, int 
     return hip_check(c, hipStreamSynchronize(c->stream), "macros sync");
 }
 
+int lbm_force(lbm_ctx* c, double* F, double* mu, int out_on_device)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    const long long N = c->g.N;
+    // F is formed in the idle population buffer (dim N <= Q N), mu in c->mu
+    double* d_F = c->S[1 - c->cur];
+    dispatch<ForceOp>(c->p.lattice, c->p.scheme, c, d_F);
+    int r = hip_check(c, hipGetLastError(), "force launch");
+    if (r) return r;
+    const hipMemcpyKind k = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (F && (r = hip_check(c, hipMemcpyAsync(F, d_F, sizeof(double) * c->dim * N, k, c->stream), "copy F")))
+        return r;
+    if (mu && (r = hip_check(c, hipMemcpyAsync(mu, c->mu, sizeof(double) * N, k, c->stream), "copy mu"))) return r;
+    return hip_check(c, hipStreamSynchronize(c->stream), "force sync");
+}
+
+int lbm_gradient(lbm_ctx* c, const double* d_in, double* d_grad, double* d_lap)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (!d_in || !d_grad) return fail(c, LBM_EINVAL, "d_in and d_grad must be device arrays");
+    if (d_in == d_grad || d_in == d_lap) return fail(c, LBM_EINVAL, "d_in must not alias the outputs");
+    dispatch<GradOp>(c->p.lattice, c->p.scheme, c, d_in, d_grad, d_lap);
+    return hip_check(c, hipGetLastError(), "gradient launch");
+}
+
 int lbm_spurious_max(lbm_ctx* c, double* umax, double* mass)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
@@ -675,6 +729,22 @@ int lbm_critical(const lbm_params* p, double* Tc, double* rho_c, double* p_c)
 {
     if (!p || !Tc || !rho_c || !p_c) return fail(nullptr, LBM_EINVAL, "NULL argument");
     pr_critical(eos_constants(p), *Tc, *rho_c, *p_c);
+    return LBM_OK;
+}
+
+int lbm_eos(const lbm_params* p, const double* rho, long n, double* p0, double* mu)
+{
+    if (!p || !rho || n < 0) return fail(nullptr, LBM_EINVAL, "NULL argument");
+    if (!(p->Tr > 0.0 && p->Tr < 1.0)) return fail(nullptr, LBM_EINVAL, "Tr must lie in (0, 1)");
+    const PR e = eos_constants(p);
+    double Tc, rc, pc;
+    pr_critical(e, Tc, rc, pc);
+    const double T = p->Tr * Tc, aa = e.a * pr_alpha(p->Tr, e.omega);
+    for (long i = 0; i < n; ++i) {
+        if (!(rho[i] > 0.0 && rho[i] * e.b < 1.0)) return fail(nullptr, LBM_EINVAL, "density outside (0, 1/b)");
+        if (p0) p0[i] = pr_pressure(e, aa, T, rho[i]);
+        if (mu) mu[i] = pr_mu(e, aa, T, rho[i]);
+    }
     return LBM_OK;
 }
 

@@ -258,6 +258,43 @@ __global__ void __launch_bounds__(256) k_collide(const double* __restrict__ S, d
     for (int i = 0; i < L::Q; ++i) Sn[(long long)i * g.ps + n] = out[i];
 }
 
+// Force (Eq 12) at every node from rho, mu_hat and, for the compact schemes,
+// the precomputed gradient fields; F stored as DIM planes of N.
+template <int LAT, int SCH>
+__global__ void __launch_bounds__(256) k_force_node(const double* __restrict__ rho, const double* __restrict__ mu,
+                                                    const double* __restrict__ grho, const double* __restrict__ gmu,
+                                                    Grid g, double* __restrict__ F)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    int x, y, z;
+    coords(n, g, x, y, z);
+    double Fx, Fy, Fz;
+    force_at<LAT, SCH>(rho, mu, grho, gmu, g, n, x, y, z, rho[n], Fx, Fy, Fz);
+    F[n] = Fx;
+    F[g.N + n] = Fy;
+    if constexpr (Lat<LAT>::DIM == 3) F[2 * g.N + n] = Fz;
+}
+
+// Gradient and Laplacian of a field with an explicit or isotropic scheme.
+template <int DIM, int SCH>
+__global__ void __launch_bounds__(256) k_gradlap(const double* __restrict__ in, double* __restrict__ grad,
+                                                 double* __restrict__ lap, Grid g)
+{
+    constexpr int R = radius(SCH);
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    int x, y, z;
+    coords(n, g, x, y, z);
+    Nbr<R, DIM> nb(x, y, z, g);
+    double gx, gy, gz;
+    grad_at<DIM, SCH, R>(in, nb, gx, gy, gz);
+    grad[n] = gx;
+    grad[g.N + n] = gy;
+    if constexpr (DIM == 3) grad[2 * g.N + n] = gz;
+    if (lap) lap[n] = lap_at<DIM, SCH, R>(in, nb);
+}
+
 // NaN-propagating maximum.
 __device__ __forceinline__ double nmax(double a, double b) { return (a > b || a != a) ? a : b; }
 

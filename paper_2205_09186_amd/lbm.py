@@ -79,6 +79,9 @@ SYMBOLS = {
     "lbm_sum_scratch_bytes": (C.c_size_t, [C.c_long]),
     "lbm_sum": (C.c_int, [C.c_void_p, C.c_long, C.c_void_p, _D, C.c_void_p]),
     "lbm_coexistence": (C.c_int, [_P, _D, _D]),
+    "lbm_eos": (C.c_int, [_P, C.c_void_p, C.c_long, C.c_void_p, C.c_void_p]),
+    "lbm_force": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "lbm_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 
@@ -158,6 +161,17 @@ def critical(p: Params | None = None):
     Tc, rc, pc = C.c_double(), C.c_double(), C.c_double()
     _check(lib().lbm_critical(C.byref(cp), C.byref(Tc), C.byref(rc), C.byref(pc)))
     return Tc.value, rc.value, pc.value
+
+
+def eos(rho, Tr: float, p: Params | None = None):
+    """(p0, psi') of the Peng-Robinson EOS (Eq 14, 15; not scaled by k) at
+    host densities rho, T = Tr Tc."""
+    q = Params(**{**(p or Params()).__dict__, "Tr": Tr})
+    cp = q.c()
+    r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+    p0, mu = np.empty_like(r), np.empty_like(r)
+    _check(lib().lbm_eos(C.byref(cp), r.ctypes.data, r.size, p0.ctypes.data, mu.ctypes.data))
+    return p0.reshape(np.shape(rho)), mu.reshape(np.shape(rho))
 
 
 def coexistence(Tr: float, p: Params | None = None):
@@ -257,6 +271,29 @@ class Simulation:
     def spurious_max(self, raise_on_nonfinite: bool = False):
         """(U = max |v|, total mass, status code)."""
         return _spurious(self, raise_on_nonfinite)
+
+    def force(self):
+        """(F[dim, *shape], mu_hat[*shape]) of the current state as host arrays
+        (Eq 12, 16, with the context's scheme)."""
+        dim = 3 if self.p.lattice == D3Q19 else 2
+        F = np.empty(dim * self.p.n)
+        mu = np.empty(self.p.n)
+        _check(lib().lbm_force(self.ctx, F.ctypes.data, mu.ctypes.data, 0), self.ctx)
+        return F.reshape((dim,) + self.p.shape), mu.reshape(self.p.shape)
+
+    def gradient(self, field):
+        """(grad[dim, *shape], lap[*shape]) of a field with the context's scheme,
+        as device tensors (the field is copied to the device if needed)."""
+        t = self.torch
+        f = t.as_tensor(np.ascontiguousarray(field, dtype=np.float64).reshape(-1) if not t.is_tensor(field)
+                        else field.reshape(-1)).to(self.device, t.float64).contiguous()
+        dim = 3 if self.p.lattice == D3Q19 else 2
+        g = t.empty(dim * self.p.n, dtype=t.float64, device=self.device)
+        lap = t.empty(self.p.n, dtype=t.float64, device=self.device)
+        _check(lib().lbm_gradient(self.ctx, C.c_void_p(f.data_ptr()), C.c_void_p(g.data_ptr()),
+                                  C.c_void_p(lap.data_ptr())), self.ctx)
+        t.cuda.current_stream().synchronize()
+        return g.view((dim,) + self.p.shape), lap.view(self.p.shape)
 
     def populations(self) -> np.ndarray:
         return _populations(self)

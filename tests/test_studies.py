@@ -1,0 +1,63 @@
+"""Pins of the flat-interface profile of Eq 29 (host computation through the
+library's EOS): it must satisfy the condition that defines it, reach the
+Maxwell densities, and scale with sqrt(kappa_hat)/k."""
+import numpy as np
+import pytest
+
+from paper_2205_09186_amd import lbm, studies
+
+
+@pytest.fixture(scope="module")
+def fi():
+    return studies.FlatInterface(0.6, 0.2, 0.004)
+
+
+def _residual(fi, h):
+    """max |k^2 psi'(rho) - kappa rho'' - k^2 mu_M| / (k^2 |mu_M|) with a
+    fourth-order second difference of step h over the interface."""
+    d = np.arange(-4.0, 10.0, h)
+    r, s = fi.profile(d)
+    d2 = (-r[4:] + 16 * r[3:-1] - 30 * r[2:-2] + 16 * r[1:-3] - r[:-4]) / (12 * h * h)
+    _, mu = lbm.eos(r[2:-2], fi.Tr)
+    res = fi.k ** 2 * mu - fi.kappa * d2 - fi.k ** 2 * fi.mu_M
+    d1 = (-r[4:] + 8 * r[3:-1] - 8 * r[1:-3] + r[:-4]) / (12 * h)
+    return np.abs(res).max() / (fi.k ** 2 * abs(fi.mu_M)), np.abs(d1 - s[2:-2]).max() / s.max()
+
+
+def test_profile_satisfies_eq29(fi):
+    """Uniform chemical potential across the interface (mechanical equilibrium
+    of a flat interface), to the accuracy of the difference check: the
+    residual falls as h^4."""
+    r1, s1 = _residual(fi, 0.02)
+    r2, s2 = _residual(fi, 0.01)
+    assert r2 < 2e-6 and s2 < 2e-6, (r2, s2)
+    assert 10 < r1 / r2 < 22 and 10 < s1 / s2 < 22, (r1 / r2, s1 / s2)
+
+
+def test_profile_limits_and_maxwell(fi):
+    g, l = lbm.coexistence(0.6)
+    r, s = fi.profile(np.array([-60.0, 0.0, 60.0]))
+    assert r[0] == pytest.approx(g, rel=1e-12)
+    assert r[2] == pytest.approx(l, rel=1e-12)
+    assert r[1] == pytest.approx(0.5 * (g + l), rel=1e-12)
+    # the excess grand potential vanishes at both coexistence densities
+    # (the two one-sided integrals of psi' - mu_M meet at the mid density)
+    assert fi.omega_mismatch < 1e-10
+
+
+def test_width_scales_as_sqrt_kappa_over_k():
+    w = {k: studies.FlatInterface(0.7, k, 0.004).width() for k in (0.1, 0.2, 0.4)}
+    assert w[0.1] / w[0.2] == pytest.approx(2.0, rel=1e-9)
+    assert w[0.1] / w[0.4] == pytest.approx(4.0, rel=1e-9)
+    w2 = studies.FlatInterface(0.7, 0.1, 0.016).width()
+    assert w2 / w[0.1] == pytest.approx(2.0, rel=1e-9)
+
+
+def test_cumulative_rule_is_fourth_order():
+    for n in (41, 81):
+        x = np.linspace(0.0, 2.0, n)
+        c = studies._cumsimpson(np.exp(x), x[1] - x[0])
+        err = np.abs(c - (np.exp(x) - 1.0)).max()
+        if n == 41:
+            e1 = err
+    assert 12 < e1 / err < 20
