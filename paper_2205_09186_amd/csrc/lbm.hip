@@ -29,7 +29,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t S0, S1, rho0, rho1, mu, force, grho, gmu, lap, wtmp, partial, result, total;
+    size_t S0, S1, rho0, rho1, mu, force, ringsum, grho, gmu, lap, wtmp, partial, result, total;
     long long nparts;
 };
 
@@ -100,6 +100,11 @@ Layout layout_of(const lbm_params* p)
     L.rho1 = take(sizeof(double) * N);
     L.mu = take(sizeof(double) * N);
     if (N < (1LL << 29)) L.force = take(sizeof(double) * dim * N);
+    if (N < (1LL << 29) && p->nx % 64 == 0 && p->ny % kTileTY == 0) {
+        Grid g{};
+        g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
+        L.ringsum = take(sizeof(double) * ringsum_doubles(g, dim == 3));
+    }
     if (compact) {
         L.grho = take(sizeof(double) * dim * N);
         L.gmu = take(sizeof(double) * dim * N);
@@ -124,7 +129,7 @@ struct lbm_ctx {
     hipStream_t stream;
     char* ws;
     Layout L;
-    double *S[2], *rhob[2], *mu, *force, *grho, *gmu, *lap, *wtmp, *partial, *result;
+    double *S[2], *rhob[2], *mu, *force, *ringsum, *grho, *gmu, *lap, *wtmp, *partial, *result;
     int cur;        // index of the buffers holding the current state (S and rho)
     long steps;
     std::string err;
@@ -275,9 +280,18 @@ void launch_step(lbm_ctx* c)
             for (int d = 0; d < DIM; ++d)
                 compact_deriv(c, c->mu, sink_of(c->force + d * c->g.N, C_FORCE, rho, c->grho + d * c->g.N), d);
         }
-        mark(c, "k_ring");
-        launch_ring_collide<LAT>(CD ? c->variant - kNumFusedVariants : c->variant, c->S[c->cur], c->S[1 - c->cur],
-                                 c->force, c->rhob[1 - c->cur], c->g, c->rx, c->stream);
+        const int rv = CD ? c->variant - kNumFusedVariants : c->variant;
+        if (rv >= kNumRingVariants) {
+            mark(c, "k_tile");
+            launch_tile<LAT>(c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->ringsum, c->g, c->rx,
+                             c->stream);
+            mark(c, "k_fix");
+            launch_fix<LAT>(c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
+        } else {
+            mark(c, "k_ring");
+            launch_ring_collide<LAT>(rv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->g, c->rx,
+                                     c->stream);
+        }
         mark(c, nullptr);
         c->cur = 1 - c->cur;
         return;
@@ -425,6 +439,7 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->rhob[1] = reinterpret_cast<double*>(c->ws + L.rho1);
     c->mu = reinterpret_cast<double*>(c->ws + L.mu);
     c->force = c->g.N < (1LL << 29) ? reinterpret_cast<double*>(c->ws + L.force) : nullptr;
+    c->ringsum = (c->force && tile_fits(c->g, kTileTY)) ? reinterpret_cast<double*>(c->ws + L.ringsum) : nullptr;
     const bool compact = p->scheme >= LBM_OCFDS4;
     c->grho = compact ? reinterpret_cast<double*>(c->ws + L.grho) : nullptr;
     c->gmu = compact ? reinterpret_cast<double*>(c->ws + L.gmu) : nullptr;
@@ -692,7 +707,8 @@ int lbm_step_timed(lbm_ctx* c, long nsteps, double* ms, int cap, int* nphases)
 int lbm_num_variants(const lbm_ctx* c)
 {
     if (!c || !c->fused) return 1;
-    return c->p.scheme <= LBM_CD6 ? kNumFusedVariants + kNumRingVariants : kNumRingVariants;
+    const int tiles = c->ringsum ? kNumTileVariants : 0;
+    return (c->p.scheme <= LBM_CD6 ? kNumFusedVariants : 0) + kNumRingVariants + tiles;
 }
 
 int lbm_set_variant(lbm_ctx* c, int v)

@@ -510,6 +510,61 @@ inline void launch_force_march(const double* rho, const double* mu, double* F, c
 }
 
 // ---------------------------------------------------------------------------
+// Collision of one node (Eq 1 SRT or D2Q9 MRT, Eq 6, Eq 8) from its pulled
+// populations and force; each post-collision value goes to emit(i, o) as soon
+// as it is formed.  FULL: SRT with tau = 1, where f* = feq(rho, u + du).
+// ---------------------------------------------------------------------------
+template <int LAT, bool FULL, typename Emit>
+__device__ __forceinline__ void collide_emit(const double (&f)[Lat<LAT>::Q], double Fx, double Fy, double Fz,
+                                             const Relax& rx, Emit&& emit)
+{
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q;
+    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        r += f[i];
+        jx += L::ex(i) * f[i]; jy += L::ey(i) * f[i]; jz += L::ez(i) * f[i];
+    }
+    const double ir = 1.0 / r;
+    const double ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    const double vx = ux + Fx * ir, vy = uy + Fy * ir, vz = uz + Fz * ir;
+    const double uu = 1.0 - 1.5 * (ux * ux + uy * uy + uz * uz);
+    const double vv = 1.0 - 1.5 * (vx * vx + vy * vy + vz * vz);
+    double om[LAT == 0 ? 9 : 1];   // MRT post-collision values (D2Q9)
+    if constexpr (LAT == 0 && !FULL) {
+        if (rx.mrt) {
+            double fe[9], fv[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const double wr = L::w(i) * r;
+                const double eu = L::ex(i) * ux + L::ey(i) * uy;
+                const double ev = L::ex(i) * vx + L::ey(i) * vy;
+                fe[i] = wr * (uu + eu * (3.0 + 4.5 * eu));
+                fv[i] = wr * (vv + ev * (3.0 + 4.5 * ev));
+            }
+            mrt_post(f, fe, fv, rx, om);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double wr = L::w(i) * r;
+        const double ev = L::ex(i) * vx + L::ey(i) * vy + L::ez(i) * vz;
+        const double fv = wr * (vv + ev * (3.0 + 4.5 * ev));
+        double o = fv;
+        if constexpr (!FULL) {
+            const double eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
+            const double fe = wr * (uu + eu * (3.0 + 4.5 * eu));
+            o = fv + rx.omo * (f[i] - fe);
+            if constexpr (LAT == 0) {
+                if (rx.mrt) o = om[i];
+            }
+        }
+        emit(i, o);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Ring collide with a precomputed force: the same tile + ring scheme as
 // k_fused, but the force field comes from k_march (three loads per node), so
 // the kernel holds no stencil state.  The next plane's pulls are issued right
@@ -520,7 +575,6 @@ __global__ void __launch_bounds__((TX + 2) * (TY + 2), OCC)
 k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ F,
        double* __restrict__ rho_next, Grid g, TileGeom tg, Relax rx)
 {
-    const double one_m_omega = rx.omo;
     using L = Lat<LAT>;
     constexpr int Q = L::Q;
     constexpr int W = TX + 2, H = TY + 2, NTH = W * H;
@@ -594,55 +648,15 @@ k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
         }
         double own_m1 = 0.0, own_0 = 0.0, own_p1 = 0.0;   // post-collision values without in-plane shift
         if (active) {
-            double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                r += f[i];
-                jx += L::ex(i) * f[i]; jy += L::ey(i) * f[i]; jz += L::ez(i) * f[i];
-            }
-            // collision (Eq 1 SRT, Eq 6, Eq 8), each value stored as soon as formed
-            const double ir = 1.0 / r;
-            const double ux = jx * ir, uy = jy * ir, uz = jz * ir;
-            const double vx = ux + Fx * ir, vy = uy + Fy * ir, vz = uz + Fz * ir;
-            const double uu = 1.0 - 1.5 * (ux * ux + uy * uy + uz * uz);
-            const double vv = 1.0 - 1.5 * (vx * vx + vy * vy + vz * vz);
             const bool store = inner && zr >= z0 && zr < z1;
             const int n = z * nxy + yc + x;
-            double om[LAT == 0 ? 9 : 1];   // MRT post-collision values (D2Q9)
-            if constexpr (LAT == 0 && !FULL) {
-                if (rx.mrt) {
-                    double fe[9], fv[9];
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        const double wr = L::w(i) * r;
-                        const double eu = L::ex(i) * ux + L::ey(i) * uy;
-                        const double ev = L::ex(i) * vx + L::ey(i) * vy;
-                        fe[i] = wr * (uu + eu * (3.0 + 4.5 * eu));
-                        fv[i] = wr * (vv + ev * (3.0 + 4.5 * ev));
-                    }
-                    mrt_post(f, fe, fv, rx, om);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const double wr = L::w(i) * r;
-                const double ev = L::ex(i) * vx + L::ey(i) * vy + L::ez(i) * vz;
-                const double fv = wr * (vv + ev * (3.0 + 4.5 * ev));
-                double o = fv;
-                if constexpr (!FULL) {
-                    const double eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
-                    const double fe = wr * (uu + eu * (3.0 + 4.5 * eu));
-                    o = fv + one_m_omega * (f[i] - fe);
-                    if constexpr (LAT == 0) {
-                        if (rx.mrt) o = om[i];
-                    }
-                }
+            collide_emit<LAT, FULL>(f, Fx, Fy, Fz, rx, [&](int i, double o) {
                 if (store) st32(Sn + (long long)i * g.ps, (unsigned)n, o);
                 if (xcls_of<LAT>(i) >= 0) xs[xcls_of<LAT>(i)][slot] = o;
                 else if (L::ez(i) == -1) own_m1 = o;
                 else if (L::ez(i) == 0) own_0 = o;
                 else own_p1 = o;
-            }
+            });
         }
         __syncthreads();
         double a_m1 = own_m1, a_0 = own_0, a_p1 = own_p1;
@@ -676,10 +690,237 @@ k_ring(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tile collide without the ring, for grids tiled exactly by 64 x TY tiles.
+// Every node of the tile is collided once.  Values that stay inside the tile
+// reach their destination through LDS and give the tile's partial rho(t+1);
+// the first NR lanes also sum, for each ring cell around the tile, the values
+// that leave the tile into it, and store those sums.  k_fix then adds, at
+// every node on a tile edge, the sums the neighbouring tiles left for it.  In
+// z the segment is marched with one extra plane at each end, as in k_ring.
+// ---------------------------------------------------------------------------
+template <int TY>
+struct TileRing {
+    static constexpr int NR = 132 + 2 * TY;           // ring cells of a 64 x TY tile
+    static constexpr int NB = 2 * 64 + 2 * (TY - 2);  // edge nodes of the tile
+    // ring cell k -> (rx, ry) relative to the tile origin
+    __host__ __device__ static void cell(int k, int& rx, int& ry)
+    {
+        if (k < 66) { rx = k - 1; ry = -1; }
+        else if (k < 132) { rx = k - 67; ry = TY; }
+        else if (k < 132 + TY) { rx = -1; ry = k - 132; }
+        else { rx = 64; ry = k - 132 - TY; }
+    }
+    // (rx, ry) -> k, or -1 if it is no ring cell
+    __host__ __device__ static int index(int rx, int ry)
+    {
+        if (rx < -1 || rx > 64 || ry < -1 || ry > TY) return -1;
+        if (ry == -1) return rx + 1;
+        if (ry == TY) return rx + 67;
+        if (rx == -1) return 132 + ry;
+        if (rx == 64) return 132 + TY + ry;
+        return -1;
+    }
+};
+
+inline bool tile_fits(const Grid& g, int ty) { return g.nx % 64 == 0 && g.ny % ty == 0; }
+
+template <int LAT, int TY, bool FULL>
+__global__ void __launch_bounds__(64 * TY, 2)
+k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ F,
+       double* __restrict__ rho_next, double* __restrict__ ringsum, Grid g, TileGeom tg, Relax rx)
+{
+    using L = Lat<LAT>;
+    using TR = TileRing<TY>;
+    constexpr int Q = L::Q;
+    constexpr int NTH = 64 * TY;
+    constexpr int NCL = LAT == 1 ? 16 : 8;
+    __shared__ double xs[NCL][NTH];
+
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nxy = (int)g.nxy, N = (int)g.N;
+    int b = blockIdx.x;
+    {
+        const int nb = gridDim.x, per = nb / 8;
+        if (b < per * 8) b = (b % 8) * per + b / 8;
+    }
+    const int tx = b % tg.ntx;
+    const int ty = (b / tg.ntx) % tg.nty;
+    const int sz = b / (tg.ntx * tg.nty);
+    const int lid = threadIdx.x;
+    const int lx = lid % 64, ly = lid / 64;
+    const int x = tx * 64 + lx, y = ty * TY + ly;
+    const int xm = wrapc(x - 1, nx), xp = wrapc(x + 1, nx);
+    const int yc = y * nx, ym = wrapc(y - 1, ny) * nx, yp = wrapc(y + 1, ny) * nx;
+    const int z0 = LAT == 1 ? sz * FZ : 0;
+    const int z1 = LAT == 1 ? min(z0 + FZ, nz) : 1;
+    const int MZT = LAT == 1 ? FZ : 1;   // ring-sum planes per segment
+    double* rs = ringsum + (size_t)b * MZT * TR::NR;
+    const bool ring = lid < TR::NR;
+    int rcx = 0, rcy = 0;
+    if (ring) TR::cell(lid, rcx, rcy);
+
+    double f[Q], Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    auto pull_plane = [&](int z) {
+        const int zo = z * nxy;
+        const int zmo = LAT == 1 ? wrapc(z - 1, nz) * nxy : 0;
+        const int zpo = LAT == 1 ? wrapc(z + 1, nz) * nxy : 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ox = L::ex(i) == 1 ? xm : L::ex(i) == -1 ? xp : x;
+            const int oy = L::ey(i) == 1 ? ym : L::ey(i) == -1 ? yp : yc;
+            const int oz = L::ez(i) == 1 ? zmo : L::ez(i) == -1 ? zpo : zo;
+            f[i] = ld32(S + (long long)i * g.ps, (unsigned)(oz + oy + ox));
+        }
+        const unsigned n = (unsigned)(zo + yc + x);
+        Fx = ld32(F, n);
+        Fy = ld32(F + N, n);
+        if constexpr (LAT == 1) Fz = ld32(F + 2LL * N, n);
+    };
+
+    double acc_m1 = 0.0, acc_0 = 0.0, racc_m1 = 0.0, racc_0 = 0.0;
+    const int zb = LAT == 1 ? z0 - 1 : 0, ze = LAT == 1 ? z1 : 0;
+    pull_plane(LAT == 1 ? pwrap(zb, nz) : 0);
+    for (int zr = zb; zr <= ze; ++zr) {
+        const int z = LAT == 1 ? pwrap(zr, nz) : 0;
+        double own_m1 = 0.0, own_0 = 0.0, own_p1 = 0.0;
+        {
+            const bool store = zr >= z0 && zr < z1;
+            const int n = z * nxy + yc + x;
+            collide_emit<LAT, FULL>(f, Fx, Fy, Fz, rx, [&](int i, double o) {
+                if (store) st32(Sn + (long long)i * g.ps, (unsigned)n, o);
+                if (xcls_of<LAT>(i) >= 0) xs[xcls_of<LAT>(i)][lid] = o;
+                else if (L::ez(i) == -1) own_m1 = o;
+                else if (L::ez(i) == 0) own_0 = o;
+                else own_p1 = o;
+            });
+        }
+        __syncthreads();
+        // values arriving from inside the tile, at the own node and (first NR
+        // lanes) at one ring cell
+        double a_m1 = own_m1, a_0 = own_0, a_p1 = own_p1, r_m1 = 0.0, r_0 = 0.0, r_p1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (xcls_of<LAT>(i) < 0) continue;
+            const int sx = lx - L::ex(i), sy = ly - L::ey(i);
+            if (sx >= 0 && sx < 64 && sy >= 0 && sy < TY) {
+                const double v = xs[xcls_of<LAT>(i)][sy * 64 + sx];
+                if (L::ez(i) == -1) a_m1 += v; else if (L::ez(i) == 0) a_0 += v; else a_p1 += v;
+            }
+            if (ring) {
+                const int qx = rcx - L::ex(i), qy = rcy - L::ey(i);
+                if (qx >= 0 && qx < 64 && qy >= 0 && qy < TY) {
+                    const double v = xs[xcls_of<LAT>(i)][qy * 64 + qx];
+                    if (L::ez(i) == -1) r_m1 += v; else if (L::ez(i) == 0) r_0 += v; else r_p1 += v;
+                }
+            }
+        }
+        if (zr < ze) pull_plane(pwrap(zr + 1, nz));
+        __syncthreads();
+        if constexpr (LAT == 1) {
+            acc_m1 += a_m1;
+            racc_m1 += r_m1;
+            if (zr - 1 >= z0 && zr - 1 < z1) {
+                st32(rho_next, (unsigned)((zr - 1) * nxy + yc + x), acc_m1);
+                if (ring) rs[(zr - 1 - z0) * TR::NR + lid] = racc_m1;
+            }
+            acc_m1 = acc_0 + a_0;
+            acc_0 = a_p1;
+            racc_m1 = racc_0 + r_0;
+            racc_0 = r_p1;
+        } else {
+            rho_next[yc + x] = a_0;
+            if (ring) rs[lid] = r_0;
+        }
+    }
+}
+
+// Adds to every node on a tile edge the ring sums the (up to eight)
+// neighbouring tiles left for it, in a fixed order.
+template <int TY>
+__global__ void __launch_bounds__(256) k_fix(double* __restrict__ rho_next, const double* __restrict__ ringsum,
+                                            Grid g, TileGeom tg, int mzt)
+{
+    using TR = TileRing<TY>;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int ntile = tg.ntx * tg.nty * tg.nsz;
+    if (t >= ntile * mzt * TR::NB) return;
+    const int e = t % TR::NB;
+    const int rest = t / TR::NB;
+    const int zl = rest % mzt;
+    const int tile = rest / mzt;
+    const int tx = tile % tg.ntx, ty = (tile / tg.ntx) % tg.nty, sz = tile / (tg.ntx * tg.nty);
+    const int z = sz * mzt + zl;
+    if (z >= g.nz) return;
+    int lx, ly;
+    if (e < 64) { lx = e; ly = 0; }
+    else if (e < 128) { lx = e - 64; ly = TY - 1; }
+    else if (e < 128 + TY - 2) { lx = 0; ly = 1 + e - 128; }
+    else { lx = 63; ly = 1 + e - 128 - (TY - 2); }
+    const unsigned n = (unsigned)(z * (int)g.nxy + (ty * TY + ly) * g.nx + tx * 64 + lx);
+    // neighbouring tiles, wrapped without divisions
+    const int txs[3] = { tx == 0 ? tg.ntx - 1 : tx - 1, tx, tx + 1 == tg.ntx ? 0 : tx + 1 };
+    const int tys[3] = { ty == 0 ? tg.nty - 1 : ty - 1, ty, ty + 1 == tg.nty ? 0 : ty + 1 };
+    double acc = ld32(rho_next, n);
+#pragma unroll
+    for (int dty = -1; dty <= 1; ++dty)
+#pragma unroll
+        for (int dtx = -1; dtx <= 1; ++dtx) {
+            if (dtx == 0 && dty == 0) continue;
+            const int k = TR::index(lx - 64 * dtx, ly - TY * dty);
+            if (k < 0) continue;
+            const int tn = (sz * tg.nty + tys[dty + 1]) * tg.ntx + txs[dtx + 1];
+            acc += ringsum[((size_t)tn * mzt + zl) * TR::NR + k];
+        }
+    st32(rho_next, n, acc);
+}
+
+constexpr int kTileTY = 8;
+constexpr int kNumTileVariants = 1;
+
+inline size_t ringsum_doubles(const Grid& g, bool three_d)
+{
+    const size_t ntile = (size_t)(g.nx / 64) * (g.ny / kTileTY) * (three_d ? (g.nz + FZ - 1) / FZ : 1);
+    return ntile * (three_d ? FZ : 1) * TileRing<kTileTY>::NR;
+}
+
+inline TileGeom tile_geom(const Grid& g, bool three_d)
+{
+    TileGeom t;
+    t.ntx = g.nx / 64;
+    t.nty = g.ny / kTileTY;
+    t.nsz = three_d ? (g.nz + FZ - 1) / FZ : 1;
+    t.mz = FZ;
+    return t;
+}
+
+template <int LAT>
+inline void launch_tile(const double* S, double* Sn, const double* F, double* rho_next, double* ringsum,
+                        const Grid& g, const Relax& rx, hipStream_t st)
+{
+    const TileGeom t = tile_geom(g, LAT == 1);
+    const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
+    if (rx.omo == 0.0 && !rx.mrt)
+        hipLaunchKernelGGL((k_tile<LAT, kTileTY, true>), dim3(nb), dim3(64 * kTileTY), 0, st, S, Sn, F, rho_next,
+                           ringsum, g, t, rx);
+    else
+        hipLaunchKernelGGL((k_tile<LAT, kTileTY, false>), dim3(nb), dim3(64 * kTileTY), 0, st, S, Sn, F, rho_next,
+                           ringsum, g, t, rx);
+}
+
+template <int LAT>
+inline void launch_fix(double* rho_next, const double* ringsum, const Grid& g, hipStream_t st)
+{
+    const TileGeom t = tile_geom(g, LAT == 1);
+    const int mzt = LAT == 1 ? FZ : 1;
+    const long long items = (long long)t.ntx * t.nty * t.nsz * mzt * TileRing<kTileTY>::NB;
+    hipLaunchKernelGGL((k_fix<kTileTY>), dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, rho_next, ringsum,
+                       g, t, mzt);
+}
+
 struct RingVariant { int tx, ty, occ, pf; };
-constexpr RingVariant kRingVariants[] = { {64, 8, 3, 0}, {64, 8, 3, 1}, {64, 9, 3, 1}, {64, 7, 3, 1}, {64, 13, 2, 0},
-                                          {32, 16, 2, 0} };
-constexpr int kNumRingVariants = 6;
+constexpr RingVariant kRingVariants[] = { {64, 8, 3, 0}, {64, 13, 2, 0}, {64, 8, 3, 1} };
+constexpr int kNumRingVariants = 3;
 
 inline TileGeom ring_tiles(int tx, int ty, const Grid& g, bool three_d)
 {
@@ -710,11 +951,8 @@ inline void launch_ring_collide(int variant, const double* S, double* Sn, const 
                                 const Grid& g, const Relax& rx, hipStream_t st)
 {
     switch (variant) {
-    case 1: launch_ring_v<LAT, 64, 8, 3, true>(S, Sn, F, rho_next, g, rx, st); break;
-    case 2: launch_ring_v<LAT, 64, 9, 3, true>(S, Sn, F, rho_next, g, rx, st); break;
-    case 3: launch_ring_v<LAT, 64, 7, 3, true>(S, Sn, F, rho_next, g, rx, st); break;
-    case 4: launch_ring_v<LAT, 64, 13, 2, false>(S, Sn, F, rho_next, g, rx, st); break;
-    case 5: launch_ring_v<LAT, 32, 16, 2, false>(S, Sn, F, rho_next, g, rx, st); break;
+    case 1: launch_ring_v<LAT, 64, 13, 2, false>(S, Sn, F, rho_next, g, rx, st); break;
+    case 2: launch_ring_v<LAT, 64, 8, 3, true>(S, Sn, F, rho_next, g, rx, st); break;
     default: launch_ring_v<LAT, 64, 8, 3, false>(S, Sn, F, rho_next, g, rx, st); break;
     }
 }

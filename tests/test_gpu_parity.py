@@ -196,10 +196,11 @@ def test_step_timed_phases(L, orc):
                                                            (1, (21, 17, 70), 1.0, "OCFDS4", 1),
                                                            (0, (50, 131), 0.9, "E8", 1)])
 def test_launch_variants_identical(L, orc, lat, shape, tau, scheme, designs):
-    """Launch variants of one kernel design (tile height, register budget)
-    compute the same node arithmetic in the same order: bitwise equal.  The
-    designs differ only in where the force is formed (inside the collide
-    kernel or in its own pass), which moves rounding only."""
+    """Launch variants of one kernel design (tile height, register budget,
+    prefetch) compute the same node arithmetic in the same order; separately
+    compiled instantiations may contract multiply-adds differently, so they
+    agree to a few ulp.  The designs differ in where the force is formed and
+    in how the next density is summed, which moves rounding only."""
     g, l = orc.maxwell(0.8)
     rho0 = inputs.droplet(shape, min(shape) / 4, 4.0, g, l)
     nz, ny, nx = ((1,) + shape) if lat == 0 else shape
@@ -214,7 +215,7 @@ def test_launch_variants_identical(L, orc, lat, shape, tau, scheme, designs):
         if design not in ref:
             ref[design] = f
         else:
-            assert np.array_equal(f, ref[design]), (v, design)
+            assert np.abs(f - ref[design]).max() <= 1e-14 * np.abs(f).max(), (v, design)
     assert len(ref) == designs, list(ref)
     if designs == 2:
         a, b = ref.values()
@@ -243,3 +244,30 @@ def test_graph_replay_equals_plain_launches(L, orc, lat, shape, scheme, monkeypa
     b.set_variant(b.num_variants - 1)
     a.step(9); b.step(9)
     assert np.array_equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("lat,shape,scheme,tau,coll", [
+    (1, (20, 16, 128), "CD6", 1.0, 0), (1, (12, 8, 64), "CD4", 0.8, 0), (1, (9, 24, 192), "OCFDS4", 1.0, 0),
+    (1, (10, 16, 64), "E8", 1.0, 0), (0, (40, 64), "CD6", 1.0, 0), (0, (16, 192), "CD2", 0.9, 0),
+    (0, (48, 128), "CD6", 0.9, 1), (0, (8, 64), "CD4", 1.0, 0)])
+def test_tile_design(L, orc, lat, shape, scheme, tau, coll):
+    """The ring-free tile collide (in-tile LDS exchange plus the ring sums that
+    k_fix adds at tile edges) against the oracle and against the ring collide,
+    including grids one tile wide, where a tile's ring wraps onto itself."""
+    Tr = 0.95 if scheme in ("CD2", "E8") else 0.9
+    g, l = orc.maxwell(Tr)
+    rho0 = inputs.droplet(shape, min(shape) / 4, 4.0, g, l)
+    nz, ny, nx = ((1,) + shape) if lat == 0 else shape
+    kw = dict(lattice=lat, nx=nx, ny=ny, nz=nz, tau=tau, Tr=Tr, k=0.16, kappa=0.004, scheme=L.SCHEMES[scheme])
+    p = L.Params(**kw, collision=coll)
+    a = L.Simulation(p, rho0)
+    a.set_variant(a.num_variants - 1)
+    assert [n for n, _ in a.step_timed(1)][-2:] == ["k_tile", "k_fix"]
+    a.step(39)
+    b = L.Simulation(p, rho0)
+    b.set_variant(a.num_variants - 2)   # a ring variant
+    b.step(40)
+    assert np.abs(a.populations() - b.populations()).max() < 1e-13
+    o = orc.Sim(orc.Params(**kw, collision=coll), rho0)
+    o.step(40)
+    _compare(a, o)
