@@ -51,6 +51,8 @@ def kernel_bytes_per_node(kname: str, Q: int, dim: int, scheme: str) -> int:
     every array element it must read or write, once (halo re-reads excluded).
       k_ring    reads Q pulled populations + dim force components,
                 writes Q populations + rho(t+1)
+      k_tile    the same as k_ring (its per-tile partial sums of rho(t+1)
+                and the k_fix pass that adds them are not algorithmic)
       k_fused   reads Q populations + rho + mu_hat, writes Q + rho(t+1)
       k_collide reads Q + rho + mu_hat (explicit schemes) or Q + 2 dim
                 derivative fields (compact schemes), writes Q
@@ -61,6 +63,7 @@ def kernel_bytes_per_node(kname: str, Q: int, dim: int, scheme: str) -> int:
     compact = scheme.startswith(("OCFDS", "CFDS"))
     table = {
         "k_ring": (Q + dim) + (Q + 1),
+        "k_tile": (Q + dim) + (Q + 1),
         "k_fused": (Q + 2) + (Q + 1),
         "k_collide": (Q + (2 * dim if compact else 2)) + Q,
         "k_mu_march": 2,
@@ -88,8 +91,8 @@ def traffic_record(kernel: str, workload: str):
         rec = json.load(open(path))
     except Exception:
         return None
-    ent = rec.get(workload)
-    if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("kernel") != kernel:
+    ent = rec.get(f"{workload} | {kernel}")
+    if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
 

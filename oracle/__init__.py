@@ -23,9 +23,10 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 D2Q9, D3Q19 = 0, 1
-CD2, CD4, CD6, E4, E8, OCFDS4, CFDS4, CFDS6, CFDS8 = range(9)
+CD2, CD4, CD6, E4, E8, OCFDS4, CFDS4, CFDS6, CFDS8, E6, E10 = range(11)
 SCHEME_NAMES = {"CD2": CD2, "CD4": CD4, "CD6": CD6, "E4": E4, "E8": E8,
-                "OCFDS4": OCFDS4, "CFDS4": CFDS4, "CFDS6": CFDS6, "CFDS8": CFDS8}
+                "OCFDS4": OCFDS4, "CFDS4": CFDS4, "CFDS6": CFDS6, "CFDS8": CFDS8,
+                "E6": E6, "E10": E10}
 
 # Peng-Robinson constants used in the paper's simulations (Sec 2.2).
 PR_A, PR_B, PR_R, PR_OMEGA = 2.0 / 49.0, 2.0 / 21.0, 1.0, 0.344
@@ -214,6 +215,8 @@ def iso_stencil(dim: int, scheme: int):
     e = np.zeros(128 * 3, np.int32)
     w = np.zeros(128)
     n = lib().orc_iso_stencil(dim, scheme, e, w)
+    if n < 0:
+        raise ValueError(f"no isotropic stencil for scheme {scheme} in {dim}D")
     return e[: 3 * n].reshape(n, 3).copy(), w[:n].copy()
 
 
@@ -233,7 +236,8 @@ def grad(g, scheme: int, dim: int | None = None) -> np.ndarray:
     g, d0, (nz, ny, nx) = _shape3(g)
     dim = dim or max(d0, 2)
     out = np.zeros((3,) + g.shape)
-    lib().orc_grad(dim, nx, ny, nz, scheme, g.ravel(), out.reshape(-1))
+    if lib().orc_grad(dim, nx, ny, nz, scheme, g.ravel(), out.reshape(-1)) != 0:
+        raise ValueError(f"scheme {scheme} is not defined in {dim}D")
     return out[:dim]
 
 
@@ -241,7 +245,8 @@ def lap(g, scheme: int, dim: int | None = None) -> np.ndarray:
     g, d0, (nz, ny, nx) = _shape3(g)
     dim = dim or max(d0, 2)
     out = np.zeros(g.shape)
-    lib().orc_lap(dim, nx, ny, nz, scheme, g.ravel(), out.reshape(-1))
+    if lib().orc_lap(dim, nx, ny, nz, scheme, g.ravel(), out.reshape(-1)) != 0:
+        raise ValueError(f"scheme {scheme} is not defined in {dim}D")
     return out
 
 

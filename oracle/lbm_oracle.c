@@ -25,8 +25,11 @@
  *     second difference per axis; of the compact schemes the composition D(D);
  *     of the isotropic schemes Eq 25b;
  *   - D3Q19 is the standard 19-velocity set (the paper only names 3D runs);
- *   - the 3D E4 weights are the D3Q19 weights divided by cs^2; the E8 weights
- *     are those that make the lattice tensors isotropic to eighth order;
+ *   - the 3D E4 weights are the D3Q19 weights divided by cs^2; the E6, E8
+ *     and E10 weights (Fig 6 names these schemes but prints no weights) are
+ *     the unique ones that make the weighted lattice tensors isotropic to
+ *     sixth, eighth and tenth order on the shells listed with them; E10 is
+ *     two-dimensional only;
  *   - OCFDS keeps the printed alpha and c; a and b come from the two
  *     fourth-order conditions so the scheme is exactly fourth order;
  *   - compact systems on a periodic line are cyclic tridiagonal, solved by the
@@ -52,7 +55,7 @@
 enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1 };
 enum { ORC_CD2 = 0, ORC_CD4 = 1, ORC_CD6 = 2, ORC_E4 = 3, ORC_E8 = 4,
        ORC_OCFDS4 = 5, ORC_CFDS4 = 6, ORC_CFDS6 = 7, ORC_CFDS8 = 8,
-       ORC_NSCHEMES = 9 };
+       ORC_E6 = 9, ORC_E10 = 10, ORC_NSCHEMES = 11 };
 
 typedef struct {
     int lattice;            /* ORC_D2Q9 or ORC_D3Q19 */
@@ -587,7 +590,7 @@ void orc_compact_coeffs(int scheme, double *out4)
 }
 
 static int is_compact(int s) { return s == ORC_OCFDS4 || s == ORC_CFDS4 || s == ORC_CFDS6 || s == ORC_CFDS8; }
-static int is_iso(int s) { return s == ORC_E4 || s == ORC_E8; }
+static int is_iso(int s) { return s == ORC_E4 || s == ORC_E6 || s == ORC_E8 || s == ORC_E10; }
 
 /* Solve the periodic (cyclic) tridiagonal system
  *   al y_{i-1} + y_i + al y_{i+1} = d_i,  i = 0..n-1 (indices mod n),
@@ -700,8 +703,28 @@ static double iso_weight(int dim, int scheme, int s)
         if (dim == 2) return s == 1 ? 1.0 / 3.0 : (s == 2 ? 1.0 / 12.0 : 0.0);  /* Sec 2.3.3 */
         return s == 1 ? 1.0 / 6.0 : (s == 2 ? 1.0 / 12.0 : 0.0);
     }
-    /* E8: eighth-order isotropic weights (unique solution of the isotropy
-     * conditions on these shells) */
+    /* Higher isotropy: the weights solving sum_i w(|e_i|^2) (e_i.n)^(2m) =
+     * C_m |n|^(2m) for every direction n and m = 1..order/2, with C_1 = 1 (so
+     * Eq 25a is a first derivative); unique on the shells listed. */
+    if (scheme == ORC_E6) {
+        if (dim == 2) {     /* shells 1, 2, 4 */
+            switch (s) { case 1: return 4.0 / 15.0; case 2: return 1.0 / 10.0; case 4: return 1.0 / 120.0; }
+            return 0.0;
+        }
+        switch (s) {        /* shells 1, 2, 3, 4 */
+        case 1: return 2.0 / 15.0; case 2: return 1.0 / 15.0; case 3: return 1.0 / 60.0; case 4: return 1.0 / 120.0;
+        }
+        return 0.0;
+    }
+    if (scheme == ORC_E10) {  /* two-dimensional only: shells 1, 2, 4, 5, 8, 9, 10 */
+        switch (s) {
+        case 1: return 262.0 / 1785.0; case 2: return 93.0 / 1190.0; case 4: return 7.0 / 340.0;
+        case 5: return 6.0 / 595.0; case 8: return 9.0 / 9520.0; case 9: return 2.0 / 5355.0;
+        case 10: return 1.0 / 7140.0;
+        }
+        return 0.0;
+    }
+    /* E8: shells 1, 2, 4, 5, 8 (2D); 1, 2, 3, 4, 5, 6, 8 (3D) */
     if (dim == 2) {
         switch (s) {
         case 1: return 4.0 / 21.0; case 2: return 4.0 / 45.0; case 4: return 1.0 / 60.0;
@@ -720,7 +743,7 @@ static double iso_weight(int dim, int scheme, int s)
 static void iso_build(int dim, int scheme, iso_stencil *S)
 {
     S->n = 0;
-    int R = (scheme == ORC_E4) ? 1 : 2;
+    int R = (scheme == ORC_E4) ? 1 : (scheme == ORC_E10 ? 3 : 2);
     int zr = (dim == 3) ? R : 0;
     for (int z = -zr; z <= zr; ++z)
         for (int y = -R; y <= R; ++y)
@@ -738,6 +761,7 @@ static void iso_build(int dim, int scheme, iso_stencil *S)
 /* Isotropic stencil table for the tests: returns the number of vectors. */
 int orc_iso_stencil(int dim, int scheme, int *e_out, double *w_out)
 {
+    if (!is_iso(scheme) || (scheme == ORC_E10 && dim == 3)) return -1;
     iso_stencil S; iso_build(dim, scheme, &S);
     for (int i = 0; i < S.n; ++i) {
         for (int d = 0; d < 3; ++d) e_out[3 * i + d] = S.e[i][d];
@@ -822,6 +846,7 @@ static void lap_field(const grid *G, int scheme, const double *g, double *out)
 int orc_grad(int dim, int nx, int ny, int nz, int scheme, const double *g, double *out)
 {
     grid G = { nx, ny, nz, dim };
+    if (scheme == ORC_E10 && dim == 3) return -1;
     grad_field(&G, scheme, g, out);
     return 0;
 }
@@ -829,6 +854,7 @@ int orc_grad(int dim, int nx, int ny, int nz, int scheme, const double *g, doubl
 int orc_lap(int dim, int nx, int ny, int nz, int scheme, const double *g, double *out)
 {
     grid G = { nx, ny, nz, dim };
+    if (scheme == ORC_E10 && dim == 3) return -1;
     lap_field(&G, scheme, g, out);
     return 0;
 }
@@ -846,6 +872,7 @@ static int check_params(const orc_params *p)
     if (!(p->Tr > 0.0 && p->Tr < 1.0)) return -1;
     if (!(p->k > 0.0) || !(p->kappa > 0.0)) return -1;
     if (p->scheme < 0 || p->scheme >= ORC_NSCHEMES) return -1;
+    if (p->scheme == ORC_E10 && p->lattice == ORC_D3Q19) return -1;
     if (p->collision != 0 && p->collision != 1) return -1;
     if (p->collision == 1 && p->lattice != ORC_D2Q9) return -1;
     return 0;

@@ -8,7 +8,8 @@ then a few steps of the benchmark workload, so one rocprofv3 run covers both.
 --trace DIR`` reads the CSV output of the counter runs (FETCH_SIZE, then
 WRITE_SIZE, KiB per dispatch) and of a kernel-trace run, scales each counter by
 what it reads for the calibration copy, and writes ``profiles/traffic.json``
-(consumed by bench.py) plus a markdown summary.
+(consumed by bench.py, one entry per workload and kernel) plus a markdown
+summary.
 """
 from __future__ import annotations
 
@@ -134,7 +135,7 @@ def summarize(args):
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(tpath)) if os.path.exists(tpath) else {}
     if ent:
-        data[args.workload] = {"kernel": dom, "bytes_per_launch": round(ent["bytes"]), "source_hash": source_hash(),
+        data[f"{args.workload} | {dom}"] = {"kernel": dom, "bytes_per_launch": round(ent["bytes"]), "source_hash": source_hash(),
                                "avg_us_rocprof": round(ent["avg_us"], 2), "fetch_scale": round(f_scale, 5),
                                "write_scale": round(w_scale, 5)}
         json.dump(data, open(tpath, "w"), indent=1)

@@ -205,12 +205,12 @@ def test_cyclic_solve_bruteforce(orc, n):
 # --------------------------------------------------------------------------- #
 # Isotropic schemes (Eq 25)                                                     #
 # --------------------------------------------------------------------------- #
-def _iso_weights_from_isotropy(dim, shells):
+def _iso_weights_from_isotropy(dim, shells, order):
     """Solve the isotropy conditions for the shell weights: the lattice tensors
-    sum_i w(|e_i|^2) e_i^(2m) are isotropic for 2m up to 2*len(shells) (2D) or
-    to the order the shells allow (3D), normalised by sum w e_x^2 = 1."""
+    sum_i w(|e_i|^2) e_i^(2m) are isotropic for 2m = 2 .. order, normalised by
+    sum w e_x^2 = 1."""
     vecs = {}
-    R = 2
+    R = math.isqrt(max(shells))
     rng_ = range(-R, R + 1)
     for v in ([(x, y, 0) for x in rng_ for y in rng_] if dim == 2 else
               [(x, y, z) for x in rng_ for y in rng_ for z in rng_]):
@@ -225,7 +225,7 @@ def _iso_weights_from_isotropy(dim, shells):
 
     eqs = [sp.Eq(mom(2, 0), 1)]
     df = lambda k: sp.factorial2(k - 1) if k > 0 else 1
-    max_m = 4 if len(shells) > 2 else 2
+    max_m = order // 2
     for m in range(2, max_m + 1):
         comps = []
         if dim == 2:
@@ -245,11 +245,16 @@ def _iso_weights_from_isotropy(dim, shells):
     return {s: sol[0][W[j]] for j, s in enumerate(shells)}
 
 
-@pytest.mark.parametrize("dim,name,shells", [
-    (2, "E4", (1, 2)), (3, "E4", (1, 2)),
-    (2, "E8", (1, 2, 4, 5, 8)), (3, "E8", (1, 2, 3, 4, 5, 6, 8))])
-def test_isotropic_weights_from_isotropy(orc, dim, name, shells):
-    wts = _iso_weights_from_isotropy(dim, shells)
+ISO_SHELLS = [
+    (2, "E4", 4, (1, 2)), (3, "E4", 4, (1, 2)),
+    (2, "E6", 6, (1, 2, 4)), (3, "E6", 6, (1, 2, 3, 4)),
+    (2, "E8", 8, (1, 2, 4, 5, 8)), (3, "E8", 8, (1, 2, 3, 4, 5, 6, 8)),
+    (2, "E10", 10, (1, 2, 4, 5, 8, 9, 10))]
+
+
+@pytest.mark.parametrize("dim,name,order,shells", ISO_SHELLS)
+def test_isotropic_weights_from_isotropy(orc, dim, name, order, shells):
+    wts = _iso_weights_from_isotropy(dim, shells, order)
     if (dim, name) == (2, "E4"):
         # Sec 2.3.3 prints w(1) = 1/3, w(2) = 1/12
         assert wts == {1: sp.Rational(1, 3), 2: sp.Rational(1, 12)}
@@ -277,9 +282,44 @@ def test_e4_equals_cd2_on_one_dimensional_fields(orc):
     np.testing.assert_allclose(orc.lap(g3, orc.E4), orc.lap(g3, orc.CD2), atol=1e-13)
 
 
+@pytest.mark.parametrize("dim,name,order,shells", ISO_SHELLS)
+def test_isotropic_plane_wave_anisotropy_order(orc, dim, name, order, shells):
+    """Eq 25a applied to exp(i k n.x) gives i k_eff n-ish with, along n,
+    k_eff(n) = sum_i w (e_i.n) sin(k e_i.n).  Tensors isotropic to rank
+    `order` leave the direction dependence of k_eff at O(k^(order+1)), so
+    halving k shrinks the spread over directions by 2^(order+1)."""
+    e, w = orc.iso_stencil(dim, orc.SCHEME_NAMES[name])
+    rng = np.random.default_rng(3)
+    dirs = rng.standard_normal((400, 3))
+    if dim == 2:
+        dirs[:, 2] = 0.0
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+
+    def spread(k):
+        proj = dirs @ e.T.astype(float)            # e_i . n
+        keff = (w[None, :] * proj * np.sin(k * proj)).sum(axis=1)
+        return keff.max() - keff.min()
+
+    k = 0.4
+    ratio = spread(k) / spread(k / 2)
+    assert ratio == pytest.approx(2.0 ** (order + 1), rel=0.08)
+    # and the isotropic part is the exact derivative to first order
+    proj = dirs[:1] @ e.T.astype(float)
+    assert (w * proj * np.sin(1e-4 * proj)).sum() / 1e-4 == pytest.approx(1.0, abs=1e-7)
+
+
+def test_isotropic_e10_is_two_dimensional_only(orc):
+    with pytest.raises(ValueError):
+        orc.iso_stencil(3, orc.E10)
+    with pytest.raises(ValueError):
+        orc.grad(np.zeros((4, 5, 6)), orc.E10)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("name", ["E4", "E8"])
+@pytest.mark.parametrize("name", ["E4", "E6", "E8", "E10"])
 def test_isotropic_second_order_exact_on_quadratics(orc, dim, name):
+    if (dim, name) == (3, "E10"):
+        pytest.skip("E10 is two-dimensional only")
     sch = orc.SCHEME_NAMES[name]
     shape = (13, 14) if dim == 2 else (11, 12, 13)
     idx = np.meshgrid(*[np.arange(s) - s // 2 for s in shape], indexing="ij")
