@@ -49,14 +49,16 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
 /* Difference schemes of Sec 2.3:
  *   CD2, CD4, CD6  explicit central first derivatives of Eq 18-20; Laplacian
  *                  the matched-order central second difference per axis;
- *   E4, E8         isotropic differences of Eq 25a/25b (fourth- and
- *                  eighth-order isotropy);
+ *   E4, E6, E8, E10  isotropic differences of Eq 25a/25b with fourth-, sixth-,
+ *                  eighth- and tenth-order isotropy (the four of Fig 6); E10
+ *                  is defined in 2D only (LBM_EINVAL for D3Q19);
  *   OCFDS4         the optimised fourth-order compact scheme of Sec 3.1
  *                  (Eq 21 with beta = 0, alpha = 0.446776, c = -0.0541132);
  *   CFDS4/6/8      the compact schemes of Eq 22-24.
  * For the compact schemes the Laplacian is D(D(rho)) per axis. */
 enum { LBM_CD2 = 0, LBM_CD4 = 1, LBM_CD6 = 2, LBM_E4 = 3, LBM_E8 = 4,
-       LBM_OCFDS4 = 5, LBM_CFDS4 = 6, LBM_CFDS6 = 7, LBM_CFDS8 = 8 };
+       LBM_OCFDS4 = 5, LBM_CFDS4 = 6, LBM_CFDS6 = 7, LBM_CFDS8 = 8,
+       LBM_E6 = 9, LBM_E10 = 10 };
 
 /* Collision operators of Eq 1. */
 enum { LBM_SRT = 0, LBM_MRT = 1 };
@@ -71,7 +73,7 @@ typedef struct {
     double Tr;               /* reduced temperature T/Tc, 0 < Tr < 1 (Sec 2.2) */
     double k;                /* proportional coefficient of Eq 16, > 0 */
     double kappa;            /* kappa-hat of Eq 16, > 0 */
-    int    scheme;           /* LBM_CD2 .. LBM_CFDS8 */
+    int    scheme;           /* LBM_CD2 .. LBM_E10 */
     double a, b, R, omega;   /* Peng-Robinson constants of Eq 14; 0 selects the
                                 paper's a = 2/49, b = 2/21, R = 1, omega = 0.344 */
     int    collision;        /* LBM_SRT (0) or LBM_MRT (D2Q9 only) */

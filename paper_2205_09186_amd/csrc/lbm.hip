@@ -55,7 +55,8 @@ const char* validate(const lbm_params* p)
     if (!(p->Tr > 0.0 && p->Tr < 1.0)) return "Tr must lie in (0, 1)";
     if (!(p->k > 0.0) || !std::isfinite(p->k)) return "k must be > 0";
     if (!(p->kappa > 0.0) || !std::isfinite(p->kappa)) return "kappa must be > 0";
-    if (p->scheme < LBM_CD2 || p->scheme > LBM_CFDS8) return "unknown scheme";
+    if (p->scheme < LBM_CD2 || p->scheme > LBM_E10) return "unknown scheme";
+    if (p->scheme == LBM_E10 && p->lattice == LBM_D3Q19) return "E10 is defined in two dimensions only";
     if (p->a < 0.0 || p->b < 0.0 || p->R < 0.0 || p->omega < 0.0) return "negative EOS constant";
     if (p->collision != LBM_SRT && p->collision != LBM_MRT) return "unknown collision operator";
     if (p->collision == LBM_MRT && p->lattice != LBM_D2Q9) return "the MRT collision is defined for D2Q9 (Eq 3)";
@@ -91,7 +92,7 @@ Layout layout_of(const lbm_params* p)
     const long long N = (long long)p->nx * p->ny * p->nz;
     const int Q = p->lattice == LBM_D2Q9 ? 9 : 19;
     const int dim = p->lattice == LBM_D2Q9 ? 2 : 3;
-    const bool compact = p->scheme >= LBM_OCFDS4;
+    const bool compact = is_compact(p->scheme);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.S0 = take(sizeof(double) * Q * pop_stride(N));
@@ -324,12 +325,12 @@ void dispatch(int lat, int sch, A... a)
     if (lat == LBM_D2Q9) {
         switch (sch) {
             LBM_CASE(0, 0) LBM_CASE(0, 1) LBM_CASE(0, 2) LBM_CASE(0, 3) LBM_CASE(0, 4)
-            LBM_CASE(0, 5) LBM_CASE(0, 6) LBM_CASE(0, 7) LBM_CASE(0, 8)
+            LBM_CASE(0, 5) LBM_CASE(0, 6) LBM_CASE(0, 7) LBM_CASE(0, 8) LBM_CASE(0, 9) LBM_CASE(0, 10)
         }
     } else {
         switch (sch) {
             LBM_CASE(1, 0) LBM_CASE(1, 1) LBM_CASE(1, 2) LBM_CASE(1, 3) LBM_CASE(1, 4)
-            LBM_CASE(1, 5) LBM_CASE(1, 6) LBM_CASE(1, 7) LBM_CASE(1, 8)
+            LBM_CASE(1, 5) LBM_CASE(1, 6) LBM_CASE(1, 7) LBM_CASE(1, 8) LBM_CASE(1, 9)
         }
     }
 #undef LBM_CASE
@@ -386,7 +387,7 @@ void set_lines(lbm_ctx* c)
         lg.nch = (lg.n + lg.C - 1) / lg.C;
         lg.K = 0;
     }
-    if (c->p.scheme >= LBM_OCFDS4) {
+    if (is_compact(c->p.scheme)) {
         const Compact cc = compact_scheme(c->p.scheme);
         c->z = (-1.0 + std::sqrt(1.0 - 4.0 * cc.al * cc.al)) / (2.0 * cc.al);
         c->zscale = 1.0 + c->z * c->z;
@@ -440,7 +441,7 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->mu = reinterpret_cast<double*>(c->ws + L.mu);
     c->force = c->g.N < (1LL << 29) ? reinterpret_cast<double*>(c->ws + L.force) : nullptr;
     c->ringsum = (c->force && tile_fits(c->g, kTileTY)) ? reinterpret_cast<double*>(c->ws + L.ringsum) : nullptr;
-    const bool compact = p->scheme >= LBM_OCFDS4;
+    const bool compact = is_compact(p->scheme);
     c->grho = compact ? reinterpret_cast<double*>(c->ws + L.grho) : nullptr;
     c->gmu = compact ? reinterpret_cast<double*>(c->ws + L.gmu) : nullptr;
     c->lap = compact ? reinterpret_cast<double*>(c->ws + L.lap) : nullptr;
@@ -908,7 +909,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         I.nblk = (int)((c->g.N + BNODES - 1) / BNODES);
         for (int k = 0; k < I.nblk; ++k) blk_inst.push_back(i);
         I.part0 = I.blk0;
-        if (ps[i].scheme >= LBM_OCFDS4) b->has_compact = 1;
+        if (is_compact(ps[i].scheme)) b->has_compact = 1;
     }
     if (rc != LBM_OK) { std::string e = b->err; lbm_batch_free(b); return bfail(nullptr, rc, e); }
     size_t off = B.tables;
@@ -921,7 +922,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     int convM[4];
     for (int k = 0; k < 4; ++k) convM[k] = compact_conv(LBM_OCFDS4 + k, conv.data() + k * kConvMax);
     for (int i = 0; i < n; ++i) {
-        if (ps[i].scheme >= LBM_OCFDS4) {
+        if (is_compact(ps[i].scheme)) {
             const int k = ps[i].scheme - LBM_OCFDS4;
             b->inst[i].cconv = d_conv + k * kConvMax;
             b->inst[i].M = convM[k];

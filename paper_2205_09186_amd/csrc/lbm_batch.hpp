@@ -69,7 +69,9 @@ __device__ void b_force_any(const BInst& I, long long n, int x, int y, double r,
     case CD4: b_force<CD4>(I, n, x, y, r, Fx, Fy, Fz); break;
     case CD6: b_force<CD6>(I, n, x, y, r, Fx, Fy, Fz); break;
     case E4: b_force<E4>(I, n, x, y, r, Fx, Fy, Fz); break;
+    case E6: b_force<E6>(I, n, x, y, r, Fx, Fy, Fz); break;
     case E8: b_force<E8>(I, n, x, y, r, Fx, Fy, Fz); break;
+    case E10: b_force<E10>(I, n, x, y, r, Fx, Fy, Fz); break;
     default: b_force<OCFDS4>(I, n, x, y, r, Fx, Fy, Fz); break;   // gradient fields
     }
 }
@@ -143,6 +145,8 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
                 case CD4: b_mu_node<CD4>(I, n, x, y); break;
                 case CD6: b_mu_node<CD6>(I, n, x, y); break;
                 case E4: b_mu_node<E4>(I, n, x, y); break;
+                case E6: b_mu_node<E6>(I, n, x, y); break;
+                case E10: b_mu_node<E10>(I, n, x, y); break;
                 default: b_mu_node<E8>(I, n, x, y); break;
                 }
             }

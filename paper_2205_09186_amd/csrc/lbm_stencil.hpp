@@ -5,16 +5,17 @@
 
 namespace lbm {
 
-enum Scheme { CD2 = 0, CD4 = 1, CD6 = 2, E4 = 3, E8 = 4, OCFDS4 = 5, CFDS4 = 6, CFDS6 = 7, CFDS8 = 8 };
+enum Scheme { CD2 = 0, CD4 = 1, CD6 = 2, E4 = 3, E8 = 4, OCFDS4 = 5, CFDS4 = 6, CFDS6 = 7, CFDS8 = 8,
+              E6 = 9, E10 = 10 };
 
-__host__ __device__ constexpr bool is_compact(int s) { return s >= OCFDS4; }
-__host__ __device__ constexpr bool is_iso(int s) { return s == E4 || s == E8; }
+__host__ __device__ constexpr bool is_compact(int s) { return s >= OCFDS4 && s <= CFDS8; }
+__host__ __device__ constexpr bool is_iso(int s) { return s == E4 || s == E6 || s == E8 || s == E10; }
 
 // Stencil radius of the explicit operators (compact schemes: radius of the
 // right-hand side of Eq 21).
 __host__ __device__ constexpr int radius(int s)
 {
-    return s == CD2 ? 1 : s == CD4 ? 2 : s == CD6 ? 3 : s == E4 ? 1 : s == E8 ? 2 : 3;
+    return s == CD2 ? 1 : s == CD4 ? 2 : s == CD6 ? 3 : s == E4 ? 1 : s == E6 ? 2 : s == E8 ? 2 : 3;
 }
 
 // Explicit central first derivative, Eq 18-20: f' = sum_m d1(m) (f[+m] - f[-m]).
@@ -36,14 +37,25 @@ __host__ __device__ constexpr double d2(int s, int m)
 }
 
 // Isotropic weights w(|e|^2) of Eq 25.  E4 in 2D as printed in Sec 2.3.3; in 3D
-// the D3Q19 weights divided by cs^2.  E8: the weights that make the lattice
-// tensors isotropic to eighth order on the shells |e|^2 = 1,2,4,5,8 (2D) and
-// 1,2,3,4,5,6,8 (3D).
+// the D3Q19 weights divided by cs^2.  E6, E8, E10 (the higher isotropy orders
+// of Fig 6): the weights for which sum_i w (e_i.n)^(2m) is a multiple of
+// |n|^(2m) for every 2m up to the order, with sum_i w e_ix^2 = 1, on the
+// shells |e|^2 = 1,2,4 (E6, 2D), 1,2,3,4 (E6, 3D), 1,2,4,5,8 (E8, 2D),
+// 1,2,3,4,5,6,8 (E8, 3D) and 1,2,4,5,8,9,10 (E10, 2D only).
 __host__ __device__ constexpr double iso_w(int dim, int s, int sh)
 {
-    return s == E4 ? (dim == 2 ? (sh == 1 ? 1.0 / 3.0 : sh == 2 ? 1.0 / 12.0 : 0.0)
-                               : (sh == 1 ? 1.0 / 6.0 : sh == 2 ? 1.0 / 12.0 : 0.0))
-         : dim == 2 ? (sh == 1 ? 4.0 / 21.0 : sh == 2 ? 4.0 / 45.0 : sh == 4 ? 1.0 / 60.0
+    if (s == E4)
+        return dim == 2 ? (sh == 1 ? 1.0 / 3.0 : sh == 2 ? 1.0 / 12.0 : 0.0)
+                        : (sh == 1 ? 1.0 / 6.0 : sh == 2 ? 1.0 / 12.0 : 0.0);
+    if (s == E6)
+        return dim == 2 ? (sh == 1 ? 4.0 / 15.0 : sh == 2 ? 1.0 / 10.0 : sh == 4 ? 1.0 / 120.0 : 0.0)
+                        : (sh == 1 ? 2.0 / 15.0 : sh == 2 ? 1.0 / 15.0 : sh == 3 ? 1.0 / 60.0
+                           : sh == 4 ? 1.0 / 120.0 : 0.0);
+    if (s == E10)
+        return sh == 1 ? 262.0 / 1785.0 : sh == 2 ? 93.0 / 1190.0 : sh == 4 ? 7.0 / 340.0
+             : sh == 5 ? 6.0 / 595.0 : sh == 8 ? 9.0 / 9520.0 : sh == 9 ? 2.0 / 5355.0
+             : sh == 10 ? 1.0 / 7140.0 : 0.0;
+    return dim == 2 ? (sh == 1 ? 4.0 / 21.0 : sh == 2 ? 4.0 / 45.0 : sh == 4 ? 1.0 / 60.0
                        : sh == 5 ? 2.0 / 315.0 : sh == 8 ? 1.0 / 5040.0 : 0.0)
                     : (sh == 1 ? 4.0 / 45.0 : sh == 2 ? 1.0 / 21.0 : sh == 3 ? 2.0 / 105.0
                        : sh == 4 ? 5.0 / 504.0 : sh == 5 ? 1.0 / 315.0 : sh == 6 ? 1.0 / 630.0

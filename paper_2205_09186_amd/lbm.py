@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 D2Q9, D3Q19 = 0, 1
 SRT, MRT = 0, 1
-CD2, CD4, CD6, E4, E8, OCFDS4, CFDS4, CFDS6, CFDS8 = range(9)
+CD2, CD4, CD6, E4, E8, OCFDS4, CFDS4, CFDS6, CFDS8, E6, E10 = range(11)
 SCHEMES = {"CD2": CD2, "CD4": CD4, "CD6": CD6, "E4": E4, "E8": E8, "OCFDS4": OCFDS4,
-           "CFDS4": CFDS4, "CFDS6": CFDS6, "CFDS8": CFDS8}
+           "CFDS4": CFDS4, "CFDS6": CFDS6, "CFDS8": CFDS8, "E6": E6, "E10": E10}
 LBM_OK, LBM_EINVAL, LBM_ENOSPC, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 
 

@@ -179,7 +179,7 @@ def exact_droplet_force(x, y, x0, y0, r0, W, rho_g, rho_l, Tr, k, kappa):
 
 
 def force_angles(Tr=0.7, n=300, r0=60.0, W=10.0, k=0.16, kappa=0.004,
-                 schemes=("CD2", "CD4", "CD6", "E4", "E8", "CFDS4", "CFDS6", "OCFDS4")):
+                 schemes=("CD2", "CD4", "CD6", "E4", "E6", "E8", "E10", "CFDS4", "CFDS6", "OCFDS4")):
     """Angle deviation (Eq 30) and relative error of the force of the Eq 26
     droplet, over nodes with |F| above 1% of its maximum."""
     g, l = lbm.coexistence(Tr)

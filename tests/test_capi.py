@@ -31,7 +31,8 @@ def test_workspace_validation():
     ok = lbm.Params(lattice=lbm.D3Q19, nx=16, ny=16, nz=16, scheme=lbm.CD6)
     nb = lbm.workspace_bytes(ok)
     assert nb >= 2 * 19 * 16 ** 3 * 8
-    bad = [dict(tau=0.5), dict(Tr=1.0), dict(Tr=0.0), dict(k=0.0), dict(kappa=-1.0), dict(scheme=9),
+    bad = [dict(tau=0.5), dict(Tr=1.0), dict(Tr=0.0), dict(k=0.0), dict(kappa=-1.0), dict(scheme=11),
+           dict(scheme=-1), dict(scheme=lbm.E10),
            dict(nz=1), dict(nx=3), dict(lattice=2), dict(collision=2), dict(collision=lbm.MRT),
            dict(collision=lbm.MRT, s_e=2.0), dict(s_q=-1.0)]
     for b in bad:
@@ -39,6 +40,9 @@ def test_workspace_validation():
         assert lbm.workspace_bytes(q) == 0, b
     q2 = lbm.Params(lattice=lbm.D2Q9, nx=16, ny=16, nz=2)
     assert lbm.workspace_bytes(q2) == 0
+    # E6 in both dimensions, E10 in 2D only
+    assert lbm.workspace_bytes(lbm.Params(**{**ok.__dict__, "scheme": lbm.E6})) > 0
+    assert lbm.workspace_bytes(lbm.Params(lattice=lbm.D2Q9, nx=16, ny=16, scheme=lbm.E10)) > 0
     # MRT is defined for D2Q9 (Eq 3)
     assert lbm.workspace_bytes(lbm.Params(lattice=lbm.D2Q9, nx=16, ny=16, collision=lbm.MRT)) > 0
     # compact schemes need the gradient fields as well

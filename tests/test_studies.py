@@ -61,3 +61,32 @@ def test_cumulative_rule_is_fourth_order():
         if n == 41:
             e1 = err
     assert 12 < e1 / err < 20
+
+
+def test_isotropy_order_trades_angle_for_accuracy(orc):
+    """Sec 3.2, Fig 6 and 7 with the oracle's force on the Eq 26 droplet: raising
+    the isotropy order E4 -> E6 -> E8 -> E10 lowers the angle deviation of
+    Eq 30 and raises the force error; CD6 deviates no more than E4 in angle
+    and is far more accurate."""
+    Tr, n, r0, W, k, kappa = 0.7, 120, 30.0, 10.0, 0.16, 0.004
+    g, l = orc.maxwell(Tr)
+    yy, xx = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64), indexing="ij")
+    x0 = y0 = n // 2
+    Fx_e, Fy_e, rho = studies.exact_droplet_force(xx, yy, x0, y0, r0, W, g, l, Tr, k, kappa)
+    mag = np.hypot(Fx_e, Fy_e)
+    sel = mag > 0.01 * mag.max()
+    ang, err = {}, {}
+    for s in ("E4", "E6", "E8", "E10", "CD6"):
+        F, _ = orc.force(orc.Params(lattice=0, nx=n, ny=n, Tr=Tr, k=k, kappa=kappa,
+                                    scheme=orc.SCHEME_NAMES[s]), rho)
+        F = F.reshape(2, n, n)
+        Fx, Fy = F[0][sel], F[1][sel]
+        dth = np.angle(np.exp(1j * (np.arctan2(Fy, Fx) - np.arctan2(-(yy[sel] - y0), -(xx[sel] - x0)))))
+        ang[s] = np.sqrt(np.mean(dth ** 2))
+        err[s] = np.sqrt(np.mean((Fx - Fx_e[sel]) ** 2 + (Fy - Fy_e[sel]) ** 2)) / mag[sel].max()
+    iso = ("E4", "E6", "E8", "E10")
+    for a, b in zip(iso, iso[1:]):
+        assert ang[b] < 0.2 * ang[a], (a, b, ang)
+        assert err[b] > err[a], (a, b, err)
+    assert ang["CD6"] < ang["E4"]
+    assert err["CD6"] < 0.05 * err["E4"]
