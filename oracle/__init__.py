@@ -48,7 +48,8 @@ class _Params(C.Structure):
                 ("kappa", C.c_double), ("scheme", C.c_int),
                 ("a", C.c_double), ("b", C.c_double), ("R", C.c_double),
                 ("omega", C.c_double), ("collision", C.c_int), ("s_e", C.c_double),
-                ("s_eps", C.c_double), ("s_q", C.c_double)]
+                ("s_eps", C.c_double), ("s_q", C.c_double), ("solid", C.c_void_p),
+                ("mu_wall", C.c_double)]
 
 
 _lib = None
@@ -71,6 +72,7 @@ def lib():
         L.orc_collide_node_mrt.argtypes = [D, D, D, D, dp, D, D, D, dp]
         L.orc_mrt_matrix.argtypes = [dp, dp]
         L.orc_force.argtypes = [P, dp, dp, dp]
+        L.orc_wall_density.argtypes = [P, dp, ip]
         L.orc_pr_alpha.argtypes = [D, D]; L.orc_pr_alpha.restype = D
         L.orc_pr_p0.argtypes = [D, D, D, D, D]; L.orc_pr_p0.restype = D
         L.orc_pr_mub.argtypes = [D, D, D, D, D]; L.orc_pr_mub.restype = D
@@ -153,6 +155,17 @@ def force(p: "Params", rho):
     dim = 2 if p.lattice == D2Q9 else 3
     shape = np.shape(rho)
     return F[: dim * r.size].reshape((dim,) + shape), mu.reshape(shape)
+
+
+def wall_density(p: "Params", rho):
+    """(rho with the solid layers filled by Eq A.1, layer map) for p.solid:
+    layer 0 fluid, 1..r the solid layers, -1 solid beyond them (Appendix)."""
+    cp = p.c()
+    r = np.array(rho, dtype=np.float64).reshape(-1)
+    layer = np.zeros(r.size, np.int32)
+    if lib().orc_wall_density(C.byref(cp), r, layer):
+        raise ValueError("invalid parameters or no solid")
+    return r.reshape(np.shape(rho)), layer.reshape(np.shape(rho))
 
 
 def mrt_matrix():
@@ -273,6 +286,8 @@ class Params:
     s_e: float = 0.0
     s_eps: float = 0.0
     s_q: float = 0.0
+    solid: np.ndarray | None = None   # uint8 per node (x fastest); nonzero = solid (Appendix)
+    mu_wall: float = 0.0              # mu_hat on the solid layers
 
     @property
     def q(self) -> int:
@@ -283,9 +298,15 @@ class Params:
         return self.nx * self.ny * self.nz
 
     def c(self) -> _Params:
+        sp = None
+        if self.solid is not None:
+            # keep a contiguous uint8 copy alive as long as this Params
+            self._solid_buf = np.ascontiguousarray(self.solid, dtype=np.uint8).reshape(-1)
+            assert self._solid_buf.size == self.n
+            sp = self._solid_buf.ctypes.data
         return _Params(self.lattice, self.nx, self.ny, self.nz, self.tau, self.Tr, self.k,
                        self.kappa, self.scheme, self.a, self.b, self.R, self.omega, self.collision,
-                       self.s_e, self.s_eps, self.s_q)
+                       self.s_e, self.s_eps, self.s_q, sp, self.mu_wall)
 
 
 class Sim:

@@ -33,7 +33,13 @@
  *   - OCFDS keeps the printed alpha and c; a and b come from the two
  *     fourth-order conditions so the scheme is exactly fourth order;
  *   - compact systems on a periodic line are cyclic tridiagonal, solved by the
- *     Thomas algorithm (Sec 2.3.2) with a Sherman-Morrison correction.
+ *     Thomas algorithm (Sec 2.3.2) with a Sherman-Morrison correction;
+ *   - solid nodes (Appendix): the layers are counted through the lattice
+ *     directions, as many as the central scheme's radius; their density is
+ *     Eq A.1 layer by layer and their chemical potential the given mu_wall;
+ *     the populations meet the wall by halfway bounce-back (the paper does not
+ *     name one); only the central schemes of Eq 18-20 take walls, as the
+ *     appendix describes them for those.
  *
  * Parity of every function here is pinned by the CPU tests (polynomial
  * exactness, modified wavenumber Eq 28, Table 1 constants, moment identities,
@@ -69,6 +75,9 @@ typedef struct {
     int collision;          /* 0: SRT; 1: MRT (D2Q9, Eq 1, 3, 5) */
     double s_e, s_eps, s_q; /* MRT rates of the energy, energy-square and heat-flux
                                moments; 0 selects the values of Sec 2.1 */
+    const unsigned char *solid; /* NULL: every node is fluid; else nonzero marks a
+                                   solid node of the wetting boundary (Appendix) */
+    double mu_wall;         /* mu_hat assigned to the solid layers (Appendix) */
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -875,6 +884,7 @@ static int check_params(const orc_params *p)
     if (p->scheme == ORC_E10 && p->lattice == ORC_D3Q19) return -1;
     if (p->collision != 0 && p->collision != 1) return -1;
     if (p->collision == 1 && p->lattice != ORC_D2Q9) return -1;
+    if (p->solid && p->scheme > ORC_CD6) return -1;
     return 0;
 }
 
@@ -901,11 +911,87 @@ static int eos_of(const orc_params *p, eos_t *E)
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Wetting boundary (Appendix)                                                 */
+/* ------------------------------------------------------------------------- */
+
+static int cd_radius(int scheme) { return scheme == ORC_CD2 ? 1 : (scheme == ORC_CD4 ? 2 : 3); }
+
+static int opposite(const orc_lattice *L, int i)
+{
+    for (int j = 0; j < L->q; ++j)
+        if (L->e[j][0] == -L->e[i][0] && L->e[j][1] == -L->e[i][1] && L->e[j][2] == -L->e[i][2]) return j;
+    return -1;
+}
+
+/* layer[n] = 0 on fluid nodes.  A solid node joins layer l (1 <= l <= r) when
+ * one of its lattice neighbours x + e_i lies in layer l - 1; solid nodes that
+ * no layer reaches get -1.  r is the stencil radius of the central scheme
+ * (1, 2, 3 layers for CD2, CD4, CD6).  NULL when there is no solid. */
+static int *wall_layers(const orc_params *p, const orc_lattice *L, const grid *G)
+{
+    if (!p->solid) return NULL;
+    long N = (long)G->nx * G->ny * G->nz;
+    int *layer = (int *)malloc(sizeof(int) * N);
+    for (long n = 0; n < N; ++n) layer[n] = p->solid[n] ? -1 : 0;
+    for (int l = 1; l <= cd_radius(p->scheme); ++l)
+        for (int z = 0; z < G->nz; ++z)
+            for (int y = 0; y < G->ny; ++y)
+                for (int x = 0; x < G->nx; ++x) {
+                    long n = gidx(G, x, y, z);
+                    if (layer[n] != -1) continue;
+                    for (int i = 1; i < L->q; ++i)
+                        if (layer[gidx(G, x + L->e[i][0], y + L->e[i][1], z + L->e[i][2])] == l - 1) {
+                            layer[n] = l;
+                            break;
+                        }
+                }
+    return layer;
+}
+
+/* Eq A.1: the density of a layer-l node is the lattice-weighted mean of its
+ * neighbours in layer l - 1 (s_w selects them), layer after layer.  Solid
+ * nodes beyond the last layer get 1 (no fluid stencil reaches them). */
+static void wall_density(const orc_params *p, const orc_lattice *L, const grid *G, const int *layer, double *rho)
+{
+    for (int l = 1; l <= cd_radius(p->scheme); ++l)
+        for (int z = 0; z < G->nz; ++z)
+            for (int y = 0; y < G->ny; ++y)
+                for (int x = 0; x < G->nx; ++x) {
+                    long n = gidx(G, x, y, z);
+                    if (layer[n] != l) continue;
+                    double num = 0.0, den = 0.0;
+                    for (int i = 1; i < L->q; ++i) {
+                        long m = gidx(G, x + L->e[i][0], y + L->e[i][1], z + L->e[i][2]);
+                        if (layer[m] == l - 1) { num += L->w[i] * rho[m]; den += L->w[i]; }
+                    }
+                    rho[n] = num / den;
+                }
+    long N = (long)G->nx * G->ny * G->nz;
+    for (long n = 0; n < N; ++n)
+        if (layer[n] < 0) rho[n] = 1.0;
+}
+
+/* For the tests: the layer map (int per node) and, in place, the density of
+ * the solid layers by Eq A.1 from the fluid densities in rho. */
+int orc_wall_density(const orc_params *p, double *rho, int *layer_out)
+{
+    if (check_params(p) || !p->solid) return -1;
+    orc_lattice L; get_lattice(p->lattice, &L);
+    grid G = { p->nx, p->ny, p->nz, p->lattice == ORC_D2Q9 ? 2 : 3 };
+    int *layer = wall_layers(p, &L, &G);
+    wall_density(p, &L, &G, layer, rho);
+    long N = (long)p->nx * p->ny * p->nz;
+    if (layer_out) memcpy(layer_out, layer, sizeof(int) * N);
+    free(layer);
+    return 0;
+}
+
 /* Steps 1-5 of the step on the post-streaming state f: rho, j, and the force
  * F = -rho grad(mu_hat) + cs^2 grad(rho), with
  * mu_hat = k^2 psi'(rho) - kappa_hat lap(rho) (Eq 12, 16). */
 static void force_of_rho(const orc_params *p, const grid *G, const eos_t *E, const double *rho,
-                         double *mu, double *F)
+                         const int *layer, double *mu, double *F)
 {
     long N = (long)G->nx * G->ny * G->nz;
     double *lap = (double *)malloc(sizeof(double) * N);
@@ -916,18 +1002,22 @@ static void force_of_rho(const orc_params *p, const grid *G, const eos_t *E, con
     #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n)
         mu[n] = p->k * p->k * orc_pr_mub(rho[n], E->T, E->aa, E->b, E->R) - p->kappa * lap[n];
+    if (layer)          /* the wall's chemical potential (Appendix) */
+        for (long n = 0; n < N; ++n)
+            if (layer[n] != 0) mu[n] = p->mu_wall;
     /* 4. gradients */
     grad_field(G, p->scheme, rho, grho);
     grad_field(G, p->scheme, mu, gmu);
     /* 5. force */
     for (int d = 0; d < 3; ++d)
         for (long n = 0; n < N; ++n)
-            F[d * N + n] = (d < G->dim) ? (-rho[n] * gmu[d * N + n] + CS2 * grho[d * N + n]) : 0.0;
+            F[d * N + n] = (d < G->dim && !(layer && layer[n] != 0))
+                           ? (-rho[n] * gmu[d * N + n] + CS2 * grho[d * N + n]) : 0.0;
     free(lap); free(grho); free(gmu);
 }
 
 static int force_fields(const orc_params *p, const orc_lattice *L, const double *f,
-                        double *rho, double *j /* 3N */, double *F /* 3N */)
+                        const int *layer, double *rho, double *j /* 3N */, double *F /* 3N */)
 {
     grid G = { p->nx, p->ny, p->nz, p->lattice == ORC_D2Q9 ? 2 : 3 };
     long N = (long)p->nx * p->ny * p->nz;
@@ -943,8 +1033,9 @@ static int force_fields(const orc_params *p, const orc_lattice *L, const double 
         }
         rho[n] = r; j[n] = jx; j[N + n] = jy; j[2 * N + n] = jz;
     }
+    if (layer) wall_density(p, L, &G, layer, rho);
     double *mu = (double *)malloc(sizeof(double) * N);
-    force_of_rho(p, &G, &E, rho, mu, F);
+    force_of_rho(p, &G, &E, rho, layer, mu, F);
     free(mu);
     return 0;
 }
@@ -957,7 +1048,14 @@ int orc_force(const orc_params *p, const double *rho, double *mu, double *F)
     grid G = { p->nx, p->ny, p->nz, p->lattice == ORC_D2Q9 ? 2 : 3 };
     eos_t E;
     if (eos_of(p, &E)) return -1;
-    force_of_rho(p, &G, &E, rho, mu, F);
+    orc_lattice L; get_lattice(p->lattice, &L);
+    int *layer = wall_layers(p, &L, &G);
+    long N = (long)p->nx * p->ny * p->nz;
+    double *r = (double *)malloc(sizeof(double) * N);
+    memcpy(r, rho, sizeof(double) * N);
+    if (layer) wall_density(p, &L, &G, layer, r);
+    force_of_rho(p, &G, &E, r, layer, mu, F);
+    free(r); free(layer);
     return 0;
 }
 
@@ -969,6 +1067,10 @@ int orc_init(const orc_params *p, const double *rho0, double *f)
     long N = (long)p->nx * p->ny * p->nz;
     const double zero[3] = { 0.0, 0.0, 0.0 };
     for (long n = 0; n < N; ++n) {
+        if (p->solid && p->solid[n]) {       /* no populations on solid nodes */
+            for (int i = 0; i < L.q; ++i) f[(long)i * N + n] = 0.0;
+            continue;
+        }
         if (!(rho0[n] > 0.0) || !isfinite(rho0[n])) return -1;
         for (int i = 0; i < L.q; ++i) f[(long)i * N + n] = feq_i(&L, i, rho0[n], zero);
     }
@@ -985,25 +1087,37 @@ int orc_step(const orc_params *p, const double *f, double *fout)
     double *rho = (double *)malloc(sizeof(double) * N);
     double *j = (double *)malloc(sizeof(double) * 3 * N);
     double *F = (double *)malloc(sizeof(double) * 3 * N);
-    if (force_fields(p, &L, f, rho, j, F)) { free(rho); free(j); free(F); return -1; }
+    int *layer = wall_layers(p, &L, &G);
+    if (force_fields(p, &L, f, layer, rho, j, F)) { free(rho); free(j); free(F); free(layer); return -1; }
     double S[9];
     rates_of(p, S);
     if (p->collision == 1 && !mrt_ready) mrt_setup();
-    /* 6. collision, 7. streaming f_i(x + e_i, t+1) = f*_i(x, t) */
+    int opp[19];
+    for (int i = 0; i < L.q; ++i) opp[i] = opposite(&L, i);
+    if (layer)
+        for (long n = 0; n < N; ++n)
+            if (layer[n] != 0)
+                for (int i = 0; i < L.q; ++i) fout[(long)i * N + n] = 0.0;
+    /* 6. collision, 7. streaming f_i(x + e_i, t+1) = f*_i(x, t); a population
+     * whose target is solid returns to its node reversed (halfway bounce-back) */
     #pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < G.nz; ++z)
         for (int y = 0; y < G.ny; ++y)
             for (int x = 0; x < G.nx; ++x) {
                 long n = gidx(&G, x, y, z);
+                if (layer && layer[n] != 0) continue;
                 double fl[19], fs[19];
                 for (int i = 0; i < L.q; ++i) fl[i] = f[(long)i * N + n];
                 double Fn[3] = { F[n], F[N + n], F[2 * N + n] };
                 if (p->collision == 1) collide_node_mrt(&L, S, fl, Fn, fs);
                 else collide_node(&L, p->tau, fl, Fn, fs);
-                for (int i = 0; i < L.q; ++i)
-                    fout[(long)i * N + gidx(&G, x + L.e[i][0], y + L.e[i][1], z + L.e[i][2])] = fs[i];
+                for (int i = 0; i < L.q; ++i) {
+                    long m = gidx(&G, x + L.e[i][0], y + L.e[i][1], z + L.e[i][2]);
+                    if (layer && layer[m] != 0) fout[(long)opp[i] * N + n] = fs[i];
+                    else fout[(long)i * N + m] = fs[i];
+                }
             }
-    free(rho); free(j); free(F);
+    free(rho); free(j); free(F); free(layer);
     return 0;
 }
 
@@ -1029,19 +1143,26 @@ int orc_macros(const orc_params *p, const double *f, double *rho, double *vx,
     long N = (long)p->nx * p->ny * p->nz;
     double *j = (double *)malloc(sizeof(double) * 3 * N);
     double *F = (double *)malloc(sizeof(double) * 3 * N);
-    if (force_fields(p, &L, f, rho, j, F)) { free(j); free(F); return -1; }
+    grid G = { p->nx, p->ny, p->nz, p->lattice == ORC_D2Q9 ? 2 : 3 };
+    int *layer = wall_layers(p, &L, &G);
+    if (force_fields(p, &L, f, layer, rho, j, F)) { free(j); free(F); free(layer); return -1; }
     for (long n = 0; n < N; ++n) {
+        if (layer && layer[n] != 0) {       /* solid: no fluid there */
+            rho[n] = 0.0; vx[n] = 0.0; vy[n] = 0.0;
+            if (vz) vz[n] = 0.0;
+            continue;
+        }
         double r = rho[n];
         vx[n] = j[n] / r + F[n] / (2.0 * r);
         vy[n] = j[N + n] / r + F[N + n] / (2.0 * r);
         if (vz) vz[n] = j[2 * N + n] / r + F[2 * N + n] / (2.0 * r);
     }
     if (F_out) memcpy(F_out, F, sizeof(double) * 3 * N);
-    free(j); free(F);
+    free(j); free(F); free(layer);
     return 0;
 }
 
-/* Spurious current U = max |v| over the domain (Sec 3.3) and total mass,
+/* Spurious current U = max |v| over the fluid nodes (Sec 3.3) and total mass,
  * summed with Neumaier's compensated summation. */
 int orc_observables(const orc_params *p, const double *f, double *umax, double *mass)
 {
