@@ -81,6 +81,11 @@ typedef struct {
                                 moments, each in (0, 2); 0 selects Sec 2.1's 1.64,
                                 1.54 and 1.7.  Density and momentum relax with 1,
                                 the stresses with 1/tau. */
+    int    wall;             /* 0: every node fluid, all axes periodic.  1: solid
+                                nodes given to lbm_init_wall (wetting boundary of
+                                the Appendix; central schemes only) */
+    double mu_wall;          /* with wall = 1, the chemical potential mu_hat (mesh
+                                units, as Eq 16) assigned to the solid layers */
 } lbm_params;
 
 /* Bytes of device workspace lbm_init() needs for these parameters (0 if the
@@ -94,9 +99,24 @@ size_t lbm_workspace_bytes(const lbm_params* p);
  *                   (0, 1/b); a host pointer if rho0_on_device == 0, else a
  *                   device pointer.
  *   hip_stream      stream every later call of this context is ordered on.
- * Errors: LBM_EINVAL (bad parameters or rho0), LBM_ENOSPC (workspace too
- * small), LBM_EHIP (runtime failure).  On success *out holds the context.
- * Synchronises the stream before returning. */
+ * Errors: LBM_EINVAL (bad parameters or rho0, or p->wall != 0), LBM_ENOSPC
+ * (workspace too small), LBM_EHIP (runtime failure).  On success *out holds
+ * the context.  Synchronises the stream before returning. */
+/* Context with solid nodes: the chemical-potential wetting boundary of the
+ * Appendix.  p->wall must be 1 and p->scheme one of CD2, CD4, CD6.
+ *   solid     N bytes, nonzero marks a solid node (x fastest, as rho0); read
+ *             once.  rho0 and solid are both host (on_device == 0) or both
+ *             device pointers.  rho0 is not read on solid nodes.
+ * The r = 1, 2, 3 (CD2, CD4, CD6) layers of solid next to the fluid, counted
+ * through the lattice directions, take the density of Eq A.1 from the layer
+ * before them and the chemical potential p->mu_wall; populations that stream
+ * into a solid node return to their node reversed (halfway bounce-back, the
+ * reading taken where the paper names no rule).  Solid nodes report rho = 0
+ * and v = 0; the observables run over the fluid.  The step runs on the
+ * node-parallel kernels (no launch variants).  Errors as lbm_init. */
+int lbm_init_wall(const lbm_params* p, const double* rho0, const unsigned char* solid, int on_device,
+                  void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
+
 int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device,
              void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
 
@@ -163,13 +183,15 @@ int lbm_eos(const lbm_params* p, const double* rho, long n, double* p0, double* 
  *   mu_hat = k^2 psi'(rho) - kappa_hat lap(rho)        (Eq 15, 16)
  *   F      = -rho grad(mu_hat) + cs^2 grad(rho)         (Eq 12)
  * F receives dim planes of N (x, y[, z] components), mu N values; either may
- * be NULL.  Host or device arrays per out_on_device; synchronises. */
+ * be NULL.  With walls, F is 0 and mu is mu_wall on solid nodes.  Host or
+ * device arrays per out_on_device; synchronises. */
 int lbm_force(lbm_ctx* c, double* F, double* mu, int out_on_device);
 
 /* Gradient (dim planes of N) and Laplacian (N) of a device field d_in with the
  * context's difference scheme (Sec 2.3: Eq 18-20 explicit, Eq 21-24 compact
- * with D(D) as Laplacian, Eq 25 isotropic).  d_lap may be NULL.  Enqueued on
- * the context's stream; d_in must not alias the outputs. */
+ * with D(D) as Laplacian, Eq 25 isotropic), periodic on every axis (solid
+ * nodes are not special here).  d_lap may be NULL.  Enqueued on the context's
+ * stream; d_in must not alias the outputs. */
 int lbm_gradient(lbm_ctx* c, const double* d_in, double* d_grad, double* d_lap);
 
 /* ------------------------------------------------------------------------

@@ -29,7 +29,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t S0, S1, rho0, rho1, mu, force, ringsum, grho, gmu, lap, wtmp, partial, result, total;
+    size_t S0, S1, rho0, rho1, mu, force, ringsum, grho, gmu, lap, wtmp, wl, partial, result, total;
     long long nparts;
 };
 
@@ -62,6 +62,9 @@ const char* validate(const lbm_params* p)
     if (p->collision == LBM_MRT && p->lattice != LBM_D2Q9) return "the MRT collision is defined for D2Q9 (Eq 3)";
     for (double s : { p->s_e, p->s_eps, p->s_q })
         if (!(s == 0.0 || (s > 0.0 && s < 2.0))) return "MRT rates must lie in (0, 2) (0 selects the default)";
+    if (p->wall != 0 && p->wall != 1) return "wall must be 0 or 1";
+    if (p->wall && p->scheme > LBM_CD6) return "walls take the central schemes CD2, CD4, CD6 (Appendix)";
+    if (!std::isfinite(p->mu_wall)) return "mu_wall must be finite";
     return nullptr;
 }
 
@@ -106,6 +109,7 @@ Layout layout_of(const lbm_params* p)
         g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
         L.ringsum = take(sizeof(double) * ringsum_doubles(g, dim == 3));
     }
+    if (p->wall) L.wl = take(N);
     if (compact) {
         L.grho = take(sizeof(double) * dim * N);
         L.gmu = take(sizeof(double) * dim * N);
@@ -123,7 +127,7 @@ Layout layout_of(const lbm_params* p)
 
 struct lbm_ctx {
     lbm_params p;
-    Grid g;
+    Grid g{};
     Eos eos;
     int Q, dim;
     Relax rx;        // collision of Eq 1 (SRT or D2Q9 MRT)
@@ -238,6 +242,10 @@ void launch_fields(lbm_ctx* c)
     double* rho = c->rhob[c->cur];
     if (!c->fused)
         hipLaunchKernelGGL(k_rho<LAT>, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream, S, rho, c->g);
+    if (c->g.wl)        // density of the solid layers, Eq A.1, layer after layer
+        for (int l = 1; l <= radius(SCH); ++l)
+            hipLaunchKernelGGL(k_wall_rho<LAT>, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                               rho, c->g, l);
     if constexpr (is_compact(SCH)) {
         compact_mu(c, rho, DIM);
         for (int d = 0; d < DIM; ++d) compact_deriv(c, c->mu, sink_of(c->gmu + d * c->g.N, C_STORE), d);
@@ -408,8 +416,14 @@ size_t lbm_workspace_bytes(const lbm_params* p)
     return layout_of(p).total;
 }
 
-int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* d_workspace,
-             size_t ws_bytes, void* hip_stream, lbm_ctx** out)
+}  // extern "C"
+
+namespace {
+
+// Shared by lbm_init and lbm_init_wall; solid is nullptr without walls and
+// lies where rho0 lies (host or device).
+int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid, int rho0_on_device,
+             void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out)
 {
     if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -446,12 +460,14 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->gmu = compact ? reinterpret_cast<double*>(c->ws + L.gmu) : nullptr;
     c->lap = compact ? reinterpret_cast<double*>(c->ws + L.lap) : nullptr;
     c->wtmp = compact ? reinterpret_cast<double*>(c->ws + L.wtmp) : nullptr;
+    unsigned char* wl = p->wall ? reinterpret_cast<unsigned char*>(c->ws + L.wl) : nullptr;
     c->partial = reinterpret_cast<double*>(c->ws + L.partial);
     c->result = reinterpret_cast<double*>(c->ws + L.result);
     c->cur = 0;
     c->steps = 0;
     c->rx = relax_of(p);
-    c->fused = c->g.N < (1LL << 29) && std::getenv("LBM_NO_FUSED") == nullptr;
+    // walls run on the node-parallel path
+    c->fused = c->g.N < (1LL << 29) && !p->wall && std::getenv("LBM_NO_FUSED") == nullptr;
     // untuned default for the CD schemes: the ring collide with its own force
     // pass in 3D, the collide that forms the force itself in 2D (fastest of
     // each on 256^3 and 1024^2); the other schemes have only ring variants
@@ -471,20 +487,39 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     c->eos.k2aa = k2 * aa;
     c->eos.b = e.b;
     c->eos.kappa = p->kappa;
+    c->eos.mu_wall = p->mu_wall;
 
     // initial density: validate on the host, stage through the rho buffer
     const long long N = c->g.N;
     const double rho_max = 1.0 / e.b;
     int rc_ = LBM_OK;
-    if (!rho0_on_device) {
+    if (wl) {
+        // the solid mask into the layer map: 0 fluid, kDeepSolid solid, then
+        // the layers 1..r counted from the fluid
+        rc_ = hip_check(c, hipMemcpyAsync(wl, solid, N, rho0_on_device ? hipMemcpyDeviceToDevice
+                                                                        : hipMemcpyHostToDevice, c->stream),
+                        "copy solid mask");
+        if (rc_ == LBM_OK) {
+            hipLaunchKernelGGL(k_wall_mark, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, wl, N);
+            for (int l = 1; l <= radius(p->scheme); ++l) {
+                if (p->lattice == LBM_D2Q9)
+                    hipLaunchKernelGGL(k_wall_layer<0>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, wl, c->g, l);
+                else
+                    hipLaunchKernelGGL(k_wall_layer<1>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, wl, c->g, l);
+            }
+            c->g.wl = wl;
+        }
+    }
+    if (rc_ == LBM_OK && !rho0_on_device) {
         for (long long n = 0; n < N; ++n) {
+            if (solid && solid[n]) continue;       // no density is read on solid nodes
             const double r = rho0[n];
             if (!(r > 0.0 && r < rho_max)) { rc_ = fail(c, LBM_EINVAL, "rho0 must be finite and in (0, 1/b)"); break; }
         }
         if (rc_ == LBM_OK)
             rc_ = hip_check(c, hipMemcpyAsync(c->rhob[1], rho0, sizeof(double) * N, hipMemcpyHostToDevice,
                                               c->stream), "copy rho0");
-    } else {
+    } else if (rc_ == LBM_OK) {
         rc_ = hip_check(c, hipMemcpyAsync(c->rhob[1], rho0, sizeof(double) * N, hipMemcpyDeviceToDevice,
                                           c->stream), "copy rho0");
     }
@@ -497,6 +532,8 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
             launch_init<1>(c, c->rhob[1]);
             hipLaunchKernelGGL(k_rho<1>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, c->S[0], c->rhob[0], c->g);
         }
+        // the step recomputes rho on the node-parallel path; only the fused
+        // path (never with walls) reads this one
         rc_ = hip_check(c, hipGetLastError(), "init launch");
     }
     if (rc_ == LBM_OK) rc_ = hip_check(c, hipStreamSynchronize(c->stream), "init sync");
@@ -510,6 +547,34 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* 
     if (rc_ != LBM_OK) { delete c; return rc_; }
     *out = c;
     return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device, void* d_workspace,
+             size_t ws_bytes, void* hip_stream, lbm_ctx** out)
+{
+    if (p && p->wall) {
+        if (out) *out = nullptr;
+        return fail(nullptr, LBM_EINVAL, "wall = 1 needs lbm_init_wall and a solid mask");
+    }
+    return init_ctx(p, rho0, nullptr, rho0_on_device, d_workspace, ws_bytes, hip_stream, out);
+}
+
+int lbm_init_wall(const lbm_params* p, const double* rho0, const unsigned char* solid, int on_device,
+                  void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out)
+{
+    if (!p || !p->wall) {
+        if (out) *out = nullptr;
+        return fail(nullptr, LBM_EINVAL, "lbm_init_wall needs wall = 1");
+    }
+    if (!solid) {
+        if (out) *out = nullptr;
+        return fail(nullptr, LBM_EINVAL, "solid is NULL");
+    }
+    return init_ctx(p, rho0, solid, on_device, d_workspace, ws_bytes, hip_stream, out);
 }
 
 namespace {
@@ -832,6 +897,7 @@ bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
     for (int i = 0; i < n; ++i) {
         if (const char* w = validate(&ps[i])) { *why = w; return false; }
         if (ps[i].lattice != LBM_D2Q9) { *why = "the batched sweep runs D2Q9 instances"; return false; }
+        if (ps[i].wall) { *why = "the batched sweep runs periodic instances"; return false; }
         B.inst_off[i] = off;
         off = align_up(off + layout_of(&ps[i]).total);
         const long long N = (long long)ps[i].nx * ps[i].ny;
@@ -1073,7 +1139,7 @@ int mlp_field(const float* d_params, const float* norm7, const lbm_params* p, do
 {
     if (!d_params || !norm7 || !feat3 || !d_rho) return fail(nullptr, LBM_EINVAL, "mlp_field: bad arguments");
     if (const char* why = validate(p)) return fail(nullptr, LBM_EINVAL, why);
-    Grid g;
+    Grid g{};
     g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
     g.nxy = (long long)p->nx * p->ny;
     g.N = g.nxy * p->nz;

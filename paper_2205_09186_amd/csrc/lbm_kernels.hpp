@@ -14,7 +14,12 @@ struct Grid {
     long long N;     // nx*ny*nz
     long long nxy;   // nx*ny
     long long ps;    // element stride between population arrays (>= N)
+    // wetting boundary (Appendix): per node 0 = fluid, l = 1..r the solid
+    // layer, kDeepSolid beyond the last layer; nullptr = no solid nodes
+    const unsigned char* wl;
 };
+
+constexpr unsigned char kDeepSolid = 255;
 
 __device__ __forceinline__ int wrapc(int a, int n)
 {
@@ -125,6 +130,9 @@ __device__ __forceinline__ double lap_at(const double* __restrict__ f, const Nbr
 // next step pulls to x + e_i; so S_i(y) = feq_i(rho0(y + e_i), 0) makes the
 // pulled state at time zero feq(rho0, 0).
 // ---------------------------------------------------------------------------
+//   With solid nodes a value that the next step sends into the solid comes
+// back to its own node reversed (halfway bounce-back), so there it carries
+// rho0 of the node itself; solid nodes hold zeros, which nothing reads.
 template <int LAT>
 __global__ void __launch_bounds__(256) k_init(const double* __restrict__ rho0, double* __restrict__ S, Grid g)
 {
@@ -134,21 +142,93 @@ __global__ void __launch_bounds__(256) k_init(const double* __restrict__ rho0, d
     int x, y, z;
     coords(n, g, x, y, z);
     Nbr<1, L::DIM> nb(x, y, z, g);
+    if (g.wl && g.wl[n] != 0) {
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i)
-        S[(long long)i * g.ps + n] = L::w(i) * rho0[nb.at(L::ex(i), L::ey(i), L::ez(i))];
+        for (int i = 0; i < L::Q; ++i) S[(long long)i * g.ps + n] = 0.0;
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const long long m = nb.at(L::ex(i), L::ey(i), L::ez(i));
+        S[(long long)i * g.ps + n] = L::w(i) * rho0[(g.wl && g.wl[m] != 0) ? n : m];
+    }
 }
 
-// Pull the Q populations of node n: f_i(x) = S_i(x - e_i).
+// Pull the Q populations of fluid node n: f_i(x) = S_i(x - e_i), or, when
+// x - e_i is solid, the node's own post-collision value in the opposite
+// direction, S_opp(i)(x) (halfway bounce-back at the wetting boundary).
 template <int LAT>
 __device__ __forceinline__ void pull(const double* __restrict__ S, const Grid& g, long long n,
                                      const Nbr<1, Lat<LAT>::DIM>& nb, double (&f)[Lat<LAT>::Q])
 {
     using L = Lat<LAT>;
-    (void)n;
+    if (g.wl) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const long long m = nb.at(-L::ex(i), -L::ey(i), -L::ez(i));
+            f[i] = g.wl[m] != 0 ? S[(long long)L::opp(i) * g.ps + n] : S[(long long)i * g.ps + m];
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
         f[i] = S[(long long)i * g.ps + nb.at(-L::ex(i), -L::ey(i), -L::ez(i))];
+}
+
+// ---------------------------------------------------------------------------
+// Wetting boundary (Appendix).  The solid layers are counted through the
+// lattice directions: a solid node joins layer l when a neighbour x + e_i is
+// in layer l - 1 (layer 0 = fluid), for l = 1..r, r the radius of the central
+// scheme.  Their density is Eq A.1, the lattice-weighted mean over the
+// neighbours in layer l - 1; their chemical potential is the given mu_wall.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_wall_mark(unsigned char* __restrict__ wl, long long N)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) wl[n] = wl[n] != 0 ? kDeepSolid : 0;
+}
+
+// Nodes still unassigned that touch layer l - 1 join layer l.  Concurrent
+// writes only turn kDeepSolid into l, never into l - 1, so the test is exact.
+template <int LAT>
+__global__ void __launch_bounds__(256) k_wall_layer(unsigned char* __restrict__ wl, Grid g, int l)
+{
+    using L = Lat<LAT>;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N || wl[n] != kDeepSolid) return;
+    int x, y, z;
+    coords(n, g, x, y, z);
+    Nbr<1, L::DIM> nb(x, y, z, g);
+    bool touch = false;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) touch |= wl[nb.at(L::ex(i), L::ey(i), L::ez(i))] == l - 1;
+    if (touch) wl[n] = (unsigned char)l;
+}
+
+// Eq A.1 on layer l; the l = 1 launch also gives the solid beyond the last
+// layer a harmless density of 1 (no fluid stencil reaches it).
+template <int LAT>
+__global__ void __launch_bounds__(256) k_wall_rho(double* __restrict__ rho, Grid g, int l)
+{
+    using L = Lat<LAT>;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const int ln = g.wl[n];
+    if (ln == kDeepSolid) {
+        if (l == 1) rho[n] = 1.0;
+        return;
+    }
+    if (ln != l) return;
+    int x, y, z;
+    coords(n, g, x, y, z);
+    Nbr<1, L::DIM> nb(x, y, z, g);
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const long long m = nb.at(L::ex(i), L::ey(i), L::ez(i));
+        if (g.wl[m] == l - 1) { num += L::w(i) * rho[m]; den += L::w(i); }
+    }
+    rho[n] = num / den;
 }
 
 // Post-streaming populations of the stored state, f_i(x) = S_i(x - e_i).
@@ -162,7 +242,12 @@ __global__ void __launch_bounds__(256) k_pull_all(const double* __restrict__ S, 
     coords(n, g, x, y, z);
     Nbr<1, L::DIM> nb(x, y, z, g);
     double f[L::Q];
-    pull<LAT>(S, g, n, nb, f);
+    if (g.wl && g.wl[n] != 0) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) f[i] = 0.0;
+    } else {
+        pull<LAT>(S, g, n, nb, f);
+    }
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) out[(long long)i * g.N + n] = f[i];
 }
@@ -172,7 +257,7 @@ __global__ void __launch_bounds__(256) k_rho(const double* __restrict__ S, doubl
 {
     using L = Lat<LAT>;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.N) return;
+    if (n >= g.N || (g.wl && g.wl[n] != 0)) return;   // solid: k_wall_rho
     int x, y, z;
     coords(n, g, x, y, z);
     Nbr<1, L::DIM> nb(x, y, z, g);
@@ -191,6 +276,10 @@ __global__ void __launch_bounds__(256) k_mu(const double* __restrict__ rho, doub
     constexpr int R = radius(SCH);
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
+    if (g.wl && g.wl[n] != 0) {      // the wall's chemical potential
+        mu[n] = e.mu_wall;
+        return;
+    }
     int x, y, z;
     coords(n, g, x, y, z);
     Nbr<R, DIM> nb(x, y, z, g);
@@ -239,7 +328,7 @@ __global__ void __launch_bounds__(256) k_collide(const double* __restrict__ S, d
 {
     using L = Lat<LAT>;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.N) return;
+    if (n >= g.N || (g.wl && g.wl[n] != 0)) return;   // no collision in the solid
     int x, y, z;
     coords(n, g, x, y, z);
     Nbr<1, L::DIM> nb(x, y, z, g);
@@ -269,8 +358,8 @@ __global__ void __launch_bounds__(256) k_force_node(const double* __restrict__ r
     if (n >= g.N) return;
     int x, y, z;
     coords(n, g, x, y, z);
-    double Fx, Fy, Fz;
-    force_at<LAT, SCH>(rho, mu, grho, gmu, g, n, x, y, z, rho[n], Fx, Fy, Fz);
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    if (!(g.wl && g.wl[n] != 0)) force_at<LAT, SCH>(rho, mu, grho, gmu, g, n, x, y, z, rho[n], Fx, Fy, Fz);
     F[n] = Fx;
     F[g.N + n] = Fy;
     if constexpr (Lat<LAT>::DIM == 3) F[2 * g.N + n] = Fz;
@@ -329,7 +418,12 @@ __global__ void __launch_bounds__(256) k_macros(const double* __restrict__ S,
     using L = Lat<LAT>;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double vmax = 0.0, msum = 0.0;
-    if (n < g.N) {
+    if (n < g.N && g.wl && g.wl[n] != 0) {    // solid: no fluid there
+        if (orho) orho[n] = 0.0;
+        if (ovx) ovx[n] = 0.0;
+        if (ovy) ovy[n] = 0.0;
+        if (ovz) ovz[n] = 0.0;
+    } else if (n < g.N) {
         int x, y, z;
         coords(n, g, x, y, z);
         Nbr<1, L::DIM> nb(x, y, z, g);

@@ -28,6 +28,10 @@ template <> struct Lat<0> {
     __host__ __device__ static constexpr double w(int i) {
         return i == 0 ? 0x1.c71c71c71c71dp-2 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
     }
+    // direction with e = -e_i
+    __host__ __device__ static constexpr int opp(int i) {
+        return i == 0 ? 0 : (i < 5 ? (i + 1) % 4 + 1 : (i - 3) % 4 + 5);
+    }
 };
 
 template <> struct Lat<1> {
@@ -48,6 +52,8 @@ template <> struct Lat<1> {
     __host__ __device__ static constexpr double w(int i) {
         return i == 0 ? 0x1.5555555555556p-2 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
     }
+    // direction with e = -e_i (the table pairs them as odd, even)
+    __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : (i % 2 ? i + 1 : i - 1); }
 };
 
 // ---------------------------------------------------------------------------
@@ -157,6 +163,7 @@ struct Eos {
     double k2aa;     // k^2 a alpha(T)
     double b;
     double kappa;    // kappa-hat
+    double mu_wall;  // mu_hat of the solid layers (wetting boundary, Appendix)
 };
 
 // Natural logarithm of a positive normal double by the classic argument

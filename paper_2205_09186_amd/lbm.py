@@ -34,7 +34,7 @@ class lbm_params(C.Structure):
                 ("tau", C.c_double), ("Tr", C.c_double), ("k", C.c_double), ("kappa", C.c_double),
                 ("scheme", C.c_int), ("a", C.c_double), ("b", C.c_double), ("R", C.c_double),
                 ("omega", C.c_double), ("collision", C.c_int), ("s_e", C.c_double), ("s_eps", C.c_double),
-                ("s_q", C.c_double)]
+                ("s_q", C.c_double), ("wall", C.c_int), ("mu_wall", C.c_double)]
 
 
 _lib = None
@@ -45,6 +45,8 @@ _D = C.POINTER(C.c_double)
 SYMBOLS = {
     "lbm_workspace_bytes": (C.c_size_t, [_P]),
     "lbm_init": (C.c_int, [_P, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbm_init_wall": (C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p,
+                                C.POINTER(C.c_void_p)]),
     "lbm_step": (C.c_int, [C.c_void_p, C.c_long]),
     "lbm_macros": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "lbm_spurious_max": (C.c_int, [C.c_void_p, _D, _D]),
@@ -132,11 +134,13 @@ class Params:
     s_e: float = 0.0           # MRT rates; 0 selects the values of Sec 2.1
     s_eps: float = 0.0
     s_q: float = 0.0
+    wall: int = 0              # 1: solid nodes passed to Simulation(..., solid=) (Appendix)
+    mu_wall: float = 0.0       # mu_hat of the solid layers
 
     def c(self) -> lbm_params:
         return lbm_params(self.lattice, self.nx, self.ny, self.nz, self.tau, self.Tr, self.k, self.kappa,
                           self.scheme, self.a, self.b, self.R, self.omega, self.collision, self.s_e, self.s_eps,
-                          self.s_q)
+                          self.s_q, self.wall, self.mu_wall)
 
     @property
     def n(self) -> int:
@@ -194,7 +198,9 @@ class _View:
 class Simulation:
     """One lattice on one GPU: a caller-owned torch workspace, a torch stream."""
 
-    def __init__(self, p: Params, rho0, device: str = "cuda:0", stream=None):
+    def __init__(self, p: Params, rho0, device: str = "cuda:0", stream=None, solid=None):
+        """solid: optional uint8 mask shaped like the grid (nonzero = solid
+        node) for the wetting boundary; needs p.wall = 1."""
         import torch
         self.p = p
         self.torch = torch
@@ -216,8 +222,21 @@ class Simulation:
                 raise ValueError("rho0 has the wrong size")
             self._rho0_keep = r
             ptr, on_dev = r.ctypes.data_as(C.c_void_p), 0
-        code = lib().lbm_init(C.byref(self._cp), ptr, on_dev, C.c_void_p(self.ws.data_ptr()), nbytes,
-                              C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if solid is None:
+            code = lib().lbm_init(C.byref(self._cp), ptr, on_dev, C.c_void_p(self.ws.data_ptr()), nbytes,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        else:
+            if on_dev:
+                m = torch.as_tensor(solid, device=self.device).to(torch.uint8).contiguous().reshape(-1)
+                sptr = C.c_void_p(m.data_ptr())
+            else:
+                m = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1)
+                sptr = m.ctypes.data_as(C.c_void_p)
+            if (m.numel() if on_dev else m.size) != p.n:
+                raise ValueError("solid has the wrong size")
+            self._solid_keep = m
+            code = lib().lbm_init_wall(C.byref(self._cp), ptr, sptr, on_dev, C.c_void_p(self.ws.data_ptr()),
+                                       nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         _check(code)
         self.ctx = ctx
 

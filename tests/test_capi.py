@@ -69,6 +69,26 @@ def test_init_rejects_bad_arguments_without_gpu():
     assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert L.lbm_last_error(None) is not None
     L.lbm_free(None)
+    # walls: lbm_init refuses wall = 1, lbm_init_wall needs it and a mask
+    pw = lbm.Params(lattice=lbm.D2Q9, nx=8, ny=8, wall=1).c()
+    rc = L.lbm_init(C.byref(pw), rho.ctypes.data_as(C.c_void_p), 0, C.c_void_p(addr), 4000, None, C.byref(ctx))
+    assert rc == lbm.LBM_EINVAL and "lbm_init_wall" in L.lbm_last_error(None).decode()
+    mask = np.zeros(64, np.uint8)
+    rc = L.lbm_init_wall(C.byref(p), rho.ctypes.data_as(C.c_void_p), mask.ctypes.data_as(C.c_void_p), 0,
+                         C.c_void_p(addr), 4000, None, C.byref(ctx))
+    assert rc == lbm.LBM_EINVAL and "wall = 1" in L.lbm_last_error(None).decode()
+    rc = L.lbm_init_wall(C.byref(pw), rho.ctypes.data_as(C.c_void_p), None, 0, C.c_void_p(addr), 4000, None,
+                         C.byref(ctx))
+    assert rc == lbm.LBM_EINVAL and "solid" in L.lbm_last_error(None).decode()
+
+
+def test_wall_parameters_are_validated():
+    base = dict(lattice=lbm.D2Q9, nx=16, ny=16, wall=1, scheme=lbm.CD6, mu_wall=0.01)
+    ok = lbm.workspace_bytes(lbm.Params(**base))
+    assert ok == lbm.workspace_bytes(lbm.Params(**{**base, "wall": 0})) + 256
+    for bad in (dict(scheme=lbm.E4), dict(scheme=lbm.OCFDS4), dict(scheme=lbm.CFDS6), dict(wall=2),
+                dict(mu_wall=float("nan"))):
+        assert lbm.workspace_bytes(lbm.Params(**{**base, **bad})) == 0, bad
 
 
 def test_critical_point_matches_oracle(orc):
