@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=10, help="oracle steps timed for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--wall", type=int, default=0,
+                    help="solid floor this many nodes thick under the droplet (wetting boundary; 0 = periodic)")
     return ap.parse_args()
 
 
@@ -97,13 +99,13 @@ def traffic_record(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(args, p, rho0):
+def cpu_baseline(args, p, rho0, solid=None):
     import oracle
     oracle.build(force=False)
     nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     oracle.set_threads(nthreads)
     op = oracle.Params(lattice=p.lattice, nx=p.nx, ny=p.ny, nz=p.nz, tau=p.tau, Tr=p.Tr, k=p.k,
-                       kappa=p.kappa, scheme=p.scheme)
+                       kappa=p.kappa, scheme=p.scheme, solid=solid, mu_wall=p.mu_wall)
     sim = oracle.Sim(op, rho0)
     sim.step(1)  # warm-up
     t0 = time.perf_counter()
@@ -129,12 +131,20 @@ def main():
     lat = lbm.D3Q19 if args.lattice == "D3Q19" else lbm.D2Q9
     n = args.n
     shape = (n, n, n) if lat == lbm.D3Q19 else (n, n)
-    p = lbm.Params(lattice=lat, nx=n, ny=n, nz=(n if lat == lbm.D3Q19 else 1), tau=1.0, Tr=args.Tr, k=args.k,
-                   kappa=args.kappa, scheme=lbm.SCHEMES[args.scheme])
     rho_g, rho_l = lbm.coexistence(args.Tr)
+    solid = None
+    mu_wall = 0.0
+    if args.wall > 0:
+        # a floor of solid planes across the slowest axis under the same
+        # droplet, the wall's chemical potential at the coexistence value
+        solid = np.zeros(shape, np.uint8)
+        solid[:args.wall] = 1
+        mu_wall = args.k ** 2 * float(lbm.eos(np.array([rho_g]), args.Tr)[1][0])
+    p = lbm.Params(lattice=lat, nx=n, ny=n, nz=(n if lat == lbm.D3Q19 else 1), tau=1.0, Tr=args.Tr, k=args.k,
+                   kappa=args.kappa, scheme=lbm.SCHEMES[args.scheme], wall=int(args.wall > 0), mu_wall=mu_wall)
     rho0 = inputs.droplet(shape, 0.25 * n, 10.0, rho_g, rho_l)
     stream = torch.cuda.current_stream()
-    sim = lbm.Simulation(p, torch.from_numpy(rho0.reshape(-1)).cuda())
+    sim = lbm.Simulation(p, torch.from_numpy(rho0.reshape(-1)).cuda(), solid=solid)
     # tile-shape tuner: times every launch variant of the step kernel on this
     # grid and keeps the fastest (counts as warm-up)
     tuned = sim.tune(steps=3) if sim.num_variants > 1 else {0: None}
@@ -160,6 +170,8 @@ def main():
     step_bytes = (2 * Q + 2) * 8
     step_gbs = step_bytes * p.n / (ms_step * 1e-3) / 1e9
     workload = f"{args.lattice} {n}^{len(shape)} droplet R={0.25 * n:g} Tr={args.Tr} {args.scheme} k={args.k}"
+    if args.wall > 0:
+        workload += f" wall={args.wall}"
     traffic = traffic_record(kname, workload)
     out = {
         "metric": "MLUPS D3Q19 FP64 (% HBM roofline)" if lat == lbm.D3Q19 else "MLUPS D2Q9 FP64",
@@ -182,7 +194,7 @@ def main():
     del sim
     torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args, p, rho0)
+        out["cpu_baseline"] = cpu_baseline(args, p, rho0, solid)
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,95 @@
+"""Parity at the benchmark's full sizes, in the launch designs the tuner picks
+from (the fused 2D collide, the 3D ring collide, the ring-free tile collide):
+D3Q19 256^3 and D2Q9 1024^2 droplets (radius L/4, Tr = 0.7, tanh width 10)
+against the oracle on every node after a few steps, and mass conservation
+over a longer run (a property at any size)."""
+import numpy as np
+import pytest
+
+from paper_2205_09186_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_09186_amd import lbm
+    lbm.lib()
+    return lbm
+
+
+def _workload(orc, lat, n, scheme):
+    shape = (n, n, n) if lat == 1 else (n, n)
+    g, l = orc.maxwell(0.7)
+    rho0 = inputs.droplet(shape, 0.25 * n, 10.0, g, l)
+    nz = n if lat == 1 else 1
+    kw = dict(lattice=lat, nx=n, ny=n, nz=nz, tau=1.0, Tr=0.7, k=0.1, kappa=0.004, scheme=scheme)
+    return shape, rho0, kw
+
+
+def _design_variants(L, sim, lat, scheme):
+    """One launch variant of each design the context offers: k_fused (CD
+    schemes), the first ring variant, and the tile collide if present."""
+    nv = sim.num_variants
+    cd = scheme in (L.CD2, L.CD4, L.CD6)
+    fused = 7 if cd else 0
+    out = []
+    if cd:
+        out.append(0)
+    out.append(fused)
+    if nv > fused + 3:
+        out.append(nv - 1)
+    return out
+
+
+@pytest.mark.parametrize("lat,n,scheme,steps", [(1, 256, "CD6", 3), (0, 1024, "CD6", 20), (0, 1024, "OCFDS4", 10)])
+def test_full_size_against_oracle(L, orc, lat, n, scheme, steps):
+    import torch
+    shape, rho0, kw = _workload(orc, lat, n, L.SCHEMES[scheme])
+    print(f"case full size lattice={lat} n={n} scheme={scheme} steps={steps}", flush=True)
+    o = orc.Sim(orc.Params(**kw), rho0)
+    o.step(steps)
+    ro, vxo, vyo, vzo = o.macros()
+    Uo, Mo = o.observables()
+    del o
+    d_rho0 = torch.from_numpy(rho0.reshape(-1)).cuda()
+    probe = L.Simulation(L.Params(**kw), d_rho0)
+    variants = _design_variants(L, probe, lat, L.SCHEMES[scheme])
+    probe.close()
+    del probe
+    for v in variants:
+        print(f"  variant {v}", flush=True)
+        sim = L.Simulation(L.Params(**kw), d_rho0)
+        sim.set_variant(v)
+        sim.step(steps)
+        r, vx, vy, vz = sim.macros()
+        d = max(np.abs(r - ro).max(), np.abs(vx - vxo).max(), np.abs(vy - vyo).max())
+        if vz is not None:
+            d = max(d, np.abs(vz - vzo).max())
+        assert d <= TOL, (v, d)
+        U, M, code = sim.spurious_max()
+        assert code == 0
+        assert U == pytest.approx(Uo, abs=TOL)
+        assert M == pytest.approx(Mo, rel=1e-13)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("lat,n", [(1, 256), (0, 1024)])
+def test_full_size_mass_conservation(L, orc, lat, n):
+    import torch
+    shape, rho0, kw = _workload(orc, lat, n, L.CD6)
+    sim = L.Simulation(L.Params(**kw), torch.from_numpy(rho0.reshape(-1)).cuda())
+    sim.tune(steps=1)
+    _, M0, _ = sim.spurious_max()
+    sim.step(200)
+    U, M, code = sim.spurious_max()
+    assert code == 0 and np.isfinite(U)
+    assert abs(M - M0) <= 1e-13 * M0
+    sim.close()
