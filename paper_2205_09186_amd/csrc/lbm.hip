@@ -292,10 +292,11 @@ void launch_step(lbm_ctx* c)
         const int rv = CD ? c->variant - kNumFusedVariants : c->variant;
         if (rv >= kNumRingVariants) {
             mark(c, "k_tile");
-            launch_tile<LAT>(c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->ringsum, c->g, c->rx,
-                             c->stream);
+            const int tv = rv - kNumRingVariants;
+            launch_tile<LAT>(tv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->ringsum, c->g,
+                             c->rx, c->stream);
             mark(c, "k_fix");
-            launch_fix<LAT>(c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
+            launch_fix<LAT>(tv, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
         } else {
             mark(c, "k_ring");
             launch_ring_collide<LAT>(rv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->g, c->rx,
@@ -773,7 +774,7 @@ int lbm_step_timed(lbm_ctx* c, long nsteps, double* ms, int cap, int* nphases)
 int lbm_num_variants(const lbm_ctx* c)
 {
     if (!c || !c->fused) return 1;
-    const int tiles = c->ringsum ? kNumTileVariants : 0;
+    const int tiles = c->ringsum ? num_tile_variants(c->g) : 0;
     return (c->p.scheme <= LBM_CD6 ? kNumFusedVariants : 0) + kNumRingVariants + tiles;
 }
 

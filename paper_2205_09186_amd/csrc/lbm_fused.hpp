@@ -726,7 +726,7 @@ struct TileRing {
 inline bool tile_fits(const Grid& g, int ty) { return g.nx % 64 == 0 && g.ny % ty == 0; }
 
 template <int LAT, int TY, bool FULL>
-__global__ void __launch_bounds__(64 * TY, 2)
+__global__ void __launch_bounds__(64 * TY, TY <= 8 ? 2 : 1)
 k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ F,
        double* __restrict__ rho_next, double* __restrict__ ringsum, Grid g, TileGeom tg, Relax rx)
 {
@@ -875,8 +875,20 @@ __global__ void __launch_bounds__(256) k_fix(double* __restrict__ rho_next, cons
     st32(rho_next, n, acc);
 }
 
-constexpr int kTileTY = 8;
-constexpr int kNumTileVariants = 1;
+// Tile heights of the tile collide.  The taller tile halves the edge share
+// (16% of the nodes instead of 29%) at one 1024-thread workgroup per CU.
+// kTileTY, the lowest, sizes the ring-sum buffer: it has the most ring cells
+// per node, and every grid the taller tile fits is tiled by it too.
+constexpr int kTileTYs[] = { 8, 16 };
+constexpr int kNumTileVariants = 2;
+constexpr int kTileTY = kTileTYs[0];
+
+inline int num_tile_variants(const Grid& g)
+{
+    int n = 0;
+    for (int v = 0; v < kNumTileVariants; ++v) n += tile_fits(g, kTileTYs[v]) ? 1 : 0;
+    return n;
+}
 
 inline size_t ringsum_doubles(const Grid& g, bool three_d)
 {
@@ -884,38 +896,54 @@ inline size_t ringsum_doubles(const Grid& g, bool three_d)
     return ntile * (three_d ? FZ : 1) * TileRing<kTileTY>::NR;
 }
 
-inline TileGeom tile_geom(const Grid& g, bool three_d)
+inline TileGeom tile_geom(const Grid& g, bool three_d, int ty)
 {
     TileGeom t;
     t.ntx = g.nx / 64;
-    t.nty = g.ny / kTileTY;
+    t.nty = g.ny / ty;
     t.nsz = three_d ? (g.nz + FZ - 1) / FZ : 1;
     t.mz = FZ;
     return t;
 }
 
-template <int LAT>
-inline void launch_tile(const double* S, double* Sn, const double* F, double* rho_next, double* ringsum,
-                        const Grid& g, const Relax& rx, hipStream_t st)
+template <int LAT, int TY>
+inline void launch_tile_ty(const double* S, double* Sn, const double* F, double* rho_next, double* ringsum,
+                           const Grid& g, const Relax& rx, hipStream_t st)
 {
-    const TileGeom t = tile_geom(g, LAT == 1);
+    const TileGeom t = tile_geom(g, LAT == 1, TY);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
     if (rx.omo == 0.0 && !rx.mrt)
-        hipLaunchKernelGGL((k_tile<LAT, kTileTY, true>), dim3(nb), dim3(64 * kTileTY), 0, st, S, Sn, F, rho_next,
-                           ringsum, g, t, rx);
+        hipLaunchKernelGGL((k_tile<LAT, TY, true>), dim3(nb), dim3(64 * TY), 0, st, S, Sn, F, rho_next, ringsum,
+                           g, t, rx);
     else
-        hipLaunchKernelGGL((k_tile<LAT, kTileTY, false>), dim3(nb), dim3(64 * kTileTY), 0, st, S, Sn, F, rho_next,
-                           ringsum, g, t, rx);
+        hipLaunchKernelGGL((k_tile<LAT, TY, false>), dim3(nb), dim3(64 * TY), 0, st, S, Sn, F, rho_next, ringsum,
+                           g, t, rx);
+}
+
+template <int TY>
+inline void launch_fix_ty(double* rho_next, const double* ringsum, const Grid& g, bool three_d, hipStream_t st)
+{
+    const TileGeom t = tile_geom(g, three_d, TY);
+    const int mzt = three_d ? FZ : 1;
+    const long long items = (long long)t.ntx * t.nty * t.nsz * mzt * TileRing<TY>::NB;
+    hipLaunchKernelGGL((k_fix<TY>), dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, rho_next, ringsum,
+                       g, t, mzt);
+}
+
+// tv: tile variant, 0 .. num_tile_variants(g) - 1
+template <int LAT>
+inline void launch_tile(int tv, const double* S, double* Sn, const double* F, double* rho_next, double* ringsum,
+                        const Grid& g, const Relax& rx, hipStream_t st)
+{
+    if (tv == 1) launch_tile_ty<LAT, kTileTYs[1]>(S, Sn, F, rho_next, ringsum, g, rx, st);
+    else launch_tile_ty<LAT, kTileTYs[0]>(S, Sn, F, rho_next, ringsum, g, rx, st);
 }
 
 template <int LAT>
-inline void launch_fix(double* rho_next, const double* ringsum, const Grid& g, hipStream_t st)
+inline void launch_fix(int tv, double* rho_next, const double* ringsum, const Grid& g, hipStream_t st)
 {
-    const TileGeom t = tile_geom(g, LAT == 1);
-    const int mzt = LAT == 1 ? FZ : 1;
-    const long long items = (long long)t.ntx * t.nty * t.nsz * mzt * TileRing<kTileTY>::NB;
-    hipLaunchKernelGGL((k_fix<kTileTY>), dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, rho_next, ringsum,
-                       g, t, mzt);
+    if (tv == 1) launch_fix_ty<kTileTYs[1]>(rho_next, ringsum, g, LAT == 1, st);
+    else launch_fix_ty<kTileTYs[0]>(rho_next, ringsum, g, LAT == 1, st);
 }
 
 struct RingVariant { int tx, ty, occ, pf; };

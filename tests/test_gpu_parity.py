@@ -262,14 +262,23 @@ def test_tile_design(L, orc, lat, shape, scheme, tau, coll):
     nz, ny, nx = ((1,) + shape) if lat == 0 else shape
     kw = dict(lattice=lat, nx=nx, ny=ny, nz=nz, tau=tau, Tr=Tr, k=0.16, kappa=0.004, scheme=L.SCHEMES[scheme])
     p = L.Params(**kw, collision=coll)
-    a = L.Simulation(p, rho0)
-    a.set_variant(a.num_variants - 1)
-    assert [n for n, _ in a.step_timed(1)][-2:] == ["k_tile", "k_fix"]
-    a.step(39)
+    # the launch design of each variant, from the phases of one timed step
+    names = {}
+    for v in range(L.Simulation(p, rho0).num_variants):
+        s = L.Simulation(p, rho0)
+        s.set_variant(v)
+        names[v] = [n for n, _ in s.step_timed(1)]
+    tiles = [v for v, n in names.items() if n[-2:] == ["k_tile", "k_fix"]]
+    ring = [v for v, n in names.items() if n[-1] == "k_ring"][0]
+    assert len(tiles) == (2 if ny % 16 == 0 else 1), names   # tile heights 8 and 16
     b = L.Simulation(p, rho0)
-    b.set_variant(a.num_variants - 2)   # a ring variant
+    b.set_variant(ring)
     b.step(40)
-    assert np.abs(a.populations() - b.populations()).max() < 1e-13
     o = orc.Sim(orc.Params(**kw, collision=coll), rho0)
     o.step(40)
-    _compare(a, o)
+    for v in tiles:
+        a = L.Simulation(p, rho0)
+        a.set_variant(v)
+        a.step(40)
+        assert np.abs(a.populations() - b.populations()).max() < 1e-13, v
+        _compare(a, o)
