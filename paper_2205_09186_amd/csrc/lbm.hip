@@ -203,6 +203,16 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
 {
     const LineGeom& lg = c->lines[d];
     const Compact cc = compact_scheme(c->p.scheme);
+    if (d > 0 && lg.s1 == 1 && lg.n <= kSegMaxWaves * kSegLen && c->g.N < (1LL << 29)) {
+        // whole lines per workgroup, one segment of kSegLen points per wave
+        const int W = (lg.n + kSegLen - 1) / kSegLen;
+        const unsigned blocks = (unsigned)(((lg.n1 + 63) / 64) * (long long)lg.n2);
+        const double zS = std::pow(c->z, kSegLen), zLast = std::pow(c->z, lg.n - kSegLen * (W - 1));
+        const double zN = std::pow(c->z, lg.n);
+        hipLaunchKernelGGL(k_compact_seg<kSegLen>, dim3(blocks), dim3(64 * W), 0, c->stream, in, sink, lg, cc, c->z,
+                           c->zscale, zS, zLast, zN);
+        return;
+    }
     if (d == 0 && lg.n <= 4096 && lg.K <= kScanWarm) {
         // whole rows, one wavefront each, the row and its forward results in
         // LDS (2 nx doubles per wavefront, at most 64 KiB per workgroup)

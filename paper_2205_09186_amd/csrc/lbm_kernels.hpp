@@ -571,6 +571,108 @@ __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ 
     }
 }
 
+// Compact derivative along y or z of whole lines in one pass (lines of at
+// most kSegMaxWaves * kSegLen = 256 points; lanes along x with unit stride).  A workgroup
+// takes 64 neighbouring lines; wave w solves points [w S, w S + L_w) of each
+// in registers.  Both recursions run locally from a zero start and are then
+// made exact for the periodic line by the carries of the other segments:
+//   forward   a_i = v_i + z a_{i-1}: segment w ends at E_w locally; the true
+//             end T_m = sum_j z^(distance from end_j to end_m) E_j / (1 - z^n),
+//             and A_i = a_i + z^(i - s_w + 1) T_{w-1};
+//   backward  y_i = A_i + z y_{i+1}: segment w starts at B_w locally; the true
+//             start U_m from the B_j the same way, and y_i = b_i +
+//             z^(s_w + L_w - i) U_{w+1}.
+// The sink receives scale * y.  Each point of g is read once (plus the
+// three-point halos of the right-hand side) and each output written once.
+constexpr int kSegMaxWaves = 8;
+constexpr int kSegLen = 32;   // 162 VGPRs, no spills; 64 points spill
+
+template <int S>
+__global__ void __launch_bounds__(64 * kSegMaxWaves)
+k_compact_seg(const double* __restrict__ f, CompactSink sink, LineGeom lg, Compact c, double z, double scale,
+              double zS, double zLast, double zN)
+{
+    __shared__ double ends[kSegMaxWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6;
+    const int n = lg.n;
+    const int groups = (lg.n1 + 63) / 64;
+    const int o1 = min((int)(blockIdx.x % groups) * 64 + lane, lg.n1 - 1);
+    const bool active = (int)(blockIdx.x % groups) * 64 + lane < lg.n1;
+    const int o2 = (int)(blockIdx.x / groups);
+    // element offsets fit 32 bits (the host launches this for N < 2^29), so
+    // each load address is one register over the uniform base pointer
+    const unsigned base = (unsigned)(o1 * lg.s1 + (long long)o2 * lg.s2);
+    const unsigned sa = (unsigned)lg.sa;
+    const char* fb = reinterpret_cast<const char*>(f);
+    const int s0 = w * S;
+    const int L = min(S, n - s0);
+    const double ha = 0.5 * c.ca, hb = 0.25 * c.cb, hc = c.cc / 6.0;
+    // g at s0 - 3 .. s0 + L + 2; the forward results replace it in place
+    double r[S + 6];
+#pragma unroll
+    for (int k = 0; k < S + 6; ++k) {
+        int idx = s0 - 3 + k;            // in [-3, n + 2]; n >= 4
+        idx += idx < 0 ? n : 0;
+        idx -= idx >= n ? n : 0;
+        r[k] = k < L + 6 ? *reinterpret_cast<const double*>(fb + (size_t)((base + (unsigned)idx * sa) * 8u)) : 0.0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        if (i < L) {
+            const double v = ha * (r[i + 4] - r[i + 2]) + hb * (r[i + 5] - r[i + 1]) + hc * (r[i + 6] - r[i]);
+            acc = v + z * acc;
+            r[i] = acc;
+        }
+    }
+    ends[w][lane] = acc;
+    __syncthreads();
+    {
+        // true end of the previous segment (periodic), from every segment's local end
+        const int m = w == 0 ? W - 1 : w - 1;
+        double t = 0.0, p = 1.0;
+        for (int k = 0, j = m; k < W; ++k) {
+            t += p * ends[j][lane];
+            p *= j == W - 1 ? zLast : zS;
+            j = j == 0 ? W - 1 : j - 1;
+        }
+        t /= 1.0 - zN;
+        double q = z;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (i < L) { r[i] += q * t; q *= z; }
+        }
+    }
+    __syncthreads();   // every wave has read the forward ends
+    acc = 0.0;
+#pragma unroll
+    for (int i = S - 1; i >= 0; --i) {
+        if (i < L) { acc = r[i] + z * acc; r[i] = acc; }
+    }
+    ends[w][lane] = acc;
+    __syncthreads();
+    {
+        const int m = w == W - 1 ? 0 : w + 1;
+        double u = 0.0, p = 1.0;
+        for (int k = 0, j = m; k < W; ++k) {
+            u += p * ends[j][lane];
+            p *= j == W - 1 ? zLast : zS;
+            j = j == W - 1 ? 0 : j + 1;
+        }
+        u /= 1.0 - zN;
+        double q = z;
+#pragma unroll
+        for (int i = S - 1; i >= 0; --i) {
+            if (i < L) {
+                if (active) sink.put((long long)(base + (unsigned)(s0 + i) * sa), scale * (r[i] + q * u));
+                q *= z;
+            }
+        }
+    }
+}
+
 // Compact derivative along x (unit stride) of whole rows: one wavefront per
 // row, lanes along x.  The row is first staged in LDS (all its loads in
 // flight at once).  Both recursions then run as wavefront-wide scans over

@@ -1,0 +1,60 @@
+"""The compact schemes' line solves on multi-segment lines: lines along y and
+z longer than one 32-point segment, with a ragged last segment, solved in one
+pass with exact periodic carries between segments, against the oracle's
+Thomas + Sherman-Morrison solves."""
+import numpy as np
+import pytest
+
+from paper_2205_09186_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_09186_amd import lbm
+    lbm.lib()
+    return lbm
+
+
+@pytest.mark.parametrize("scheme", ["OCFDS4", "CFDS4", "CFDS6", "CFDS8"])
+@pytest.mark.parametrize("shape", [(70, 37, 64), (33, 256, 20), (4, 65, 96)])
+def test_gradient_multisegment_lines(L, orc, scheme, shape):
+    rng = np.random.default_rng(7)
+    grids = np.meshgrid(*[np.arange(s) * 2 * np.pi / s for s in shape], indexing="ij")
+    f = 2.0 + sum(0.2 * rng.standard_normal() * np.cos(sum(int(k) * g for k, g in zip(rng.integers(1, 4, 3), grids))
+                                                        + rng.uniform(0, 6)) for _ in range(4))
+    f += 1e-3 * rng.standard_normal(shape)      # every wavenumber present
+    nz, ny, nx = shape
+    p = L.Params(lattice=1, nx=nx, ny=ny, nz=nz, scheme=L.SCHEMES[scheme], Tr=0.9)
+    sim = L.Simulation(p, np.full(shape, 3.0))
+    g, lap = sim.gradient(f)
+    go = np.zeros(3 * f.size)
+    lo = np.zeros(f.size)
+    lib = orc.lib()
+    lib.orc_grad(3, nx, ny, nz, L.SCHEMES[scheme], np.ascontiguousarray(f.reshape(-1)), go)
+    lib.orc_lap(3, nx, ny, nz, L.SCHEMES[scheme], np.ascontiguousarray(f.reshape(-1)), lo)
+    scale = np.abs(go).max()
+    np.testing.assert_allclose(g.cpu().numpy().reshape(3, -1), go.reshape(3, -1), atol=1e-13 * scale)
+    np.testing.assert_allclose(lap.cpu().numpy().reshape(-1), lo, atol=1e-13 * np.abs(lo).max())
+
+
+@pytest.mark.parametrize("scheme", ["OCFDS4", "CFDS8"])
+def test_step_multisegment_lines(L, orc, scheme):
+    shape = (70, 37, 64)
+    g, l = orc.maxwell(0.9)
+    rho0 = inputs.droplet(shape, 12, 4.0, g, l)
+    nz, ny, nx = shape
+    kw = dict(lattice=1, nx=nx, ny=ny, nz=nz, Tr=0.9, k=0.16, kappa=0.004, scheme=L.SCHEMES[scheme])
+    print(f"case compact step shape={shape} scheme={scheme}", flush=True)
+    sim = L.Simulation(L.Params(**kw), rho0)
+    sim.step(30)
+    o = orc.Sim(orc.Params(**kw), rho0)
+    o.step(30)
+    r, vx, vy, vz = sim.macros()
+    ro, vxo, vyo, vzo = o.macros()
+    d = max(np.abs(r - ro).max(), np.abs(vx - vxo).max(), np.abs(vy - vyo).max(), np.abs(vz - vzo).max())
+    assert d <= 1e-11, d
