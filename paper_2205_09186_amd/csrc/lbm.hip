@@ -150,6 +150,9 @@ struct lbm_ctx {
     hipStream_t cap_stream = nullptr;
     int graph_cur = -1, graph_variant = -1;
     bool use_graph = true;
+    // fewest lines for which the compact line solves take k_compact_seg
+    // (LBM_SEG_MIN_LINES overrides; the tests set 0 to exercise it on small grids)
+    long long seg_min_lines = 1LL << 14;
     // phase timing (lbm_step_timed)
     bool timing = false;
     int nmarks = 0;
@@ -194,7 +197,7 @@ void launch_init(lbm_ctx* c, const double* rho0)
 // added, or turned into the force component of Eq 12).
 CompactSink sink_of(double* out, int mode, const double* rho = nullptr, const double* grad = nullptr)
 {
-    CompactSink k;
+    CompactSink k{};
     k.out = out; k.mode = mode; k.rho = rho; k.grad = grad;
     return k;
 }
@@ -203,14 +206,27 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
 {
     const LineGeom& lg = c->lines[d];
     const Compact cc = compact_scheme(c->p.scheme);
-    if (d > 0 && lg.s1 == 1 && lg.n <= kSegMaxWaves * kSegLen && c->g.N < (1LL << 29)) {
-        // whole lines per workgroup, one segment of kSegLen points per wave
+    // whole lines, one segment of kSegLen points per wave (y, z) or per lane
+    // (x, rows staged in LDS), used where there are enough lines to fill the chip
+    const bool seg = lg.n <= kSegMaxWaves * kSegLen && c->g.N < (1LL << 29) &&
+                     (long long)lg.n1 * lg.n2 >= c->seg_min_lines;
+    if (seg) {
         const int W = (lg.n + kSegLen - 1) / kSegLen;
-        const unsigned blocks = (unsigned)(((lg.n1 + 63) / 64) * (long long)lg.n2);
         const double zS = std::pow(c->z, kSegLen), zLast = std::pow(c->z, lg.n - kSegLen * (W - 1));
         const double zN = std::pow(c->z, lg.n);
-        hipLaunchKernelGGL(k_compact_seg<kSegLen>, dim3(blocks), dim3(64 * W), 0, c->stream, in, sink, lg, cc, c->z,
-                           c->zscale, zS, zLast, zN);
+        if (d == 0) {
+            const XSegGeom q = xseg_geom(lg.n);
+            const long long rows = (long long)lg.n1 * lg.n2;
+            // up to four wavefronts, within 64 KiB of LDS per workgroup
+            const int waves = std::max(1, std::min(4, (int)(65536 / (sizeof(double) * q.RW * q.P))));
+            const unsigned blocks = (unsigned)((rows + (long long)waves * q.RW - 1) / ((long long)waves * q.RW));
+            hipLaunchKernelGGL(k_compact_xseg, dim3(blocks), dim3(64 * waves), sizeof(double) * waves * q.RW * q.P,
+                               c->stream, in, sink, rows, q, cc, c->z, c->zscale, zS, zLast, zN);
+        } else {
+            const unsigned blocks = (unsigned)(((lg.n1 + 63) / 64) * (long long)lg.n2);
+            hipLaunchKernelGGL(k_compact_seg<kSegLen>, dim3(blocks), dim3(64 * W), 0, c->stream, in, sink, lg, cc,
+                               c->z, c->zscale, zS, zLast, zN);
+        }
         return;
     }
     if (d == 0 && lg.n <= 4096 && lg.K <= kScanWarm) {
@@ -234,10 +250,12 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
 void compact_mu(lbm_ctx* c, const double* rho, int dim)
 {
     for (int d = 0; d < dim; ++d) compact_deriv(c, rho, sink_of(c->grho + d * c->g.N, C_STORE), d);
-    for (int d = 0; d < dim; ++d)
+    // the last axis's term completes the Laplacian and forms mu_hat (Eq 16)
+    for (int d = 0; d < dim - 1; ++d)
         compact_deriv(c, c->grho + d * c->g.N, sink_of(c->lap, d > 0 ? C_ADD : C_STORE), d);
-    hipLaunchKernelGGL(k_mu_lap, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
-                       rho, c->lap, c->mu, c->g.N, c->eos);
+    CompactSink mu_sink = sink_of(c->mu, C_MU, rho, c->lap);
+    mu_sink.eos = c->eos;
+    compact_deriv(c, c->grho + (dim - 1) * c->g.N, mu_sink, dim - 1);
 }
 
 // rho of the current state, then the chemical potential and (compact schemes)
@@ -484,6 +502,7 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
     // each on 256^3 and 1024^2); the other schemes have only ring variants
     c->variant = (p->lattice == LBM_D3Q19 && p->scheme <= LBM_CD6) ? kNumFusedVariants : 0;
     c->use_graph = std::getenv("LBM_NO_GRAPH") == nullptr;
+    if (const char* e = std::getenv("LBM_SEG_MIN_LINES")) c->seg_min_lines = std::atoll(e);
     set_lines(c);
 
     // equation of state in mesh units (Eq 16): k^2 psi'

@@ -286,15 +286,6 @@ __global__ void __launch_bounds__(256) k_mu(const double* __restrict__ rho, doub
     mu[n] = mu_bulk(rho[n], e) - e.kappa * lap_at<DIM, SCH, R>(rho, nb);
 }
 
-// mu_hat from a precomputed Laplacian field (compact schemes).
-__global__ void __launch_bounds__(256) k_mu_lap(const double* __restrict__ rho, const double* __restrict__ lap,
-                                                double* __restrict__ mu, long long N, Eos e)
-{
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    mu[n] = mu_bulk(rho[n], e) - e.kappa * lap[n];
-}
-
 // Force F = -rho grad(mu_hat) + cs^2 grad(rho) at one node (Eq 12).
 template <int LAT, int SCH>
 __device__ __forceinline__ void force_at(const double* __restrict__ rho_f, const double* __restrict__ mu_f,
@@ -530,19 +521,59 @@ __global__ void __launch_bounds__(256) k_compact_fwd(const double* __restrict__ 
 }
 
 // What the last pass of a compact derivative D g writes at node o.
-enum CompactOut { C_STORE = 0, C_ADD = 1, C_FORCE = 2 };
+enum CompactOut { C_STORE = 0, C_ADD = 1, C_FORCE = 2, C_MU = 3 };
 struct CompactSink {
     double* out;
     int mode;             // C_STORE: out = D g; C_ADD: out += D g;
     const double* rho;    // C_FORCE: out = -rho D mu_hat + cs^2 G[rho] (Eq 12), g = mu_hat,
-    const double* grad;   //          grad = the same component of G[rho]
+    const double* grad;   //          grad = the same component of G[rho];
+    Eos eos;              // C_MU: the last term of the Laplacian, out = mu_hat =
+                          //       k^2 psi'(rho) - kappa (grad + D g) (Eq 16), grad = the
+                          //       sum of the other axes' terms
     __device__ __forceinline__ void put(long long o, double d) const
     {
         if (mode == C_FORCE) out[o] = -rho[o] * d + (1.0 / 3.0) * grad[o];
         else if (mode == C_ADD) out[o] += d;
+        else if (mode == C_MU) out[o] = mu_bulk(rho[o], eos) - eos.kappa * (grad[o] + d);
         else out[o] = d;
     }
 };
+
+// The sink of a run of M points (element offsets o, values v, ok = written):
+// every load of the run is issued before its first store, so the run costs
+// one memory round trip rather than one per point.
+template <int M>
+__device__ __forceinline__ void sink_run_impl(int mode, const Eos& eos, double* __restrict__ out,
+                                              const double* __restrict__ rho, const double* __restrict__ gr,
+                                              const unsigned (&o)[M], const double (&v)[M], const bool (&ok)[M])
+{
+    if (mode == C_STORE) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (ok[m]) out[o[m]] = v[m];
+        return;
+    }
+    double a[M], b[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        a[m] = ok[m] ? (mode == C_ADD ? out[o[m]] : rho[o[m]]) : 1.0;
+        b[m] = ok[m] && mode != C_ADD ? gr[o[m]] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        if (!ok[m]) continue;
+        if (mode == C_ADD) out[o[m]] = a[m] + v[m];
+        else if (mode == C_FORCE) out[o[m]] = -a[m] * v[m] + (1.0 / 3.0) * b[m];
+        else out[o[m]] = mu_bulk(a[m], eos) - eos.kappa * (b[m] + v[m]);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void sink_run(const CompactSink& k, const unsigned (&o)[M], const double (&v)[M],
+                                         const bool (&ok)[M])
+{
+    sink_run_impl<M>(k.mode, k.eos, k.out, k.rho, k.grad, o, v, ok);
+}
 
 // Backward recursion y_i = w_i + z y_{i+1}; the sink receives scale * y.
 __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ w, CompactSink sink,
@@ -665,11 +696,166 @@ k_compact_seg(const double* __restrict__ f, CompactSink sink, LineGeom lg, Compa
         double q = z;
 #pragma unroll
         for (int i = S - 1; i >= 0; --i) {
+            if (i < L) { r[i] = scale * (r[i] + q * u); q *= z; }
+        }
+    }
+    // the sink, in runs of 16 points
+#pragma unroll
+    for (int h = 0; h < S; h += 16) {
+        unsigned o[16];
+        double v[16];
+        bool ok[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            o[m] = base + (unsigned)(s0 + h + m) * sa;
+            v[m] = r[h + m];
+            ok[m] = active && h + m < L;
+        }
+        sink_run<16>(sink, o, v, ok);
+    }
+}
+
+// Compact derivative along x of rows of at most 8 * kSegLen = 256 points, the
+// row-wise counterpart of k_compact_seg.  Each wavefront stages RW rows in
+// LDS with coalesced loads; lane l then solves segment s = l % NS (NS = the
+// segments per row) of row l / NS from LDS, the periodic carries between the
+// segments of a row coming from the other lanes of that row by cross-lane
+// reads.  The results go back to LDS and leave through coalesced stores
+// (element offsets in 32 bits: launched for N < 2^29).
+// Row layout in LDS: point x at x + x / 32 (a one-element skew per segment)
+// in rows of P doubles, P = 8 (mod 16), so the lanes of a half-wave read
+// different banks.
+struct XSegGeom {
+    int n, NS, RW, P;     // row length, segments per row, rows per wave, LDS row stride
+    unsigned magic;       // e / n == (e * magic) >> 20 for 0 <= e < 2048
+};
+
+inline XSegGeom xseg_geom(int n)
+{
+    XSegGeom q;
+    q.n = n;
+    q.NS = (n + kSegLen - 1) / kSegLen;
+    q.RW = 64 / q.NS;
+    q.P = (n + q.NS + 7) / 16 * 16 + 8;
+    q.magic = ((1u << 20) + (unsigned)n - 1) / (unsigned)n;
+    return q;
+}
+
+__global__ void __launch_bounds__(256) k_compact_xseg(const double* __restrict__ f, CompactSink sink,
+                                                      long long nrows, XSegGeom q, Compact c, double z,
+                                                      double scale, double zS, double zLast, double zN)
+{
+    extern __shared__ double xrows[];
+    constexpr int S = kSegLen;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int n = q.n, NS = q.NS, RW = q.RW, P = q.P;
+    double* rows = xrows + (size_t)wv * RW * P;
+    const long long row0 = ((long long)blockIdx.x * (blockDim.x >> 6) + wv) * RW;
+    // the wave's RW * n <= 2048 points: element e = lane + 64 m of the rows
+    // laid end to end; all loads first, then the LDS writes
+    {
+        double t[32];
+#pragma unroll
+        for (int m = 0; m < 32; ++m) {
+            const unsigned e = (unsigned)(lane + 64 * m);
+            const unsigned j = (e * q.magic) >> 20, x = e - j * (unsigned)n;
+            t[m] = (int)j < RW && row0 + j < nrows ? f[(unsigned)((row0 + j) * n) + x] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < 32; ++m) {
+            const unsigned e = (unsigned)(lane + 64 * m);
+            const unsigned j = (e * q.magic) >> 20, x = e - j * (unsigned)n;
+            if ((int)j < RW) rows[j * P + x + x / S] = t[m];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // this lane's segment; lanes past RW * NS work on a copy of row 0 and
+    // store nothing
+    const int jr = lane / NS < RW ? lane / NS : 0;
+    const int sg = lane % NS;
+    const bool mine = lane / NS < RW && row0 + jr < nrows;
+    const int s0 = sg * S;
+    const int L = min(S, n - s0);
+    const double* rr = rows + jr * P;
+    const double ha = 0.5 * c.ca, hb = 0.25 * c.cb, hc = c.cc / 6.0;
+    double r[S + 6];
+#pragma unroll
+    for (int k = 0; k < S + 6; ++k) {
+        int x = s0 - 3 + k;             // in [-3, n + 2]; n >= 4
+        x += x < 0 ? n : 0;
+        x -= x >= n ? n : 0;
+        r[k] = k < L + 6 ? rr[x + x / S] : 0.0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        if (i < L) {
+            const double v = ha * (r[i + 4] - r[i + 2]) + hb * (r[i + 5] - r[i + 1]) + hc * (r[i + 6] - r[i]);
+            acc = v + z * acc;
+            r[i] = acc;
+        }
+    }
+    const int rl = (lane / NS) * NS;    // first lane of this row's segments
+    {
+        double t = 0.0, p = 1.0;
+        const int m = sg == 0 ? NS - 1 : sg - 1;
+        for (int k = 0, j = m; k < NS; ++k) {
+            t += p * __shfl(acc, rl + j, 64);
+            p *= j == NS - 1 ? zLast : zS;
+            j = j == 0 ? NS - 1 : j - 1;
+        }
+        t /= 1.0 - zN;
+        double qz = z;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (i < L) { r[i] += qz * t; qz *= z; }
+        }
+    }
+    acc = 0.0;
+#pragma unroll
+    for (int i = S - 1; i >= 0; --i) {
+        if (i < L) { acc = r[i] + z * acc; r[i] = acc; }
+    }
+    {
+        double u = 0.0, p = 1.0;
+        const int m = sg == NS - 1 ? 0 : sg + 1;
+        for (int k = 0, j = m; k < NS; ++k) {
+            u += p * __shfl(acc, rl + j, 64);
+            p *= j == NS - 1 ? zLast : zS;
+            j = j == NS - 1 ? 0 : j + 1;
+        }
+        u /= 1.0 - zN;
+        double qz = z;
+        // every lane has read its inputs (program order within the wavefront)
+        double* wr = rows + jr * P;
+#pragma unroll
+        for (int i = S - 1; i >= 0; --i) {
             if (i < L) {
-                if (active) sink.put((long long)(base + (unsigned)(s0 + i) * sa), scale * (r[i] + q * u));
-                q *= z;
+                if (mine) wr[s0 + i + (s0 + i) / S] = scale * (r[i] + qz * u);
+                qz *= z;
             }
         }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int h = 0; h < 32; h += 16) {
+        unsigned o[16];
+        double v[16];
+        bool ok[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const unsigned e = (unsigned)(lane + 64 * (h + m));
+            const unsigned j = (e * q.magic) >> 20, x = e - j * (unsigned)n;
+            ok[m] = (int)j < RW && row0 + j < nrows;
+            o[m] = ok[m] ? (unsigned)((row0 + j) * n) + x : 0u;
+            v[m] = ok[m] ? rows[j * P + x + x / S] : 0.0;
+        }
+        sink_run<16>(sink, o, v, ok);
     }
 }
 

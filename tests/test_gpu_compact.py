@@ -1,7 +1,8 @@
-"""The compact schemes' line solves on multi-segment lines: lines along y and
-z longer than one 32-point segment, with a ragged last segment, solved in one
-pass with exact periodic carries between segments, against the oracle's
-Thomas + Sherman-Morrison solves."""
+"""The compact schemes' line solves on multi-segment lines: lines along x, y
+and z longer than one 32-point segment, with a ragged last segment, solved in
+one pass with exact periodic carries between segments (and, for comparison,
+by the chunked recursions), against the oracle's Thomas + Sherman-Morrison
+solves."""
 import numpy as np
 import pytest
 
@@ -20,9 +21,17 @@ def L():
     return lbm
 
 
+@pytest.fixture(params=["segments", "chunks"])
+def solver(request, monkeypatch):
+    """Both line solvers: the one-pass segment kernel (forced on these small
+    grids) and the chunked forward/backward recursions."""
+    monkeypatch.setenv("LBM_SEG_MIN_LINES", "0" if request.param == "segments" else str(1 << 62))
+    return request.param
+
+
 @pytest.mark.parametrize("scheme", ["OCFDS4", "CFDS4", "CFDS6", "CFDS8"])
 @pytest.mark.parametrize("shape", [(70, 37, 64), (33, 256, 20), (4, 65, 96)])
-def test_gradient_multisegment_lines(L, orc, scheme, shape):
+def test_gradient_multisegment_lines(L, orc, scheme, shape, solver):
     rng = np.random.default_rng(7)
     grids = np.meshgrid(*[np.arange(s) * 2 * np.pi / s for s in shape], indexing="ij")
     f = 2.0 + sum(0.2 * rng.standard_normal() * np.cos(sum(int(k) * g for k, g in zip(rng.integers(1, 4, 3), grids))
@@ -43,7 +52,7 @@ def test_gradient_multisegment_lines(L, orc, scheme, shape):
 
 
 @pytest.mark.parametrize("scheme", ["OCFDS4", "CFDS8"])
-def test_step_multisegment_lines(L, orc, scheme):
+def test_step_multisegment_lines(L, orc, scheme, solver):
     shape = (70, 37, 64)
     g, l = orc.maxwell(0.9)
     rho0 = inputs.droplet(shape, 12, 4.0, g, l)
