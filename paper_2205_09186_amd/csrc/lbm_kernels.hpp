@@ -542,10 +542,10 @@ struct CompactSink {
 // The sink of a run of M points (element offsets o, values v, ok = written):
 // every load of the run is issued before its first store, so the run costs
 // one memory round trip rather than one per point.
-template <int M>
+template <int M, typename T>
 __device__ __forceinline__ void sink_run_impl(int mode, const Eos& eos, double* __restrict__ out,
                                               const double* __restrict__ rho, const double* __restrict__ gr,
-                                              const unsigned (&o)[M], const double (&v)[M], const bool (&ok)[M])
+                                              const T (&o)[M], const double (&v)[M], const bool (&ok)[M])
 {
     if (mode == C_STORE) {
 #pragma unroll
@@ -568,11 +568,11 @@ __device__ __forceinline__ void sink_run_impl(int mode, const Eos& eos, double* 
     }
 }
 
-template <int M>
-__device__ __forceinline__ void sink_run(const CompactSink& k, const unsigned (&o)[M], const double (&v)[M],
+template <int M, typename T>
+__device__ __forceinline__ void sink_run(const CompactSink& k, const T (&o)[M], const double (&v)[M],
                                          const bool (&ok)[M])
 {
-    sink_run_impl<M>(k.mode, k.eos, k.out, k.rho, k.grad, o, v, ok);
+    sink_run_impl<M, T>(k.mode, k.eos, k.out, k.rho, k.grad, o, v, ok);
 }
 
 // Backward recursion y_i = w_i + z y_{i+1}; the sink receives scale * y.
@@ -594,11 +594,26 @@ __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ 
     const int i0 = end - 1 + lg.K;
     int im = pmod(i0, n);
     double acc = 0.0;
+    // warm-up (nothing is written), then the chunk in runs of 16 points whose
+    // sink loads are all issued before the run's stores
 #pragma unroll 8
-    for (int i = i0; i >= start; --i) {
+    for (int i = i0; i >= end; --i) {
         acc = w[base + im * sa] + z * acc;
-        if (i < end) sink.put(base + im * sa, scale * acc);
         im = im == 0 ? n - 1 : im - 1;
+    }
+    for (int i = end - 1; i >= start; i -= 16) {
+        long long o[16];
+        double v[16];
+        bool ok[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            ok[m] = i - m >= start;
+            o[m] = base + im * sa;
+            acc = ok[m] ? w[o[m]] + z * acc : acc;
+            v[m] = scale * acc;
+            im = im == 0 ? n - 1 : im - 1;
+        }
+        sink_run<16, long long>(sink, o, v, ok);
     }
 }
 
@@ -616,7 +631,7 @@ __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ 
 // The sink receives scale * y.  Each point of g is read once (plus the
 // three-point halos of the right-hand side) and each output written once.
 constexpr int kSegMaxWaves = 8;
-constexpr int kSegLen = 32;   // 162 VGPRs, no spills; 64 points spill
+constexpr int kSegLen = 32;   // 64-point segments spill registers
 
 template <int S>
 __global__ void __launch_bounds__(64 * kSegMaxWaves)
@@ -917,7 +932,8 @@ __global__ void __launch_bounds__(256) k_compact_x(const double* __restrict__ f,
         carry = __shfl(a, 63, 64);
         if (valid && p >= 0) wb[x] = a;
     }
-    // backward sweep over positions nx-1+W .. 0 (lane order = descending)
+    // backward sweep over positions nx-1+W .. 0 (lane order = descending);
+    // the results replace the row of f in LDS
     carry = 0.0;
     for (int q0 = nx - 1 + kScanWarm; q0 >= 0; q0 -= 64) {
         const int q = q0 - lane;
@@ -925,7 +941,24 @@ __global__ void __launch_bounds__(256) k_compact_x(const double* __restrict__ f,
         const int x = valid ? pmod(q, nx) : 0;
         const double a = scan(valid ? wb[x] : 0.0, carry);
         carry = __shfl(a, 63, 64);
-        if (valid && q < nx) sink.put(row * nx + x, scale * a);
+        if (valid && q < nx) fr[x] = scale * a;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the sink in runs of 16 points per lane, loads before stores
+    for (int x0 = 0; x0 < nx; x0 += 64 * 16) {
+        long long o[16];
+        double v[16];
+        bool ok[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int x = x0 + lane + 64 * m;
+            ok[m] = x < nx;
+            o[m] = row * nx + (ok[m] ? x : 0);
+            v[m] = ok[m] ? fr[x] : 0.0;
+        }
+        sink_run<16, long long>(sink, o, v, ok);
     }
 }
 
