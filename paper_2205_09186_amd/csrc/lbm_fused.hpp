@@ -358,6 +358,15 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
     // z queue of the own column, index k <-> plane z - R + k for the plane z
     // computed next.  Planes before the first staged one are loaded here.
     double q[NF][QZ];
+    // 3D isotropic schemes: sums pending for the output planes p - R .. p + R
+    // (index j <-> plane p - R + j), fed by each staged plane once
+    constexpr bool PUSH = ISO && DIM == 3;
+    constexpr int NA = NF == 1 ? 1 : 6;
+    double A[PUSH ? 2 * R + 1 : 1][NA];
+#pragma unroll
+    for (int j = 0; j < (PUSH ? 2 * R + 1 : 1); ++j)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) A[j][a] = 0.0;
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -411,6 +420,66 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
                 for (int k = 0; k < QZ - 1; ++k) q[f][k] = q[f][k + 1];
                 q[f][QZ - 1] = s[f][c0];
             }
+        }
+        if constexpr (PUSH) {
+            // each in-plane neighbour of plane p is read once and added, with
+            // the weight of Eq 25 for every z offset it has, to the outputs
+            // it reaches; the output plane p - R is then complete
+            if (in) {
+                const int sl = (p - pb) % NS;
+#pragma unroll
+                for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+                    for (int dx = -R; dx <= R; ++dx) {
+                        double v[NF];
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) v[f] = sp[sl][f][c0 + dy * WR + dx];
+#pragma unroll
+                        for (int dz = -R; dz <= R; ++dz) {
+                            const int sh = dx * dx + dy * dy + dz * dz;
+                            const double w = iso_w(DIM, SCH, sh);
+                            if (sh == 0 || w == 0.0) continue;
+                            // the neighbour at +dz of output plane p - dz
+                            double* a = A[R - dz];
+                            if constexpr (NF == 1) {
+                                a[0] += w * v[0];
+                            } else {
+                                if (dx) { a[0] += (dx * w) * v[0]; a[3] += (dx * w) * v[1]; }
+                                if (dy) { a[1] += (dy * w) * v[0]; a[4] += (dy * w) * v[1]; }
+                                if (dz) { a[2] += (dz * w) * v[0]; a[5] += (dz * w) * v[1]; }
+                            }
+                        }
+                    }
+                const int z = p - R;
+                if (z >= z0) {
+                    const unsigned n = (unsigned)(z * nxy + col);
+                    const double c = sp[(z - pb) % NS][0][c0];   // rho at the output node
+                    if constexpr (NF == 1) {
+                        double wsum = 0.0;   // sum of the weights over the stencil
+#pragma unroll
+                        for (int dz = -R; dz <= R; ++dz)
+#pragma unroll
+                            for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+                                for (int dx = -R; dx <= R; ++dx) {
+                                    const int sh = dx * dx + dy * dy + dz * dz;
+                                    if (sh) wsum += iso_w(DIM, SCH, sh);
+                                }
+                        st32(out, n, mu_bulk(c, e) - e.kappa * (2.0 * (A[0][0] - wsum * c)));
+                    } else {
+                        st32(out, n, -c * A[0][3] + cs2 * A[0][0]);
+                        st32(out + N, n, -c * A[0][4] + cs2 * A[0][1]);
+                        st32(out + 2 * (size_t)N, n, -c * A[0][5] + cs2 * A[0][2]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j)
+#pragma unroll
+                for (int a = 0; a < NA; ++a) A[j][a] = A[j + 1][a];
+#pragma unroll
+            for (int a = 0; a < NA; ++a) A[2 * R][a] = 0.0;
+            continue;
         }
         if (p < z0 + LAG || !in) continue;
         const int z = p - LAG;
