@@ -113,8 +113,8 @@ Layout layout_of(const lbm_params* p)
     if (compact) {
         L.grho = take(sizeof(double) * dim * N);
         L.gmu = take(sizeof(double) * dim * N);
-        L.lap = take(sizeof(double) * N);
-        L.wtmp = take(sizeof(double) * N);
+        L.lap = take(sizeof(double) * dim * N);    // one term per axis
+        L.wtmp = take(sizeof(double) * dim * N);   // one scratch per axis
     }
     L.nparts = (N + 255) / 256;
     L.partial = take(sizeof(double) * 2 * L.nparts);
@@ -150,9 +150,17 @@ struct lbm_ctx {
     hipStream_t cap_stream = nullptr;
     int graph_cur = -1, graph_variant = -1;
     bool use_graph = true;
-    // fewest lines for which the compact line solves take k_compact_seg
-    // (LBM_SEG_MIN_LINES overrides; the tests set 0 to exercise it on small grids)
-    long long seg_min_lines = 1LL << 14;
+    // fewest lines for which the compact line solves take the segmented
+    // kernels: always along y and z; along x (rows staged in LDS, RW rows per
+    // wavefront) only where rows are many, the whole-row scan being faster on
+    // small grids.  LBM_SEG_MIN_LINES sets both (the tests force either path).
+    long long seg_min_lines_yz = 0, seg_min_lines_x = 1LL << 14;
+    // compact schemes run the per-axis derivative passes concurrently, axis
+    // d > 0 on branch stream br[d - 1], forked from and joined to the
+    // context's stream by events (LBM_NO_CONC turns it off)
+    bool conc = false;
+    hipStream_t br[2] = {};
+    hipEvent_t bfork = nullptr, bjoin[2] = {};
     // phase timing (lbm_step_timed)
     bool timing = false;
     int nmarks = 0;
@@ -209,7 +217,7 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
     // whole lines, one segment of kSegLen points per wave (y, z) or per lane
     // (x, rows staged in LDS), used where there are enough lines to fill the chip
     const bool seg = lg.n <= kSegMaxWaves * kSegLen && c->g.N < (1LL << 29) &&
-                     (long long)lg.n1 * lg.n2 >= c->seg_min_lines;
+                     (long long)lg.n1 * lg.n2 >= (d == 0 ? c->seg_min_lines_x : c->seg_min_lines_yz);
     if (seg) {
         const int W = (lg.n + kSegLen - 1) / kSegLen;
         const double zS = std::pow(c->z, kSegLen), zLast = std::pow(c->z, lg.n - kSegLen * (W - 1));
@@ -245,10 +253,64 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
                        c->wtmp, sink, lg, c->z, c->zscale);
 }
 
+// Releases the branch streams and events; the axes then run in sequence.
+void drop_branches(lbm_ctx* c)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (c->br[k]) (void)hipStreamDestroy(c->br[k]);
+        if (c->bjoin[k]) (void)hipEventDestroy(c->bjoin[k]);
+        c->br[k] = nullptr;
+        c->bjoin[k] = nullptr;
+    }
+    if (c->bfork) (void)hipEventDestroy(c->bfork);
+    c->bfork = nullptr;
+    c->conc = false;
+}
+
+// fn(d) for every axis d.  With c->conc the axes run concurrently: axis 0
+// on the context's stream, axis d > 0 on branch stream br[d - 1] with its own
+// scratch; the branches fork from and join the context's stream by events
+// (inside a graph capture this makes parallel branches of the graph).
+template <class Fn>
+void per_axis(lbm_ctx* c, int dim, Fn fn)
+{
+    if (!c->conc || dim == 1) {
+        for (int d = 0; d < dim; ++d) fn(d);
+        return;
+    }
+    hipStream_t main = c->stream;
+    double* w0 = c->wtmp;
+    (void)hipEventRecord(c->bfork, main);
+    for (int k = 0; k < dim - 1; ++k) (void)hipStreamWaitEvent(c->br[k], c->bfork, 0);
+    for (int d = 0; d < dim; ++d) {
+        c->stream = d == 0 ? main : c->br[d - 1];
+        c->wtmp = w0 + d * c->g.N;
+        fn(d);
+    }
+    c->stream = main;
+    c->wtmp = w0;
+    for (int k = 0; k < dim - 1; ++k) {
+        (void)hipEventRecord(c->bjoin[k], c->br[k]);
+        (void)hipStreamWaitEvent(main, c->bjoin[k], 0);
+    }
+}
+
 // Compact schemes: G[rho] into grho, the Laplacian D(D rho) summed over the
 // axes, then mu_hat.
 void compact_mu(lbm_ctx* c, const double* rho, int dim)
 {
+    if (c->conc) {
+        // each axis: G_d[rho], then its term D_d(G_d[rho]) of the Laplacian;
+        // mu_hat then sums the terms in axis order
+        const long long N = c->g.N;
+        per_axis(c, dim, [&](int d) {
+            compact_deriv(c, rho, sink_of(c->grho + d * N, C_STORE), d);
+            compact_deriv(c, c->grho + d * N, sink_of(c->lap + d * N, C_STORE), d);
+        });
+        hipLaunchKernelGGL(k_mu_sum, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, rho, c->lap, dim, N,
+                           c->eos, c->mu);
+        return;
+    }
     for (int d = 0; d < dim; ++d) compact_deriv(c, rho, sink_of(c->grho + d * c->g.N, C_STORE), d);
     // the last axis's term completes the Laplacian and forms mu_hat (Eq 16)
     for (int d = 0; d < dim - 1; ++d)
@@ -276,7 +338,7 @@ void launch_fields(lbm_ctx* c)
                                rho, c->g, l);
     if constexpr (is_compact(SCH)) {
         compact_mu(c, rho, DIM);
-        for (int d = 0; d < DIM; ++d) compact_deriv(c, c->mu, sink_of(c->gmu + d * c->g.N, C_STORE), d);
+        per_axis(c, DIM, [&](int d) { compact_deriv(c, c->mu, sink_of(c->gmu + d * c->g.N, C_STORE), d); });
     } else {
         hipLaunchKernelGGL((k_mu<DIM, SCH>), dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
                            rho, c->mu, c->g, c->eos);
@@ -314,8 +376,9 @@ void launch_step(lbm_ctx* c)
         } else {
             mark(c, "compact derivatives+mu+force");
             compact_mu(c, rho, DIM);
-            for (int d = 0; d < DIM; ++d)
+            per_axis(c, DIM, [&](int d) {
                 compact_deriv(c, c->mu, sink_of(c->force + d * c->g.N, C_FORCE, rho, c->grho + d * c->g.N), d);
+            });
         }
         const int rv = CD ? c->variant - kNumFusedVariants : c->variant;
         if (rv >= kNumRingVariants) {
@@ -502,8 +565,20 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
     // each on 256^3 and 1024^2); the other schemes have only ring variants
     c->variant = (p->lattice == LBM_D3Q19 && p->scheme <= LBM_CD6) ? kNumFusedVariants : 0;
     c->use_graph = std::getenv("LBM_NO_GRAPH") == nullptr;
-    if (const char* e = std::getenv("LBM_SEG_MIN_LINES")) c->seg_min_lines = std::atoll(e);
+    if (const char* e = std::getenv("LBM_SEG_MIN_LINES")) c->seg_min_lines_yz = c->seg_min_lines_x = std::atoll(e);
+    // measured faster at every size from 100^2 to 256^3 (2D 1024^2 by 15%)
+    c->conc = compact && std::getenv("LBM_NO_CONC") == nullptr;
     set_lines(c);
+    if (c->conc) {
+        int r = LBM_OK;
+        for (int k = 0; k < c->dim - 1 && r == LBM_OK; ++k) {
+            r = hip_check(c, hipStreamCreateWithFlags(&c->br[k], hipStreamNonBlocking), "branch stream");
+            if (r == LBM_OK)
+                r = hip_check(c, hipEventCreateWithFlags(&c->bjoin[k], hipEventDisableTiming), "branch event");
+        }
+        if (r == LBM_OK) r = hip_check(c, hipEventCreateWithFlags(&c->bfork, hipEventDisableTiming), "fork event");
+        if (r != LBM_OK) { lbm_free(c); return r; }
+    }
 
     // equation of state in mesh units (Eq 16): k^2 psi'
     const PR e = eos_constants(p);
@@ -826,6 +901,7 @@ void lbm_free(lbm_ctx* c)
     if (!c) return;
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    drop_branches(c);
     for (int k = 0; k < 16; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     delete c;
@@ -990,6 +1066,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         rc = lbm_init(&ps[i], rho0s[i], 0, b->ws + B.inst_off[i], sz, hip_stream, &c);
         if (rc != LBM_OK) { b->err = "instance " + std::to_string(i) + ": " + g_thread_error; break; }
         c->fused = false;
+        drop_branches(c);     // instances are stepped by the batched kernel
         b->ctx[i] = c;
         BInst& I = b->inst[i];
         I.g = c->g;

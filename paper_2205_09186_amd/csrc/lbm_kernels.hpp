@@ -286,6 +286,18 @@ __global__ void __launch_bounds__(256) k_mu(const double* __restrict__ rho, doub
     mu[n] = mu_bulk(rho[n], e) - e.kappa * lap_at<DIM, SCH, R>(rho, nb);
 }
 
+// mu_hat = k^2 psi'(rho) - kappa (lap_x + lap_y [+ lap_z]) (Eq 16) from the
+// per-axis terms of a compact Laplacian, summed in axis order.
+__global__ void __launch_bounds__(256) k_mu_sum(const double* __restrict__ rho, const double* __restrict__ lap,
+                                                int dim, long long N, Eos e, double* __restrict__ mu)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double l = lap[n] + lap[N + n];
+    if (dim == 3) l += lap[2 * N + n];
+    mu[n] = mu_bulk(rho[n], e) - e.kappa * l;
+}
+
 // Force F = -rho grad(mu_hat) + cs^2 grad(rho) at one node (Eq 12).
 template <int LAT, int SCH>
 __device__ __forceinline__ void force_at(const double* __restrict__ rho_f, const double* __restrict__ mu_f,

@@ -67,3 +67,25 @@ def test_step_multisegment_lines(L, orc, scheme, solver):
     ro, vxo, vyo, vzo = o.macros()
     d = max(np.abs(r - ro).max(), np.abs(vx - vxo).max(), np.abs(vy - vyo).max(), np.abs(vz - vzo).max())
     assert d <= 1e-11, d
+
+
+@pytest.mark.parametrize("lat,shape,scheme", [(0, (96, 130), "OCFDS4"), (1, (20, 24, 28), "CFDS6")])
+def test_concurrent_axes_equal_sequential(L, orc, lat, shape, scheme, monkeypatch):
+    """The per-axis derivative passes on branch streams (forked and joined by
+    events, also inside the captured step graph) give bitwise the state of the
+    same passes run one after another."""
+    g, l = orc.maxwell(0.8)
+    rho0 = inputs.droplet(shape, min(shape) / 4, 4.0, g, l)
+    nz, ny, nx = ((1,) + shape) if lat == 0 else shape
+    p = L.Params(lattice=lat, nx=nx, ny=ny, nz=nz, Tr=0.8, scheme=L.SCHEMES[scheme])
+    a = L.Simulation(p, rho0)
+    monkeypatch.setenv("LBM_NO_CONC", "1")
+    b = L.Simulation(p, rho0)
+    monkeypatch.delenv("LBM_NO_CONC")
+    for n in (1, 8, 3):        # plain launches and graph replays
+        a.step(n)
+        b.step(n)
+    assert np.array_equal(a.populations(), b.populations())
+    Fa, mua = a.force()
+    Fb, mub = b.force()
+    assert np.array_equal(Fa, Fb) and np.array_equal(mua, mub)
