@@ -83,9 +83,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_record(kernel: str, workload: str):
+def traffic_record(kernel: str, workload: str, variant=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources and this workload; else None."""
+    was taken on the current kernel sources, this workload and this launch
+    variant; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -93,7 +94,7 @@ def traffic_record(kernel: str, workload: str):
         rec = json.load(open(path))
     except Exception:
         return None
-    ent = rec.get(f"{workload} | {kernel}")
+    ent = rec.get(f"{workload} | {kernel}" + (f" | variant {variant}" if variant is not None else ""))
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
@@ -172,7 +173,8 @@ def main():
     workload = f"{args.lattice} {n}^{len(shape)} droplet R={0.25 * n:g} Tr={args.Tr} {args.scheme} k={args.k}"
     if args.wall > 0:
         workload += f" wall={args.wall}"
-    traffic = traffic_record(kname, workload)
+    chosen = min((v for v in tuned if tuned[v] is not None), key=lambda v: tuned[v], default=None)
+    traffic = traffic_record(kname, workload, chosen)
     out = {
         "metric": "MLUPS D3Q19 FP64 (% HBM roofline)" if lat == lbm.D3Q19 else "MLUPS D2Q9 FP64",
         "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -188,6 +190,7 @@ def main():
                      "step_achieved": round(step_gbs, 1), "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
                      "phases_ms": {k: round(v, 4) for k, v in phases}},
         "tuner_ms_per_variant": {str(k): (round(v, 4) if v is not None else None) for k, v in tuned.items()},
+        "variant": chosen,
         "spurious_current": U, "mass": M, "status": code,
     }
     sim.close()

@@ -135,7 +135,8 @@ def summarize(args):
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(tpath)) if os.path.exists(tpath) else {}
     if ent:
-        data[f"{args.workload} | {dom}"] = {"kernel": dom, "bytes_per_launch": round(ent["bytes"]), "source_hash": source_hash(),
+        key = f"{args.workload} | {dom}" + (f" | variant {args.variant}" if args.variant is not None else "")
+        data[key] = {"kernel": dom, "variant": args.variant, "bytes_per_launch": round(ent["bytes"]), "source_hash": source_hash(),
                                "avg_us_rocprof": round(ent["avg_us"], 2), "fetch_scale": round(f_scale, 5),
                                "write_scale": round(w_scale, 5)}
         json.dump(data, open(tpath, "w"), indent=1)
@@ -162,6 +163,7 @@ def main():
     s.add_argument("--trace", required=True)
     s.add_argument("--workload", required=True)
     s.add_argument("--kernel", default="k_ring")
+    s.add_argument("--variant", type=int, default=None, help="launch variant the counter runs used")
     s.add_argument("--commands", default="")
     s.add_argument("--out", required=True)
     a = ap.parse_args()
