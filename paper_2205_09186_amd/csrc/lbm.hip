@@ -959,7 +959,9 @@ struct lbm_batch {
     BState* d_st = nullptr;
     int* d_blk_inst = nullptr;
     double* d_partial = nullptr;
+    BLine* d_lines = nullptr;
     int nblk_total = 0;
+    int nlines = 0;
     int has_compact = 0;
     int grid = 0;          // workgroups of the cooperative launch (0: all resident)
     int max_grid = 0;
@@ -968,31 +970,10 @@ struct lbm_batch {
 
 namespace {
 
-constexpr int kConvMax = 128;   // longest convolution kernel (M + 1 entries)
-
-// Antisymmetric convolution kernel c_0..c_M of the periodic compact derivative:
-// the cyclic inverse of 1 + al (S + S^-1) has entries (1+z^2)/(1-z^2) z^|k|,
-// applied to the right-hand side sum_m r_m (g_{i+m} - g_{i-m}) of Eq 21.
-int compact_conv(int scheme, double* c)
-{
-    const Compact cc = compact_scheme(scheme);
-    const double z = (-1.0 + std::sqrt(1.0 - 4.0 * cc.al * cc.al)) / (2.0 * cc.al);
-    const int K = (int)std::ceil(std::log(1e-18) / std::log(std::fabs(z)));
-    const int M = K + 3;
-    const double r[4] = { 0.0, 0.5 * cc.ca, 0.25 * cc.cb, cc.cc / 6.0 };
-    auto h = [&](int k) { return (1.0 + z * z) / (1.0 - z * z) * std::pow(z, std::abs(k)); };
-    for (int j = 0; j <= M && j < kConvMax; ++j) {
-        double s = 0.0;
-        for (int m = 1; m <= 3; ++m) s += r[m] * (h(j - m) - h(j + m));
-        c[j] = s;
-    }
-    return std::min(M, kConvMax - 1);
-}
-
 struct BatchLayout {
     std::vector<size_t> inst_off;
     size_t tables, total;
-    int nblk;
+    int nblk, nlines;
 };
 
 bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
@@ -1000,6 +981,7 @@ bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
     size_t off = 0;
     B.inst_off.resize(n);
     B.nblk = 0;
+    B.nlines = 0;
     for (int i = 0; i < n; ++i) {
         if (const char* w = validate(&ps[i])) { *why = w; return false; }
         if (ps[i].lattice != LBM_D2Q9) { *why = "the batched sweep runs D2Q9 instances"; return false; }
@@ -1008,13 +990,20 @@ bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
         off = align_up(off + layout_of(&ps[i]).total);
         const long long N = (long long)ps[i].nx * ps[i].ny;
         B.nblk += (int)((N + BNODES - 1) / BNODES);
+        if (is_compact(ps[i].scheme)) {
+            if (std::max(ps[i].nx, ps[i].ny) > 64 * kLineSeg) {
+                *why = "compact-scheme instances of the batched sweep take lines of at most 1024 nodes";
+                return false;
+            }
+            B.nlines += ps[i].nx + ps[i].ny;
+        }
     }
     B.tables = off;
     off = align_up(off + sizeof(BInst) * n);
     off = align_up(off + sizeof(BState) * n);
     off = align_up(off + sizeof(int) * B.nblk);
     off = align_up(off + sizeof(double) * B.nblk);
-    off = align_up(off + sizeof(double) * 4 * kConvMax);
+    off = align_up(off + sizeof(BLine) * std::max(1, B.nlines));
     B.total = off;
     return true;
 }
@@ -1078,6 +1067,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         I.grho = c->grho; I.gmu = c->gmu; I.lap = c->lap; I.wtmp = c->wtmp;
         I.cc = compact_scheme(ps[i].scheme);
         I.z = c->z; I.zscale = c->zscale;
+        I.K = c->lines[0].K;
         I.blk0 = (int)blk_inst.size();
         I.nblk = (int)((c->g.N + BNODES - 1) / BNODES);
         for (int k = 0; k < I.nblk; ++k) blk_inst.push_back(i);
@@ -1090,24 +1080,21 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     b->d_st = reinterpret_cast<BState*>(b->ws + off); off = align_up(off + sizeof(BState) * n);
     b->d_blk_inst = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nblk);
     b->d_partial = reinterpret_cast<double*>(b->ws + off); off = align_up(off + sizeof(double) * B.nblk);
-    double* d_conv = reinterpret_cast<double*>(b->ws + off);
-    std::vector<double> conv(4 * kConvMax, 0.0);
-    int convM[4];
-    for (int k = 0; k < 4; ++k) convM[k] = compact_conv(LBM_OCFDS4 + k, conv.data() + k * kConvMax);
+    b->d_lines = reinterpret_cast<BLine*>(b->ws + off);
+    // the grid lines of the compact-scheme instances, rows then columns
+    std::vector<BLine> lines;
     for (int i = 0; i < n; ++i) {
-        if (is_compact(ps[i].scheme)) {
-            const int k = ps[i].scheme - LBM_OCFDS4;
-            b->inst[i].cconv = d_conv + k * kConvMax;
-            b->inst[i].M = convM[k];
-        } else {
-            b->inst[i].cconv = nullptr;
-            b->inst[i].M = 0;
-        }
+        if (!is_compact(ps[i].scheme)) continue;
+        for (int y = 0; y < ps[i].ny; ++y) lines.push_back(BLine{ i, 0, y });
+        for (int x = 0; x < ps[i].nx; ++x) lines.push_back(BLine{ i, 1, x });
     }
+    b->nlines = (int)lines.size();
     b->nblk_total = (int)blk_inst.size();
     std::vector<BState> st(n);
     for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.U = 0.0; x.U_prev = 0.0; }
-    hipError_t e = hipMemcpyAsync(d_conv, conv.data(), sizeof(double) * conv.size(), hipMemcpyHostToDevice, b->stream);
+    hipError_t e = hipSuccess;
+    if (!lines.empty())
+        e = hipMemcpyAsync(b->d_lines, lines.data(), sizeof(BLine) * lines.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_st, st.data(), sizeof(BState) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_blk_inst, blk_inst.data(), sizeof(int) * blk_inst.size(),
@@ -1153,6 +1140,8 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
         a.blk_inst = b->d_blk_inst;
         a.partial = b->d_partial;
         a.has_compact = b->has_compact;
+        a.lines = b->d_lines;
+        a.nlines = b->nlines;
         a.nsteps = (int)todo;
         a.check_every = (int)check_every;
         a.tol = tol;

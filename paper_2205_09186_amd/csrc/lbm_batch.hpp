@@ -31,8 +31,7 @@ struct BInst {
     double *S[2], *rho, *mu, *grho, *gmu, *lap, *wtmp;
     Compact cc;
     double z, zscale;
-    const double* cconv;    // compact derivative as a periodic convolution: c_1..c_M
-    int M;
+    int K;                  // warm-up of the compact recursions, |z|^K < 1e-18
     int blk0, nblk;         // node-block items [blk0, blk0 + nblk)
     int part0;              // first partial slot of its node blocks
 };
@@ -92,6 +91,79 @@ __device__ void b_moments(const BInst& I, const double* S, long long n, int x, i
     }
 }
 
+// One grid line of a compact-scheme instance: along x (axis 0, line = row y)
+// or along y (axis 1, line = column x).
+struct BLine {
+    int inst, axis, idx;
+};
+
+// Compact derivative (Eq 21) of f along one periodic line of instance I into
+// out, by one wavefront: lane l takes the segment [l L, l L + L_l) of the line
+// (L = ceil(n / 64) <= kLineSeg).  Both recursions of the factorised cyclic
+// solve (a_i = v_i + z a_{i-1}, then y_i = a_i + z y_{i+1}, out = (1 + z^2) y)
+// run in registers from a zero start; the true value entering each segment
+// follows from a scan over the lanes of the pairs (z^L_l, local end), closed
+// around the periodic line by 1 / (1 - z^n).  Exact, no warm-up.
+constexpr int kLineSeg = 16;   // lines of up to 64 * 16 = 1024 nodes
+
+__device__ void b_line(const BInst& I, const double* __restrict__ f, double* __restrict__ out, long long base,
+                       long long sa, int n, int lane)
+{
+    const double ha = 0.5 * I.cc.ca, hb = 0.25 * I.cc.cb, hc = I.cc.cc / 6.0, z = I.z;
+    const int L = (n + 63) / 64;
+    const int s0 = min(lane * L, n);
+    const int Ll = min(L, n - s0);
+    double r[kLineSeg + 6];
+#pragma unroll
+    for (int k = 0; k < kLineSeg + 6; ++k) {
+        int idx = s0 - 3 + k;               // in [-3, n + 2]; n >= 4
+        idx += idx < 0 ? n : 0;
+        idx -= idx >= n ? n : 0;
+        r[k] = k < Ll + 6 ? f[base + idx * sa] : 0.0;
+    }
+    double acc = 0.0, pz = 1.0;
+#pragma unroll
+    for (int i = 0; i < kLineSeg; ++i) {
+        if (i < Ll) {
+            acc = ha * (r[i + 4] - r[i + 2]) + hb * (r[i + 5] - r[i + 1]) + hc * (r[i + 6] - r[i]) + z * acc;
+            r[i] = acc;
+            pz *= z;
+        }
+    }
+    // forward: T_l = E_l + z^L_l T_{l-1}, cyclic over the lanes
+    double P = pz, V = acc;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const double Pp = __shfl_up(P, s, 64), Vp = __shfl_up(V, s, 64);
+        if (lane >= s) { V += P * Vp; P *= Pp; }
+    }
+    const double Tlast = __shfl(V, 63, 64) / (1.0 - __shfl(P, 63, 64));
+    double cin = __shfl_up(V + P * Tlast, 1, 64);
+    if (lane == 0) cin = Tlast;
+    double q = z;
+#pragma unroll
+    for (int i = 0; i < kLineSeg; ++i)
+        if (i < Ll) { r[i] += q * cin; q *= z; }
+    acc = 0.0;
+#pragma unroll
+    for (int i = kLineSeg - 1; i >= 0; --i)
+        if (i < Ll) { acc = r[i] + z * acc; r[i] = acc; }
+    // backward: U_l = B_l + z^L_l U_{l+1}, cyclic over the lanes
+    P = pz; V = acc;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const double Pn = __shfl_down(P, s, 64), Vn = __shfl_down(V, s, 64);
+        if (lane + s < 64) { V += P * Vn; P *= Pn; }
+    }
+    const double Ufirst = __shfl(V, 0, 64) / (1.0 - __shfl(P, 0, 64));
+    double cr = __shfl_down(V + P * Ufirst, 1, 64);
+    if (lane == 63) cr = Ufirst;
+    q = z;
+#pragma unroll
+    for (int i = kLineSeg - 1; i >= 0; --i)
+        if (i < Ll) { out[base + (s0 + i) * sa] = I.zscale * (r[i] + q * cr); q *= z; }
+}
+
 struct BatchArgs {
     BInst* inst;
     BState* st;
@@ -100,6 +172,8 @@ struct BatchArgs {
     int* blk_inst;            // node-block item -> instance
     double* partial;          // one max |v| per node-block item
     int has_compact;
+    const BLine* lines;       // the grid lines of every compact-scheme instance
+    int nlines;
     int nsteps;
     int check_every;
     double tol;
@@ -131,13 +205,43 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
             }
         }
         bar(gg);
-        // ---- phase: chemical potential (explicit schemes) ----------------------
+        // ---- compact schemes: the line solves of D rho, then of D(D rho) ------
+        // the x and y lines of a stage run together
+        auto line_stage = [&](int stage) {
+            // one wavefront per line (t is uniform over the wavefront)
+            const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+            for (int t = blockIdx.x * (BNODES / 64) + wv; t < a.nlines; t += gridDim.x * (BNODES / 64)) {
+                const BLine ln = a.lines[t];
+                if (a.st[ln.inst].status != B_RUNNING) continue;
+                const BInst& I = a.inst[ln.inst];
+                const long long N = I.g.N;
+                const long long base = ln.axis == 0 ? (long long)ln.idx * I.g.nx : ln.idx;
+                const long long sa = ln.axis == 0 ? 1 : I.g.nx;
+                const int n = ln.axis == 0 ? I.g.nx : I.g.ny;
+                const double* f = stage == 0 ? I.rho : stage == 1 ? I.grho + ln.axis * N : I.mu;
+                double* out = stage == 0 ? I.grho + ln.axis * N : stage == 1 ? I.lap + ln.axis * N
+                                                                               : I.gmu + ln.axis * N;
+                b_line(I, f, out, base, sa, n, lane);
+            }
+        };
+        if (a.has_compact) {
+            line_stage(0);
+            bar(gg);
+            line_stage(1);
+            bar(gg);
+        }
+        // ---- phase: chemical potential -----------------------------------------
         for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
             const int ii = a.blk_inst[it];
             const BInst& I = a.inst[ii];
-            if (a.st[ii].status != B_RUNNING || is_compact(I.scheme)) continue;
+            if (a.st[ii].status != B_RUNNING) continue;
             const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
             if (n < I.g.N) {
+                if (is_compact(I.scheme)) {
+                    // the Laplacian terms of the two axes, in axis order (Eq 16)
+                    I.mu[n] = mu_bulk(I.rho[n], I.eos) - I.eos.kappa * (I.lap[n] + I.lap[I.g.N + n]);
+                    continue;
+                }
                 int x, y, z;
                 coords(n, I.g, x, y, z);
                 switch (I.scheme) {
@@ -151,57 +255,12 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
                 }
             }
         }
-        // ---- compact schemes: D rho; then D(D rho) and mu; then D mu ------------
-        // The periodic compact derivative equals a convolution with the
-        // antisymmetric kernel c_j (|j| <= M) of the exact cyclic inverse:
-        // (D g)_i = sum_{j=1..M} c_j (g_{i+j} - g_{i-j}), indices mod n.
-        if (a.has_compact) {
-            for (int stage = 0; stage < 3; ++stage) {
-                for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
-                    const int ii = a.blk_inst[it];
-                    const BInst& I = a.inst[ii];
-                    if (a.st[ii].status != B_RUNNING || !is_compact(I.scheme)) continue;
-                    const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
-                    if (n >= I.g.N) continue;
-                    int x, y, z;
-                    coords(n, I.g, x, y, z);
-                    const int nx = I.g.nx, ny = I.g.ny;
-                    const long long row = (long long)y * nx;
-                    auto dx = [&](const double* f) {
-                        double acc = 0.0;
-                        int xp = x, xm = x;
-                        for (int j = 1; j <= I.M; ++j) {
-                            xp = xp + 1 == nx ? 0 : xp + 1;
-                            xm = xm == 0 ? nx - 1 : xm - 1;
-                            acc += I.cconv[j] * (f[row + xp] - f[row + xm]);
-                        }
-                        return acc;
-                    };
-                    auto dy = [&](const double* f) {
-                        double acc = 0.0;
-                        int yp = y, ym = y;
-                        for (int j = 1; j <= I.M; ++j) {
-                            yp = yp + 1 == ny ? 0 : yp + 1;
-                            ym = ym == 0 ? ny - 1 : ym - 1;
-                            acc += I.cconv[j] * (f[(long long)yp * nx + x] - f[(long long)ym * nx + x]);
-                        }
-                        return acc;
-                    };
-                    if (stage == 0) {
-                        I.grho[n] = dx(I.rho);
-                        I.grho[I.g.N + n] = dy(I.rho);
-                    } else if (stage == 1) {
-                        const double lp = dx(I.grho) + dy(I.grho + I.g.N);
-                        I.mu[n] = mu_bulk(I.rho[n], I.eos) - I.eos.kappa * lp;
-                    } else {
-                        I.gmu[n] = dx(I.mu);
-                        I.gmu[I.g.N + n] = dy(I.mu);
-                    }
-                }
-                bar(gg);
-            }
-        }
         bar(gg);
+        // ---- compact schemes: the line solves of D mu_hat ------------------------
+        if (a.has_compact) {
+            line_stage(2);
+            bar(gg);
+        }
         // ---- convergence check on the current state (every check_every steps) --
         const bool check = a.check_every > 0;
         if (check) {
