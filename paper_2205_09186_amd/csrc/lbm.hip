@@ -29,7 +29,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t S0, S1, rho0, rho1, mu, force, ringsum, grho, gmu, lap, wtmp, wl, partial, result, total;
+    size_t S0, S1, rho0, rho1, mu, force, ringsum, grho, gmu, lap, wtmp, wl, wb, partial, result, total;
     long long nparts;
 };
 
@@ -109,7 +109,10 @@ Layout layout_of(const lbm_params* p)
         g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
         L.ringsum = take(sizeof(double) * ringsum_doubles(g, dim == 3));
     }
-    if (p->wall) L.wl = take(N);
+    if (p->wall) {
+        L.wl = take(N);
+        L.wb = take(sizeof(unsigned) * N);
+    }
     if (compact) {
         L.grho = take(sizeof(double) * dim * N);
         L.gmu = take(sizeof(double) * dim * N);
@@ -135,6 +138,7 @@ struct lbm_ctx {
     char* ws;
     Layout L;
     double *S[2], *rhob[2], *mu, *force, *ringsum, *grho, *gmu, *lap, *wtmp, *partial, *result;
+    unsigned* wbits = nullptr;   // wetting boundary: per-node bounce-back mask of the fast path
     int cur;        // index of the buffers holding the current state (S and rho)
     long steps;
     std::string err;
@@ -356,6 +360,28 @@ void launch_step(lbm_ctx* c)
         constexpr int DIM = Lat<LAT>::DIM;
         const double* rho = c->rhob[c->cur];
         constexpr bool CD = SCH == CD2 || SCH == CD4 || SCH == CD6;
+        if constexpr (CD) {
+            if (c->g.wl) {
+                // wetting boundary: the solid layers' density (Eq A.1), the
+                // stencil passes, then the tile collide with bounce-back
+                mark(c, "k_wall_rho");
+                for (int l = 1; l <= radius(SCH); ++l)
+                    hipLaunchKernelGGL(k_wall_rho<LAT>, dim3(blocks_for(c->g.N, 256)), dim3(256), 0, c->stream,
+                                       c->rhob[c->cur], c->g, l);
+                mark(c, "k_mu_march");
+                launch_mu_march<DIM, SCH>(rho, c->mu, c->g, c->eos, c->stream);
+                mark(c, "k_force_march");
+                launch_force_march<DIM, SCH>(rho, c->mu, c->force, c->g, c->eos, c->stream);
+                mark(c, "k_tile");
+                launch_tile<LAT>(c->variant, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur],
+                                 c->ringsum, c->g, c->rx, c->stream, c->wbits);
+                mark(c, "k_fix");
+                launch_fix<LAT>(c->variant, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
+                mark(c, nullptr);
+                c->cur = 1 - c->cur;
+                return;
+            }
+        }
         if constexpr (!is_compact(SCH)) {
             mark(c, "k_mu_march");
             launch_mu_march<DIM, SCH>(rho, c->mu, c->g, c->eos, c->stream);
@@ -558,12 +584,14 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
     c->cur = 0;
     c->steps = 0;
     c->rx = relax_of(p);
-    // walls run on the node-parallel path
-    c->fused = c->g.N < (1LL << 29) && !p->wall && std::getenv("LBM_NO_FUSED") == nullptr;
+    // walls run on the tile collide (central schemes, grids tiled by 64 x 8),
+    // else on the node-parallel path
+    c->fused = c->g.N < (1LL << 29) && std::getenv("LBM_NO_FUSED") == nullptr &&
+               (!p->wall || (p->scheme <= LBM_CD6 && c->ringsum));
     // untuned default for the CD schemes: the ring collide with its own force
     // pass in 3D, the collide that forms the force itself in 2D (fastest of
     // each on 256^3 and 1024^2); the other schemes have only ring variants
-    c->variant = (p->lattice == LBM_D3Q19 && p->scheme <= LBM_CD6) ? kNumFusedVariants : 0;
+    c->variant = (p->lattice == LBM_D3Q19 && p->scheme <= LBM_CD6 && !p->wall) ? kNumFusedVariants : 0;
     c->use_graph = std::getenv("LBM_NO_GRAPH") == nullptr;
     if (const char* e = std::getenv("LBM_SEG_MIN_LINES")) c->seg_min_lines_yz = c->seg_min_lines_x = std::atoll(e);
     // measured faster at every size from 100^2 to 256^3 (2D 1024^2 by 15%)
@@ -613,6 +641,11 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
                     hipLaunchKernelGGL(k_wall_layer<1>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, wl, c->g, l);
             }
             c->g.wl = wl;
+            c->wbits = reinterpret_cast<unsigned*>(c->ws + L.wb);
+            if (p->lattice == LBM_D2Q9)
+                hipLaunchKernelGGL(k_wall_bits<0>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, wl, c->wbits, c->g);
+            else
+                hipLaunchKernelGGL(k_wall_bits<1>, dim3(blocks_for(N, 256)), dim3(256), 0, c->stream, wl, c->wbits, c->g);
         }
     }
     if (rc_ == LBM_OK && !rho0_on_device) {
@@ -878,6 +911,7 @@ int lbm_step_timed(lbm_ctx* c, long nsteps, double* ms, int cap, int* nphases)
 int lbm_num_variants(const lbm_ctx* c)
 {
     if (!c || !c->fused) return 1;
+    if (c->g.wl) return num_tile_variants(c->g);   // walls: the tile collide only
     const int tiles = c->ringsum ? num_tile_variants(c->g) : 0;
     return (c->p.scheme <= LBM_CD6 ? kNumFusedVariants : 0) + kNumRingVariants + tiles;
 }

@@ -538,7 +538,8 @@ __global__ void __launch_bounds__(MX * MY) k_march(const double* __restrict__ rh
                 acc += w * (c[0][c0 + m * WR] + c[0][c0 - m * WR]);
                 if constexpr (DIM == 3) acc += w * (q[0][R + m] + q[0][R - m]);
             }
-            st32(out, n, mu_bulk(f0, e) - e.kappa * acc);
+            // solid nodes (wetting boundary) carry the wall's chemical potential
+            st32(out, n, g.wl && g.wl[n] ? e.mu_wall : mu_bulk(f0, e) - e.kappa * acc);
         } else {
             double grx = 0.0, gry = 0.0, grz = 0.0, gmx = 0.0, gmy = 0.0, gmz = 0.0;
 #pragma unroll
@@ -794,10 +795,16 @@ struct TileRing {
 
 inline bool tile_fits(const Grid& g, int ty) { return g.nx % 64 == 0 && g.ny % ty == 0; }
 
-template <int LAT, int TY, bool FULL>
+// WALL: the wetting boundary, from the per-node mask wb (bit i: x - e_i is
+// solid; bit 31: the node is solid).  A fluid node pulls, for each direction
+// whose source is solid, its own post-collision value of the opposite
+// direction (halfway bounce-back), and adds those same values to its
+// rho(t+1); solid nodes do not collide and send nothing.
+template <int LAT, int TY, bool FULL, bool WALL = false>
 __global__ void __launch_bounds__(64 * TY, TY <= 8 ? 2 : 1)
 k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ F,
-       double* __restrict__ rho_next, double* __restrict__ ringsum, Grid g, TileGeom tg, Relax rx)
+       double* __restrict__ rho_next, double* __restrict__ ringsum, Grid g, TileGeom tg, Relax rx,
+       const unsigned* __restrict__ wb = nullptr)
 {
     using L = Lat<LAT>;
     using TR = TileRing<TY>;
@@ -830,18 +837,25 @@ k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
     if (ring) TR::cell(lid, rcx, rcy);
 
     double f[Q], Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    unsigned bits = 0, bits_next = 0;   // wall mask of the plane pulled last / next
     auto pull_plane = [&](int z) {
         const int zo = z * nxy;
         const int zmo = LAT == 1 ? wrapc(z - 1, nz) * nxy : 0;
         const int zpo = LAT == 1 ? wrapc(z + 1, nz) * nxy : 0;
+        const unsigned n = (unsigned)(zo + yc + x);
+        if constexpr (WALL) bits = bits_next;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int ox = L::ex(i) == 1 ? xm : L::ex(i) == -1 ? xp : x;
             const int oy = L::ey(i) == 1 ? ym : L::ey(i) == -1 ? yp : yc;
             const int oz = L::ez(i) == 1 ? zmo : L::ez(i) == -1 ? zpo : zo;
-            f[i] = ld32(S + (long long)i * g.ps, (unsigned)(oz + oy + ox));
+            if constexpr (WALL) {
+                const bool bb = (bits >> i) & 1u;
+                f[i] = ld32(S + (long long)(bb ? L::opp(i) : i) * g.ps, bb ? n : (unsigned)(oz + oy + ox));
+            } else {
+                f[i] = ld32(S + (long long)i * g.ps, (unsigned)(oz + oy + ox));
+            }
         }
-        const unsigned n = (unsigned)(zo + yc + x);
         Fx = ld32(F, n);
         Fy = ld32(F + N, n);
         if constexpr (LAT == 1) Fz = ld32(F + 2LL * N, n);
@@ -849,20 +863,37 @@ k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
 
     double acc_m1 = 0.0, acc_0 = 0.0, racc_m1 = 0.0, racc_0 = 0.0;
     const int zb = LAT == 1 ? z0 - 1 : 0, ze = LAT == 1 ? z1 : 0;
+    // the mask is loaded one plane ahead of the pulls it steers
+    if constexpr (WALL) bits_next = wb[(LAT == 1 ? pwrap(zb, nz) : 0) * nxy + yc + x];
     pull_plane(LAT == 1 ? pwrap(zb, nz) : 0);
+    if constexpr (WALL) {
+        if (LAT == 1 && zb < ze) bits_next = wb[pwrap(zb + 1, nz) * nxy + yc + x];
+    }
     for (int zr = zb; zr <= ze; ++zr) {
         const int z = LAT == 1 ? pwrap(zr, nz) : 0;
         double own_m1 = 0.0, own_0 = 0.0, own_p1 = 0.0;
+        double ob[WALL ? Q : 1];   // this node's post-collision values (bounce-back)
+        const unsigned mb = bits;
+        const bool solid = WALL && (mb >> 31);
         {
             const bool store = zr >= z0 && zr < z1;
             const int n = z * nxy + yc + x;
-            collide_emit<LAT, FULL>(f, Fx, Fy, Fz, rx, [&](int i, double o) {
-                if (store) st32(Sn + (long long)i * g.ps, (unsigned)n, o);
-                if (xcls_of<LAT>(i) >= 0) xs[xcls_of<LAT>(i)][lid] = o;
-                else if (L::ez(i) == -1) own_m1 = o;
-                else if (L::ez(i) == 0) own_0 = o;
-                else own_p1 = o;
-            });
+            if (!solid) {
+                collide_emit<LAT, FULL>(f, Fx, Fy, Fz, rx, [&](int i, double o) {
+                    if (store) st32(Sn + (long long)i * g.ps, (unsigned)n, o);
+                    if (xcls_of<LAT>(i) >= 0) xs[xcls_of<LAT>(i)][lid] = o;
+                    else if (L::ez(i) == -1) own_m1 = o;
+                    else if (L::ez(i) == 0) own_0 = o;
+                    else own_p1 = o;
+                    if constexpr (WALL) ob[i] = o;
+                });
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if (xcls_of<LAT>(i) >= 0) xs[xcls_of<LAT>(i)][lid] = 0.0;
+                    if constexpr (WALL) ob[i] = 0.0;
+                }
+            }
         }
         __syncthreads();
         // values arriving from inside the tile, at the own node and (first NR
@@ -884,7 +915,18 @@ k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
                 }
             }
         }
+        if constexpr (WALL) {
+            // values sent towards solid neighbours come back to this node
+            if (!solid) {
+#pragma unroll
+                for (int j = 1; j < Q; ++j)
+                    if ((mb >> j) & 1u) a_0 += ob[L::opp(j)];
+            }
+        }
         if (zr < ze) pull_plane(pwrap(zr + 1, nz));
+        if constexpr (WALL) {
+            if (LAT == 1 && zr + 1 < ze) bits_next = wb[pwrap(zr + 2, nz) * nxy + yc + x];
+        }
         __syncthreads();
         if constexpr (LAT == 1) {
             acc_m1 += a_m1;
@@ -977,16 +1019,25 @@ inline TileGeom tile_geom(const Grid& g, bool three_d, int ty)
 
 template <int LAT, int TY>
 inline void launch_tile_ty(const double* S, double* Sn, const double* F, double* rho_next, double* ringsum,
-                           const Grid& g, const Relax& rx, hipStream_t st)
+                           const Grid& g, const Relax& rx, hipStream_t st, const unsigned* wb)
 {
     const TileGeom t = tile_geom(g, LAT == 1, TY);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
-    if (rx.omo == 0.0 && !rx.mrt)
+    const bool full = rx.omo == 0.0 && !rx.mrt;
+    if (wb) {
+        if (full)
+            hipLaunchKernelGGL((k_tile<LAT, TY, true, true>), dim3(nb), dim3(64 * TY), 0, st, S, Sn, F, rho_next,
+                               ringsum, g, t, rx, wb);
+        else
+            hipLaunchKernelGGL((k_tile<LAT, TY, false, true>), dim3(nb), dim3(64 * TY), 0, st, S, Sn, F, rho_next,
+                               ringsum, g, t, rx, wb);
+    } else if (full) {
         hipLaunchKernelGGL((k_tile<LAT, TY, true>), dim3(nb), dim3(64 * TY), 0, st, S, Sn, F, rho_next, ringsum,
-                           g, t, rx);
-    else
+                           g, t, rx, nullptr);
+    } else {
         hipLaunchKernelGGL((k_tile<LAT, TY, false>), dim3(nb), dim3(64 * TY), 0, st, S, Sn, F, rho_next, ringsum,
-                           g, t, rx);
+                           g, t, rx, nullptr);
+    }
 }
 
 template <int TY>
@@ -1002,10 +1053,10 @@ inline void launch_fix_ty(double* rho_next, const double* ringsum, const Grid& g
 // tv: tile variant, 0 .. num_tile_variants(g) - 1
 template <int LAT>
 inline void launch_tile(int tv, const double* S, double* Sn, const double* F, double* rho_next, double* ringsum,
-                        const Grid& g, const Relax& rx, hipStream_t st)
+                        const Grid& g, const Relax& rx, hipStream_t st, const unsigned* wb = nullptr)
 {
-    if (tv == 1) launch_tile_ty<LAT, kTileTYs[1]>(S, Sn, F, rho_next, ringsum, g, rx, st);
-    else launch_tile_ty<LAT, kTileTYs[0]>(S, Sn, F, rho_next, ringsum, g, rx, st);
+    if (tv == 1) launch_tile_ty<LAT, kTileTYs[1]>(S, Sn, F, rho_next, ringsum, g, rx, st, wb);
+    else launch_tile_ty<LAT, kTileTYs[0]>(S, Sn, F, rho_next, ringsum, g, rx, st, wb);
 }
 
 template <int LAT>

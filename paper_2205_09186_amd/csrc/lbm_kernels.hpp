@@ -205,6 +205,26 @@ __global__ void __launch_bounds__(256) k_wall_layer(unsigned char* __restrict__ 
     if (touch) wl[n] = (unsigned char)l;
 }
 
+// Per-node mask for the fast path's bounce-back: bit 31 marks a solid node;
+// on a fluid node bit i marks a solid source x - e_i.
+template <int LAT>
+__global__ void __launch_bounds__(256) k_wall_bits(const unsigned char* __restrict__ wl, unsigned* __restrict__ wb,
+                                                   Grid g)
+{
+    using L = Lat<LAT>;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    if (wl[n] != 0) { wb[n] = 1u << 31; return; }
+    int x, y, z;
+    coords(n, g, x, y, z);
+    Nbr<1, L::DIM> nb(x, y, z, g);
+    unsigned m = 0;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i)
+        if (wl[nb.at(-L::ex(i), -L::ey(i), -L::ez(i))] != 0) m |= 1u << i;
+    wb[n] = m;
+}
+
 // Eq A.1 on layer l; the l = 1 launch also gives the solid beyond the last
 // layer a harmless density of 1 (no fluid stencil reaches it).
 template <int LAT>

@@ -158,3 +158,34 @@ def test_wall_fixed_point_uniform_fluid(L, orc):
     f0 = sim.populations()
     sim.step(20)
     assert np.abs(sim.populations() - f0).max() < 1e-14
+
+
+@pytest.mark.parametrize("lat,shape,scheme,mu_rel,coll", [(0, (48, 128), "CD6", 2.0, 0), (0, (64, 64), "CD4", -1.0, 1),
+                                                         (1, (24, 16, 64), "CD4", 1.0, 0),
+                                                         (1, (20, 32, 64), "CD6", 3.0, 0)])
+def test_wall_tile_collide(L, orc, lat, shape, scheme, mu_rel, coll, monkeypatch):
+    """Grids tiled by 64 x 8 take the tile collide with bounce-back (every tile
+    height) against the oracle and against the node-parallel path."""
+    solid, rho0 = _case(orc, lat, shape, 5 if lat == 0 else 4, ball=True, seed=2)
+    nz, ny, nx = ((1,) + tuple(shape)) if lat == 0 else tuple(shape)
+    kw = dict(lattice=lat, nx=nx, ny=ny, nz=nz, tau=1.0 if not coll else 0.9, Tr=0.8, k=0.16, kappa=0.004,
+              scheme=L.SCHEMES[scheme], collision=coll, s_e=1.25 if coll else 0.0,
+              mu_wall=_mu_M(orc, 0.8, 0.16) * (1.0 + mu_rel))
+    steps = 120 if lat == 0 else 40
+    print(f"case wall tile lattice={lat} shape={shape} scheme={scheme}", flush=True)
+    monkeypatch.setenv("LBM_NO_FUSED", "1")
+    ref = L.Simulation(L.Params(wall=1, **kw), rho0, solid=solid)
+    monkeypatch.delenv("LBM_NO_FUSED")
+    ref.step(steps)
+    o = orc.Sim(orc.Params(solid=solid, **kw), rho0)
+    o.step(steps)
+    probe = L.Simulation(L.Params(wall=1, **kw), rho0, solid=solid)
+    nv = probe.num_variants
+    assert nv == (2 if ny % 16 == 0 else 1)
+    assert [n for n, _ in probe.step_timed(1)][-2:] == ["k_tile", "k_fix"]
+    for v in range(nv):
+        sim = L.Simulation(L.Params(wall=1, **kw), rho0, solid=solid)
+        sim.set_variant(v)
+        sim.step(steps)
+        assert np.abs(sim.populations() - ref.populations()).max() < 1e-13, v
+        _compare(sim, o, solid)
