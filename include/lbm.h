@@ -112,8 +112,10 @@ size_t lbm_workspace_bytes(const lbm_params* p);
  * before them and the chemical potential p->mu_wall; populations that stream
  * into a solid node return to their node reversed (halfway bounce-back, the
  * reading taken where the paper names no rule).  Solid nodes report rho = 0
- * and v = 0; the observables run over the fluid.  The step runs on the
- * node-parallel kernels (no launch variants).  Errors as lbm_init. */
+ * and v = 0; the observables run over the fluid.  On grids tiled by 64 x 8
+ * (nx a multiple of 64, ny of 8) the step runs on the tile collide, one launch
+ * variant per tile height; otherwise on the node-parallel kernels (one
+ * variant).  Errors as lbm_init. */
 int lbm_init_wall(const lbm_params* p, const double* rho0, const unsigned char* solid, int on_device,
                   void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
 
