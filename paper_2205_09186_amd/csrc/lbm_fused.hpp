@@ -1105,11 +1105,6 @@ inline void launch_ring_collide(int variant, const double* S, double* Sn, const 
     }
 }
 
-// The fused path covers the per-axis explicit schemes on grids whose node
-// count fits 32-bit offsets.
-template <int LAT, int SCH>
-inline bool fused_available(const Grid& g) { return (SCH == CD2 || SCH == CD4 || SCH == CD6) && g.N < (1LL << 29); }
-
 // Launch variants of the fused kernel (tile height, waves per SIMD the register
 // allocation must allow).  The tuner times them on the actual grid.
 struct FusedVariant { int ty, occ, pipe; };
