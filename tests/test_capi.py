@@ -85,7 +85,9 @@ def test_init_rejects_bad_arguments_without_gpu():
 def test_wall_parameters_are_validated():
     base = dict(lattice=lbm.D2Q9, nx=16, ny=16, wall=1, scheme=lbm.CD6, mu_wall=0.01)
     ok = lbm.workspace_bytes(lbm.Params(**base))
-    assert ok == lbm.workspace_bytes(lbm.Params(**{**base, "wall": 0})) + 256
+    # the layer map (1 byte per node) and the bounce-back mask (4 bytes per node),
+    # each 256-byte aligned
+    assert ok == lbm.workspace_bytes(lbm.Params(**{**base, "wall": 0})) + 256 + 1024
     for bad in (dict(scheme=lbm.E4), dict(scheme=lbm.OCFDS4), dict(scheme=lbm.CFDS6), dict(wall=2),
                 dict(mu_wall=float("nan"))):
         assert lbm.workspace_bytes(lbm.Params(**{**base, **bad})) == 0, bad
