@@ -334,3 +334,33 @@ def test_isotropic_second_order_exact_on_quadratics(orc, dim, name):
     for d in range(dim):
         assert G[d][centre] == pytest.approx(bvec[d], abs=1e-11)
     assert orc.lap(g, sch)[centre] == pytest.approx(np.trace(A), abs=1e-11)
+
+
+@pytest.mark.parametrize("name,c1,c2", [("E6", Fraction(7, 15), Fraction(1, 60)), ("E8", Fraction(8, 21), Fraction(5, 84))])
+def test_isotropic_gradient_along_one_axis(orc, name, c1, c2):
+    """On a field that varies along x only, the 2D isotropic gradient of Eq 25a
+    collapses to a 1D central stencil c1 (f[+1] - f[-1]) + c2 (f[+2] - f[-2]),
+    the weights of every vector with the same x offset summed (E8: 8/21 and
+    5/84); the y component vanishes."""
+    rng = np.random.default_rng(11)
+    f1 = rng.standard_normal(29)
+    g = rows(f1, ny=12)
+    G = orc.grad(g, orc.SCHEME_NAMES[name])
+    ref = float(c1) * (np.roll(f1, -1) - np.roll(f1, 1)) + float(c2) * (np.roll(f1, -2) - np.roll(f1, 2))
+    for y in range(12):
+        np.testing.assert_allclose(G[0][y], ref, atol=1e-14)
+    np.testing.assert_allclose(G[1], 0.0, atol=1e-14)
+
+
+def test_ocfds_modified_wavenumber_at_half_pi(orc):
+    """Eq 28 at omega = pi/2 with the derived a and the printed c: the compact
+    derivative of sin(pi x / 2) is omega' cos(pi x / 2), omega' = a - c/3 =
+    1.559033 (sin pi = 0, and alpha cos(pi/2) = 0)."""
+    n = 16
+    x = np.arange(n)
+    g = rows(np.sin(np.pi * x / 2), ny=4)
+    G = orc.grad(g, orc.OCFDS4)[0][0]
+    c = np.cos(np.pi * x / 2)
+    sel = np.abs(c) > 0.5
+    w = G[sel] / c[sel]
+    np.testing.assert_allclose(w, 1.559033, atol=5e-7)
