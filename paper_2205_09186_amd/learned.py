@@ -311,20 +311,28 @@ def main():
     ap.add_argument("--dump", default="", help="directory for the dataset and per-instance results")
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--load", default="", help="parameters saved by --save: skip the dataset and the training")
+    ap.add_argument("--eval-seed", type=int, default=7, help="seed of the held-out droplet set")
     a = ap.parse_args()
-    t0 = time.perf_counter()
-    X, T, nprof, st = make_dataset(a.batches, steps=a.data_steps)
-    t1 = time.perf_counter()
     import os
     import torch
-    if a.dump:
-        os.makedirs(a.dump, exist_ok=True)
-        np.save(os.path.join(a.dump, "X.npy"), X)
-        np.save(os.path.join(a.dump, "T.npy"), T)
+    t0 = time.perf_counter()
     net = Net(0)
-    hist = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), iters=a.iters, lr=a.lr, batch=a.batch)
-    t2 = time.perf_counter()
-    summary, full = evaluate(net, n=a.eval, max_steps=a.max_steps)
+    if a.load:
+        net.load(np.load(a.load))
+        nprof, X, st, hist = 0, np.zeros((0, 4), np.float32), [], []
+        t1 = t2 = time.perf_counter()
+    else:
+        X, T, nprof, st = make_dataset(a.batches, steps=a.data_steps)
+        t1 = time.perf_counter()
+        if a.dump:
+            os.makedirs(a.dump, exist_ok=True)
+            np.save(os.path.join(a.dump, "X.npy"), X)
+            np.save(os.path.join(a.dump, "T.npy"), T)
+        hist = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), iters=a.iters, lr=a.lr,
+                         batch=a.batch)
+        t2 = time.perf_counter()
+    summary, full = evaluate(net, n=a.eval, seed=a.eval_seed, max_steps=a.max_steps)
     if a.dump:
         json.dump(full, open(os.path.join(a.dump, "eval_full.json"), "w"))
     t3 = time.perf_counter()
