@@ -48,7 +48,7 @@ def _compare(sim, o, tol=TOL):
 
 
 @pytest.mark.parametrize("scheme", ["CD6", "OCFDS4"])
-def test_config1_geometry_2000_steps(L, orc, scheme):
+def test_droplet_100x100_2000_steps(L, orc, scheme):
     """100 x 100, droplet R = 25, tanh width 2, noise 1e-6, tau = 1, the
     MRT rates of Sec 2.1, 2000 steps (CD4 diverges on both sides with these
     rates at T_r = 0.8: the low bulk viscosity of s_e = 1.64)."""

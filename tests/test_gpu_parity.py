@@ -56,21 +56,21 @@ def _compare(sim, o, tol=TOL):
     return d
 
 
-# Config 1 geometry: D2Q9 100x100, droplet R = 25 centred, tanh width 2,
+# The 100x100 droplet workload: D2Q9, droplet R = 25 centred, tanh width 2,
 # noise +-1e-6, tau = 1, 2000 steps.  CD2 at Tr = 0.8 diverges under the SRT
 # reading (oracle and GPU alike); the accurate schemes run at Tr = 0.8 and the
 # second-order / isotropic ones at Tr = 0.9 (E10, the least accurate, at 0.95), where
 # they are stable.
 @pytest.mark.parametrize("scheme,Tr", [("CD4", 0.8), ("CD6", 0.8), ("OCFDS4", 0.8),
                                        ("CD2", 0.9), ("E4", 0.9), ("E6", 0.9), ("E8", 0.9), ("E10", 0.95)])
-def test_config1_2000_steps(L, orc, scheme, Tr):
+def test_droplet_100x100_2000_steps(L, orc, scheme, Tr):
     sim, o = _run_pair(L, orc, L.D2Q9, (100, 100), L.SCHEMES[scheme], 2000, Tr=Tr)
     d = _compare(sim, o)
     print("max diffs", d)
 
 
-def test_config1_as_specified_diverges_on_both_sides(L, orc):
-    """CD2 at Tr = 0.8 (the literal config 1) blows up within a few hundred
+def test_droplet_100x100_cd2_tr08_diverges_on_both_sides(L, orc):
+    """CD2 at Tr = 0.8 (that workload as specified) blows up within a few hundred
     steps in the oracle; the GPU reports the same as a non-finite state."""
     sim, o = _run_pair(L, orc, L.D2Q9, (100, 100), L.CD2, 400, Tr=0.8)
     Uo, _ = o.observables()
