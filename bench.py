@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--Tr", type=float, default=0.7)
     ap.add_argument("--k", type=float, default=0.1)
     ap.add_argument("--kappa", type=float, default=0.004)
-    ap.add_argument("--cpu-steps", type=int, default=10, help="oracle steps timed for the CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="oracle steps timed for the CPU baseline (about 15 s on 16 host threads at 256^3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--wall", type=int, default=0,
