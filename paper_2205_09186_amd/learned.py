@@ -317,6 +317,8 @@ def main():
     import os
     import torch
     t0 = time.perf_counter()
+    if a.dump:
+        os.makedirs(a.dump, exist_ok=True)
     net = Net(0)
     if a.load:
         net.load(np.load(a.load))
@@ -326,7 +328,6 @@ def main():
         X, T, nprof, st = make_dataset(a.batches, steps=a.data_steps)
         t1 = time.perf_counter()
         if a.dump:
-            os.makedirs(a.dump, exist_ok=True)
             np.save(os.path.join(a.dump, "X.npy"), X)
             np.save(os.path.join(a.dump, "T.npy"), T)
         hist = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), iters=a.iters, lr=a.lr,
