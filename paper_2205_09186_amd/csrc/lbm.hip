@@ -159,6 +159,8 @@ struct lbm_ctx {
     // wavefront) only where rows are many, the whole-row scan being faster on
     // small grids.  LBM_SEG_MIN_LINES sets both (the tests force either path).
     long long seg_min_lines_yz = 0, seg_min_lines_x = 1LL << 14;
+    // y and z lines of 257..1024 points: one wavefront per line (LBM_NO_WAVE_LINES: chunked)
+    bool wave_lines = true;
     // compact schemes run the per-axis derivative passes concurrently, axis
     // d > 0 on branch stream br[d - 1], forked from and joined to the
     // context's stream by events (LBM_NO_CONC turns it off)
@@ -239,6 +241,13 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
             hipLaunchKernelGGL(k_compact_seg<kSegLen>, dim3(blocks), dim3(64 * W), 0, c->stream, in, sink, lg, cc,
                                c->z, c->zscale, zS, zLast, zN);
         }
+        return;
+    }
+    if (d > 0 && lg.n <= 64 * kLineSeg && c->wave_lines) {
+        // longer lines: one wavefront per line, exact (lanes = segments)
+        const long long lines = (long long)lg.n1 * lg.n2;
+        hipLaunchKernelGGL(k_compact_wave, dim3((unsigned)((lines + 3) / 4)), dim3(256), 0, c->stream, in, sink, lg,
+                           cc, c->z, c->zscale);
         return;
     }
     if (d == 0 && lg.n <= 4096 && lg.K <= kScanWarm) {
@@ -594,6 +603,7 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
     c->variant = (p->lattice == LBM_D3Q19 && p->scheme <= LBM_CD6 && !p->wall) ? kNumFusedVariants : 0;
     c->use_graph = std::getenv("LBM_NO_GRAPH") == nullptr;
     if (const char* e = std::getenv("LBM_SEG_MIN_LINES")) c->seg_min_lines_yz = c->seg_min_lines_x = std::atoll(e);
+    c->wave_lines = std::getenv("LBM_NO_WAVE_LINES") == nullptr;
     // measured faster at every size from 100^2 to 256^3 (2D 1024^2 by 15%)
     c->conc = compact && std::getenv("LBM_NO_CONC") == nullptr;
     set_lines(c);

@@ -98,70 +98,16 @@ struct BLine {
 };
 
 // Compact derivative (Eq 21) of f along one periodic line of instance I into
-// out, by one wavefront: lane l takes the segment [l L, l L + L_l) of the line
-// (L = ceil(n / 64) <= kLineSeg).  Both recursions of the factorised cyclic
-// solve (a_i = v_i + z a_{i-1}, then y_i = a_i + z y_{i+1}, out = (1 + z^2) y)
-// run in registers from a zero start; the true value entering each segment
-// follows from a scan over the lanes of the pairs (z^L_l, local end), closed
-// around the periodic line by 1 / (1 - z^n).  Exact, no warm-up.
-constexpr int kLineSeg = 16;   // lines of up to 64 * 16 = 1024 nodes
-
+// out, by one wavefront (wave_line).
 __device__ void b_line(const BInst& I, const double* __restrict__ f, double* __restrict__ out, long long base,
                        long long sa, int n, int lane)
 {
-    const double ha = 0.5 * I.cc.ca, hb = 0.25 * I.cc.cb, hc = I.cc.cc / 6.0, z = I.z;
-    const int L = (n + 63) / 64;
-    const int s0 = min(lane * L, n);
-    const int Ll = min(L, n - s0);
-    double r[kLineSeg + 6];
-#pragma unroll
-    for (int k = 0; k < kLineSeg + 6; ++k) {
-        int idx = s0 - 3 + k;               // in [-3, n + 2]; n >= 4
-        idx += idx < 0 ? n : 0;
-        idx -= idx >= n ? n : 0;
-        r[k] = k < Ll + 6 ? f[base + idx * sa] : 0.0;
-    }
-    double acc = 0.0, pz = 1.0;
-#pragma unroll
-    for (int i = 0; i < kLineSeg; ++i) {
-        if (i < Ll) {
-            acc = ha * (r[i + 4] - r[i + 2]) + hb * (r[i + 5] - r[i + 1]) + hc * (r[i + 6] - r[i]) + z * acc;
-            r[i] = acc;
-            pz *= z;
-        }
-    }
-    // forward: T_l = E_l + z^L_l T_{l-1}, cyclic over the lanes
-    double P = pz, V = acc;
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-        const double Pp = __shfl_up(P, s, 64), Vp = __shfl_up(V, s, 64);
-        if (lane >= s) { V += P * Vp; P *= Pp; }
-    }
-    const double Tlast = __shfl(V, 63, 64) / (1.0 - __shfl(P, 63, 64));
-    double cin = __shfl_up(V + P * Tlast, 1, 64);
-    if (lane == 0) cin = Tlast;
-    double q = z;
+    double y[kLineSeg];
+    int s0, Ll;
+    wave_line(f, base, sa, n, lane, I.cc, I.z, I.zscale, y, s0, Ll);
 #pragma unroll
     for (int i = 0; i < kLineSeg; ++i)
-        if (i < Ll) { r[i] += q * cin; q *= z; }
-    acc = 0.0;
-#pragma unroll
-    for (int i = kLineSeg - 1; i >= 0; --i)
-        if (i < Ll) { acc = r[i] + z * acc; r[i] = acc; }
-    // backward: U_l = B_l + z^L_l U_{l+1}, cyclic over the lanes
-    P = pz; V = acc;
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-        const double Pn = __shfl_down(P, s, 64), Vn = __shfl_down(V, s, 64);
-        if (lane + s < 64) { V += P * Vn; P *= Pn; }
-    }
-    const double Ufirst = __shfl(V, 0, 64) / (1.0 - __shfl(P, 0, 64));
-    double cr = __shfl_down(V + P * Ufirst, 1, 64);
-    if (lane == 63) cr = Ufirst;
-    q = z;
-#pragma unroll
-    for (int i = kLineSeg - 1; i >= 0; --i)
-        if (i < Ll) { out[base + (s0 + i) * sa] = I.zscale * (r[i] + q * cr); q *= z; }
+        if (i < Ll) out[base + (s0 + i) * sa] = y[i];
 }
 
 struct BatchArgs {
