@@ -155,11 +155,14 @@ struct lbm_ctx {
     int graph_cur = -1, graph_variant = -1;
     bool use_graph = true;
     // fewest lines for which the compact line solves take the segmented
-    // kernels: always along y and z; along x (rows staged in LDS, RW rows per
-    // wavefront) only where rows are many, the whole-row scan being faster on
-    // small grids.  LBM_SEG_MIN_LINES sets both (the tests force either path).
-    long long seg_min_lines_yz = 0, seg_min_lines_x = 1LL << 14;
-    // y and z lines of 257..1024 points: one wavefront per line (LBM_NO_WAVE_LINES: chunked)
+    // kernels (lanes across neighbouring lines, coalesced): along y and z
+    // where there are enough lines to fill the chip (fewer lines go one
+    // wavefront each); along x (rows staged in LDS, RW rows per wavefront)
+    // only where rows are many, the whole-row scan being faster on small
+    // grids.  LBM_SEG_MIN_LINES sets both (the tests force either path).
+    long long seg_min_lines_yz = 4096, seg_min_lines_x = 1LL << 14;
+    // y and z lines of up to 1024 points that the segmented kernel does not
+    // take: one wavefront per line (LBM_NO_WAVE_LINES: chunked recursions)
     bool wave_lines = true;
     // compact schemes run the per-axis derivative passes concurrently, axis
     // d > 0 on branch stream br[d - 1], forked from and joined to the
@@ -244,7 +247,7 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
         return;
     }
     if (d > 0 && lg.n <= 64 * kLineSeg && c->wave_lines) {
-        // longer lines: one wavefront per line, exact (lanes = segments)
+        // longer lines, or few of them: one wavefront per line, exact (lanes = segments)
         const long long lines = (long long)lg.n1 * lg.n2;
         hipLaunchKernelGGL(k_compact_wave, dim3((unsigned)((lines + 3) / 4)), dim3(256), 0, c->stream, in, sink, lg,
                            cc, c->z, c->zscale);
