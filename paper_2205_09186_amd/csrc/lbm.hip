@@ -1138,7 +1138,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     b->nlines = (int)lines.size();
     b->nblk_total = (int)blk_inst.size();
     std::vector<BState> st(n);
-    for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.U = 0.0; x.U_prev = 0.0; }
+    for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.stop = -1; x.U = 0.0; x.U_prev = 0.0; }
     hipError_t e = hipSuccess;
     if (!lines.empty())
         e = hipMemcpyAsync(b->d_lines, lines.data(), sizeof(BLine) * lines.size(), hipMemcpyHostToDevice, b->stream);

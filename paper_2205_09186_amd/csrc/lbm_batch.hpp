@@ -3,16 +3,21 @@
 // cooperative persistent kernel.
 //
 // Every instance keeps its own populations, density and chemical potential in
-// one pool.  A step is a fixed sequence of phases (density, chemical potential
-// or the compact derivative line solves, collision); within a phase the
-// workgroups stride over the work items of all running instances, and a
-// grid-wide barrier separates the phases.  The cooperative launch guarantees
+// one pool.  A step is a fixed sequence of phases (density; the chemical
+// potential of the explicit schemes together with the compact schemes' line
+// solves of D rho and D(D rho); the compact schemes' line solves of D mu_hat;
+// collision); within a phase the workgroups stride over the work items of all
+// running instances, and a grid-wide barrier separates the phases.  The cooperative launch guarantees
 // that every workgroup is resident, every workgroup executes the same phase
 // sequence, and every loop is bounded, so the barriers always complete.
 // Every check_every steps the spurious current U = max |v| of each instance is
 // reduced (fixed order) and compared with the previous check: an instance
 // whose U changed by less than tol is CONVERGED, one with a non-finite state
 // or U above the sound speed is DIVERGED; both stop stepping.
+// During a launch the step count of an instance stays at its launch-start
+// value (loop step s is its step steps + s), so no phase of the step is spent
+// on counters; the counts advance once, after the loop.  The check phase and
+// its two barriers run only on loop steps where some instance is due.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,11 +43,12 @@ struct BInst {
 
 struct BState {             // per instance, updated by the kernel
     int status;
-    long long steps;
+    long long steps;        // steps taken; fixed during a launch, advanced at its end
+    long long stop;         // loop step of a launch at which the instance retired, else -1
     double U, U_prev;
 };
 
-constexpr int BNODES = 256;   // nodes per node-block item (one per thread)
+constexpr int BNODES = 512;   // nodes per node-block item (one per thread), threads per workgroup
 
 // ---------------------------------------------------------------------------
 // per-node bodies with runtime scheme dispatch
@@ -97,14 +103,15 @@ struct BLine {
     int inst, axis, idx;
 };
 
-// Compact derivative (Eq 21) of f along one periodic line of instance I into
-// out, by one wavefront (wave_line).
-__device__ void b_line(const BInst& I, const double* __restrict__ f, double* __restrict__ out, long long base,
-                       long long sa, int n, int lane)
+// Compact derivative (Eq 21) along one periodic line of instance I of the
+// field that ld(o) reads, into out, by one wavefront (wave_line).
+template <class Load>
+__device__ void b_line(const BInst& I, Load&& ld, double* __restrict__ out, long long base, long long sa, int n,
+                       int lane)
 {
     double y[kLineSeg];
     int s0, Ll;
-    wave_line(f, base, sa, n, lane, I.cc, I.z, I.zscale, y, s0, Ll);
+    wave_line(ld, base, sa, n, lane, I.cc, I.z, I.zscale, y, s0, Ll);
 #pragma unroll
     for (int i = 0; i < kLineSeg; ++i)
         if (i < Ll) out[base + (s0 + i) * sa] = y[i];
@@ -140,7 +147,7 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
             const int ii = a.blk_inst[it];
             const BInst& I = a.inst[ii];
             if (a.st[ii].status != B_RUNNING) continue;
-            const double* Sc = I.S[a.st[ii].steps & 1];
+            const double* Sc = I.S[(a.st[ii].steps + s) & 1];
             const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
             if (n < I.g.N) {
                 int x, y, z;
@@ -151,10 +158,15 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
             }
         }
         bar(gg);
-        // ---- compact schemes: the line solves of D rho, then of D(D rho) ------
-        // the x and y lines of a stage run together
+        // ---- compact schemes: the line solves.  One wavefront takes a line
+        // (t is uniform over the wavefront); the x and y lines of a stage run
+        // together.  Stage 0 solves D rho and then, from the values it has just
+        // written (its own line only), D(D rho); stage 1 solves D mu_hat with
+        // mu_hat = k^2 psi'(rho) - kappa_hat (D_x D_x rho + D_y D_y rho) formed as
+        // it is read (Eq 16; the Laplacian terms in axis order), so mu_hat is
+        // never stored: the force of the compact schemes takes only the
+        // gradients. ----------------------------------------------------------
         auto line_stage = [&](int stage) {
-            // one wavefront per line (t is uniform over the wavefront)
             const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
             for (int t = blockIdx.x * (BNODES / 64) + wv; t < a.nlines; t += gridDim.x * (BNODES / 64)) {
                 const BLine ln = a.lines[t];
@@ -164,30 +176,27 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
                 const long long base = ln.axis == 0 ? (long long)ln.idx * I.g.nx : ln.idx;
                 const long long sa = ln.axis == 0 ? 1 : I.g.nx;
                 const int n = ln.axis == 0 ? I.g.nx : I.g.ny;
-                const double* f = stage == 0 ? I.rho : stage == 1 ? I.grho + ln.axis * N : I.mu;
-                double* out = stage == 0 ? I.grho + ln.axis * N : stage == 1 ? I.lap + ln.axis * N
-                                                                               : I.gmu + ln.axis * N;
-                b_line(I, f, out, base, sa, n, lane);
+                if (stage == 0) {
+                    double* g1 = I.grho + ln.axis * N;
+                    b_line(I, [&](long long o) { return I.rho[o]; }, g1, base, sa, n, lane);
+                    __threadfence_block();   // this wavefront's stores before its loads
+                    b_line(I, [&](long long o) { return g1[o]; }, I.lap + ln.axis * N, base, sa, n, lane);
+                } else {
+                    b_line(I, [&](long long o) {
+                        return mu_bulk(I.rho[o], I.eos) - I.eos.kappa * (I.lap[o] + I.lap[N + o]);
+                    }, I.gmu + ln.axis * N, base, sa, n, lane);
+                }
             }
         };
-        if (a.has_compact) {
-            line_stage(0);
-            bar(gg);
-            line_stage(1);
-            bar(gg);
-        }
-        // ---- phase: chemical potential -----------------------------------------
+        if (a.has_compact) line_stage(0);
+        // ---- phase: chemical potential of the explicit schemes (same phase as
+        // the first line solves, which it does not touch) ----------------------
         for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
             const int ii = a.blk_inst[it];
             const BInst& I = a.inst[ii];
-            if (a.st[ii].status != B_RUNNING) continue;
+            if (a.st[ii].status != B_RUNNING || is_compact(I.scheme)) continue;
             const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
             if (n < I.g.N) {
-                if (is_compact(I.scheme)) {
-                    // the Laplacian terms of the two axes, in axis order (Eq 16)
-                    I.mu[n] = mu_bulk(I.rho[n], I.eos) - I.eos.kappa * (I.lap[n] + I.lap[I.g.N + n]);
-                    continue;
-                }
                 int x, y, z;
                 coords(n, I.g, x, y, z);
                 switch (I.scheme) {
@@ -202,19 +211,21 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
             }
         }
         bar(gg);
-        // ---- compact schemes: the line solves of D mu_hat ------------------------
         if (a.has_compact) {
-            line_stage(2);
+            line_stage(1);
             bar(gg);
         }
         // ---- convergence check on the current state (every check_every steps) --
-        const bool check = a.check_every > 0;
-        if (check) {
+        // due: some instance is at a multiple of check_every (the same answer in
+        // every workgroup, from the launch-start counts)
+        int due = 0;
+        for (int i = threadIdx.x; i < a.ninst; i += BNODES) due |= (a.st[i].steps + s) % a.check_every == 0;
+        if (__syncthreads_or(due)) {
             for (int it = blockIdx.x; it < a.nblk_total; it += gridDim.x) {
                 const int ii = a.blk_inst[it];
-                if (a.st[ii].status != B_RUNNING || a.st[ii].steps % a.check_every != 0) continue;
+                if (a.st[ii].status != B_RUNNING || (a.st[ii].steps + s) % a.check_every != 0) continue;
                 const BInst& I = a.inst[ii];
-                const double* Sc = I.S[a.st[ii].steps & 1];
+                const double* Sc = I.S[(a.st[ii].steps + s) & 1];
                 const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
                 double vm = 0.0;
                 if (n < I.g.N) {
@@ -242,14 +253,15 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
             // one thread per instance folds its node-block maxima in order
             for (int ii = blockIdx.x * BNODES + threadIdx.x; ii < a.ninst; ii += gridDim.x * BNODES) {
                 BState& S = a.st[ii];
-                if (S.status != B_RUNNING || S.steps % a.check_every != 0) continue;
+                if (S.status != B_RUNNING || (S.steps + s) % a.check_every != 0) continue;
                 const BInst& I = a.inst[ii];
                 double U = 0.0;
                 for (int k = 0; k < I.nblk; ++k) U = nmax(U, a.partial[I.blk0 + k]);
                 S.U_prev = S.U;
                 S.U = U;
                 if (!(U == U) || U - U != 0.0 || U > 0.5773502691896258) S.status = B_DIVERGED;
-                else if (S.steps > 0 && fabs(U - S.U_prev) < a.tol) S.status = B_CONVERGED;
+                else if (S.steps + s > 0 && fabs(U - S.U_prev) < a.tol) S.status = B_CONVERGED;
+                if (S.status != B_RUNNING) S.stop = s;
             }
             bar(gg);
         }
@@ -258,7 +270,7 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
             const int ii = a.blk_inst[it];
             if (a.st[ii].status != B_RUNNING) continue;
             const BInst& I = a.inst[ii];
-            const int cur = (int)(a.st[ii].steps & 1);
+            const int cur = (int)((a.st[ii].steps + s) & 1);
             const double* Sc = I.S[cur];
             double* Sn = I.S[1 - cur];
             const long long n = (long long)(it - I.blk0) * BNODES + threadIdx.x;
@@ -274,10 +286,14 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
             }
         }
         bar(gg);
-        // ---- advance step counters ----------------------------------------------
-        for (int ii = blockIdx.x * BNODES + threadIdx.x; ii < a.ninst; ii += gridDim.x * BNODES)
-            if (a.st[ii].status == B_RUNNING) a.st[ii].steps++;
-        bar(gg);
+    }
+    // ---- advance the step counters: running instances took every step, the
+    // ones that retired during this launch stopped at loop step S.stop --------
+    for (int ii = blockIdx.x * BNODES + threadIdx.x; ii < a.ninst; ii += gridDim.x * BNODES) {
+        BState& S = a.st[ii];
+        if (S.status == B_RUNNING) S.steps += a.nsteps;
+        else if (S.stop >= 0) S.steps += S.stop;
+        S.stop = -1;
     }
 }
 

@@ -656,12 +656,13 @@ __global__ void __launch_bounds__(256) k_compact_bwd(const double* __restrict__ 
 // run in registers from a zero start; the true value entering each segment
 // follows from a scan over the lanes of the pairs (z^L_l, local end), closed
 // around the periodic line by 1 / (1 - z^n).  Exact, no warm-up.  The lane's
-// results land in y[0 .. Ll) for the points s0 .. s0 + Ll - 1.
+// results land in y[0 .. Ll) for the points s0 .. s0 + Ll - 1.  The field
+// value at offset o comes from ld(o).
 constexpr int kLineSeg = 16;   // lines of up to 64 * 16 = 1024 nodes
 
-__device__ __forceinline__ void wave_line(const double* __restrict__ f, long long base, long long sa, int n, int lane,
-                                          const Compact& c, double z, double scale, double (&y)[kLineSeg], int& s0,
-                                          int& Ll)
+template <class Load>
+__device__ __forceinline__ void wave_line(Load&& ld, long long base, long long sa, int n, int lane, const Compact& c,
+                                          double z, double scale, double (&y)[kLineSeg], int& s0, int& Ll)
 {
     const double ha = 0.5 * c.ca, hb = 0.25 * c.cb, hc = c.cc / 6.0;
     const int L = (n + 63) / 64;
@@ -673,7 +674,7 @@ __device__ __forceinline__ void wave_line(const double* __restrict__ f, long lon
         int idx = s0 - 3 + k;               // in [-3, n + 2]; n >= 4
         idx += idx < 0 ? n : 0;
         idx -= idx >= n ? n : 0;
-        r[k] = k < Ll + 6 ? f[base + idx * sa] : 0.0;
+        r[k] = k < Ll + 6 ? ld(base + idx * sa) : 0.0;
     }
     double acc = 0.0, pz = 1.0;
 #pragma unroll
@@ -731,7 +732,7 @@ __global__ void __launch_bounds__(256) k_compact_wave(const double* __restrict__
     const long long base = (t % lg.n1) * lg.s1 + (t / lg.n1) * lg.s2;
     double y[kLineSeg];
     int s0, Ll;
-    wave_line(f, base, lg.sa, lg.n, lane, c, z, scale, y, s0, Ll);
+    wave_line([&](long long o) { return f[o]; }, base, lg.sa, lg.n, lane, c, z, scale, y, s0, Ll);
     long long o[kLineSeg];
     bool ok[kLineSeg];
 #pragma unroll

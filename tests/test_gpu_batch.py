@@ -68,7 +68,7 @@ def test_batch_retires_diverged_and_converged(L):
     ps, rs = _build(L, specs)
     b = L.Batch(ps, rs)
     st, steps, U = b.run(600, check_every=50, tol=0.0, chunk=200)
-    assert st[0] == L.DIVERGED and steps[0] < 600
+    assert st[0] == L.DIVERGED and steps[0] < 600 and steps[0] % 50 == 0
     assert list(st[1:]) == [L.RUNNING, L.RUNNING] and list(steps[1:]) == [600, 600]
     # the diverged instance stopped stepping; the others are unaffected
     for i in (1, 2):
@@ -90,3 +90,19 @@ def test_batch_launch_size_independent(L):
     b.run(150, check_every=50, tol=0.0, chunk=60)
     for i in range(len(ps)):
         assert np.array_equal(a.instance(i).populations(), b.instance(i).populations())
+
+
+def test_batch_retire_inside_a_launch(L):
+    """Instances retire at the check step itself, also when that step falls
+    inside a launch (checks every 70 steps, launches of 50): the step count and
+    the state are those of a plain run of that many steps."""
+    ps, rs = _build(L, _specs(L)[:3])
+    b = L.Batch(ps, rs)
+    st, steps, _ = b.run(400, check_every=70, tol=1.0, chunk=50)
+    assert list(st) == [L.CONVERGED] * len(ps)
+    assert list(steps) == [70] * len(ps)
+    for i in range(len(ps)):
+        s = L.Simulation(ps[i], rs[i])
+        s.step(70)
+        assert b.instance(i).steps_done == 70
+        assert np.abs(b.instance(i).populations() - s.populations()).max() < 1e-11
