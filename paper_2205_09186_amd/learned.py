@@ -299,6 +299,91 @@ def evaluate(net: Net, n=64, seed=7, max_steps=30000, check_every=100, tol=1e-10
     return summary, out
 
 
+def droplet_set_3d(n, seed, r_frac=(0.22, 0.32), tr_range=(0.65, 0.85), k_range=(0.1, 0.25), sides=(96, 128)):
+    """Seeded 3D droplets (D3Q19, L^3 periodic) for the learned start in 3D.
+    The radius is a fraction of the box: smaller droplets evaporate into the
+    vapour of a periodic box (more readily in 3D than in 2D)."""
+    rng = np.random.default_rng(inputs.SEED_BASE + 5000 + seed)
+    out = []
+    for i in range(n):
+        L = int(sides[int(rng.integers(0, len(sides)))])
+        R = float(rng.uniform(*r_frac)) * L
+        sch = SCHEMES6[int(rng.integers(0, 6))]
+        tr = STABLE_TR.get(sch, tr_range)
+        out.append(dict(L=L, R=R, Tr=float(rng.uniform(*tr)), k=float(rng.uniform(*k_range)),
+                        scheme=sch, instance_id=20000 + 1000 * seed + i))
+    return out
+
+
+def run_to_equilibrium(p: lbm.Params, rho0, max_steps, check_every=100, tol=1e-10):
+    """One plain context from rho0 under the convergence rule of the batched
+    sweep: U = max|v| is taken every check_every steps before stepping on;
+    converged at the first check t > 0 with |U(t) - U(t - check_every)| < tol,
+    diverged on a non-finite state or U above the sound speed.
+    Returns (status, steps, U, rho_l at the centre, rho_g at the corner)."""
+    sim = lbm.Simulation(p, rho0)
+    steps, U_prev, status, U = 0, None, lbm.RUNNING, float("nan")
+    while True:
+        U = float(sim.spurious_max()[0])
+        if not np.isfinite(U) or U > 3 ** -0.5:
+            status = lbm.DIVERGED
+            break
+        if U_prev is not None and abs(U - U_prev) < tol:
+            status = lbm.CONVERGED
+            break
+        if steps >= max_steps:
+            break
+        U_prev = U
+        sim.step(check_every)
+        steps += check_every
+    if status == lbm.DIVERGED:
+        return status, steps, U, float("nan"), float("nan")
+    r = sim.macros()[0]
+    c = tuple(s // 2 for s in r.shape)
+    return status, steps, U, float(r[c]), float(r[(0,) * r.ndim])
+
+
+def evaluate_3d(net: Net, n=8, seed=7, max_steps=60000, check_every=100, tol=1e-10):
+    """3D droplets started from tanh (Eq 26, W = 10) and from the learned
+    profile (trained on 2D droplets; same mass), each run to equilibrium."""
+    import torch
+    specs = droplet_set_3d(n, seed)
+    rows, fallback = [], 0
+    for i, d in enumerate(specs):
+        L = d["L"]
+        g, l = lbm.coexistence(d["Tr"])
+        p = lbm.Params(lattice=lbm.D3Q19, nx=L, ny=L, nz=L, Tr=d["Tr"], k=d["k"], kappa=0.004, scheme=d["scheme"])
+        r_t = inputs.droplet((L, L, L), d["R"], 10.0, g, l, instance_id=d["instance_id"], relative=True)
+        rho, _ = mass_matched_field(net, p, d["R"], d["Tr"], d["k"], d["scheme"], g, l, float(r_t.sum()))
+        if rho is None or not bool(torch.isfinite(rho).all()):
+            fallback += 1
+            r_l = r_t
+        else:
+            r_l = rho.cpu().numpy().reshape(r_t.shape)
+        row = dict(spec=d)
+        for name, r0 in (("tanh", r_t), ("learned", r_l)):
+            st, steps, U, rl, rg = run_to_equilibrium(p, r0, max_steps, check_every, tol)
+            row[name] = dict(status=int(st), steps=int(steps), U=U, rho_l=rl, rho_g=rg)
+        log(f"eval3d {i + 1}/{n}: L={L} R={d['R']:.1f} scheme={d['scheme']} Tr={d['Tr']:.3f} "
+            f"tanh {row['tanh']['status']}/{row['tanh']['steps']} learned {row['learned']['status']}/"
+            f"{row['learned']['steps']}")
+        rows.append(row)
+    both = [r for r in rows if r["tanh"]["status"] == lbm.CONVERGED and r["learned"]["status"] == lbm.CONVERGED]
+    ratio = [r["learned"]["steps"] / r["tanh"]["steps"] for r in both]
+    du = [abs(r["learned"]["U"] - r["tanh"]["U"]) / abs(r["tanh"]["U"]) for r in both]
+    summary = dict(n=n, fallback=fallback, both_converged=len(both),
+                   dissolved=int(sum(1 for r in rows if r["tanh"]["status"] == lbm.CONVERGED
+                                     and r["tanh"]["rho_l"] < 1.5 * r["tanh"]["rho_g"])),
+                   steps_ratio=ratio, steps_ratio_median=float(np.median(ratio)) if ratio else None,
+                   learned_fewer_steps=int(sum(1 for x in ratio if x < 1)),
+                   U_reldiff=du,
+                   rho_l_reldiff_max=max((abs(r["learned"]["rho_l"] - r["tanh"]["rho_l"]) / r["tanh"]["rho_l"]
+                                          for r in both), default=None),
+                   rho_g_reldiff_max=max((abs(r["learned"]["rho_g"] - r["tanh"]["rho_g"]) / r["tanh"]["rho_g"]
+                                          for r in both), default=None))
+    return summary, rows
+
+
 def main():
     import argparse
     ap = argparse.ArgumentParser()
@@ -313,6 +398,9 @@ def main():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--load", default="", help="parameters saved by --save: skip the dataset and the training")
     ap.add_argument("--eval-seed", type=int, default=7, help="seed of the held-out droplet set")
+    ap.add_argument("--eval3d", type=int, default=0,
+                    help="also this many 3D (D3Q19) droplets, tanh vs learned start, each run to equilibrium")
+    ap.add_argument("--max-steps-3d", type=int, default=60000)
     a = ap.parse_args()
     import os
     import torch
@@ -333,14 +421,19 @@ def main():
         hist = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), iters=a.iters, lr=a.lr,
                          batch=a.batch)
         t2 = time.perf_counter()
-    summary, full = evaluate(net, n=a.eval, seed=a.eval_seed, max_steps=a.max_steps)
-    if a.dump:
+    summary, full = evaluate(net, n=a.eval, seed=a.eval_seed, max_steps=a.max_steps) if a.eval > 0 else (None, None)
+    if a.dump and full is not None:
         json.dump(full, open(os.path.join(a.dump, "eval_full.json"), "w"))
+    summary3d = None
+    if a.eval3d > 0:
+        summary3d, rows3d = evaluate_3d(net, n=a.eval3d, seed=a.eval_seed, max_steps=a.max_steps_3d)
+        if a.dump:
+            json.dump(rows3d, open(os.path.join(a.dump, "eval3d_full.json"), "w"))
     t3 = time.perf_counter()
     if a.save:
         np.save(a.save, net.state())
     print(json.dumps(dict(profiles=nprof, samples=int(X.shape[0]), data_diverged=int(sum(1 for s in st if s == 2)),
-                          train_history=hist, eval=summary,
+                          train_history=hist, eval=summary, eval3d=summary3d,
                           seconds=dict(data=t1 - t0, train=t2 - t1, eval=t3 - t2))))
 
 
