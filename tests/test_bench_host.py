@@ -44,3 +44,4 @@ def test_traffic_record_lookup():
             assert got is None          # stale: taken on other kernel sources
         # another launch variant never borrows this record
         assert bench.traffic_record(kernel, workload, 999) is None
+

@@ -86,6 +86,24 @@ def test_field_inference_matches_reference(env):
     assert np.abs(rho.ravel() - ref).max() < 1e-4
 
 
+def test_field_inference_3d_matches_reference(env):
+    """The same network sets the density of a 3D (D3Q19) droplet, by the
+    Euclidean distance from the centre node (nx/2, ny/2, nz/2)."""
+    torch, lbm, learned, mlp = env
+    net = learned.Net(5)
+    theta = net.state().astype(np.float64)
+    p = lbm.Params(lattice=lbm.D3Q19, nx=20, ny=18, nz=16, Tr=0.75, k=0.15, scheme=lbm.OCFDS4)
+    g, l = 0.1, 8.0
+    rho = net.field(p, 6.3, 0.75, 0.15, lbm.OCFDS4, g, l).cpu().numpy().reshape(16, 18, 20)
+    f = learned.features(0.75, 0.15, lbm.OCFDS4)
+    zs, ys, xs = np.mgrid[0:16, 0:18, 0:20]
+    d = (np.sqrt((xs - 10.0) ** 2 + (ys - 9.0) ** 2 + (zs - 8.0) ** 2) - 6.3) / learned.NORM[6]
+    X = np.column_stack([np.tile(f, (d.size, 1)), d.ravel()]).astype(np.float32)
+    y, _ = mlp.forward(theta, X.astype(np.float64))
+    ref = g + np.clip(y, 0, 1) * (l - g)
+    assert np.abs(rho.ravel() - ref).max() < 1e-4
+
+
 def test_training_reduces_loss(env):
     torch, lbm, learned, mlp = env
     rng = np.random.default_rng(9)
