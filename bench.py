@@ -12,7 +12,9 @@ Prints ONE JSON line with MLUPS (whole-job throughput), the roofline of the
 dominant kernel (its algorithmic bytes per node times the nodes of one launch,
 over its average launch duration from HIP events on the step's stream, against
 the 8 TB/s HBM3E peak), the same for the whole step ((2Q+2)*8 bytes per node),
-and the CPU oracle timed on a bounded sample of the same workload.
+both also as fractions of the measured rate of a plain copy of the Q
+population arrays on the same grid (aligned, and as the streaming pull), and
+the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -120,6 +122,41 @@ def cpu_baseline(args, p, rho0, solid=None):
                       f"{dt:.2f} s wall time, OpenMP over nodes"}
 
 
+def copy_ceiling(lat, shape, reps=10):
+    """GB/s of the library's Q-array copy on the same grid, aligned and as the
+    streaming pull (HIP events on the current stream, mean of reps launches
+    after two untimed ones): the memory ceiling of any SoA step that reads and
+    writes every population once, measured on this device."""
+    import ctypes as C
+    import torch
+    from paper_2205_09186_amd import lbm
+    nz, ny, nx = shape if len(shape) == 3 else (1,) + tuple(shape)
+    q = 19 if lat == lbm.D3Q19 else 9
+    n = nx * ny * nz
+    src = torch.rand(q * n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    lib = lbm.lib()
+    out = {}
+    for pull in (0, 1):
+        def launch():
+            lbm._check(lib.lbm_probe_copy(lat, nx, ny, nz, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                          pull, C.c_void_p(stream.cuda_stream)))
+        launch()
+        launch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out["pull_copy_GBps" if pull else "aligned_copy_GBps"] = round(2 * q * 8 * n / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -197,6 +234,12 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    # the same grid's population copy, the ceiling of the access pattern;
+    # the dominant kernel and the step as fractions of it
+    ceil = copy_ceiling(lat, shape)
+    ceil["kernel_frac_of_pull_copy"] = round(achieved / ceil["pull_copy_GBps"], 4)
+    ceil["step_frac_of_pull_copy"] = round(step_gbs / ceil["pull_copy_GBps"], 4)
+    out["roofline"]["ceiling"] = ceil
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args, p, rho0, solid)
     print(json.dumps(out), flush=True)

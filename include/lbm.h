@@ -273,6 +273,18 @@ int mlp_field(const float* d_params, const float* norm7, const lbm_params* p, do
 size_t lbm_sum_scratch_bytes(long n);
 int lbm_sum(const double* d_x, long n, double* d_scratch, double* h_sum, void* stream);
 
+/* Memory ceiling of the step's access pattern (measurement helper; no step
+ * arithmetic).  Copies the Q population arrays (Q = 9 for LBM_D2Q9, 19 for
+ * LBM_D3Q19) of an nx x ny x nz grid (nz = 1 in 2D), each of N = nx ny nz
+ * doubles and stored one after another (array i at d_src + i N, x fastest),
+ * from d_src to d_dst: aligned (pull = 0, dst_i(x) = src_i(x)) or as the
+ * streaming pull (pull != 0, dst_i(x) = src_i(x - e_i), all axes periodic).
+ * Both buffers are device memory of Q N doubles owned by the caller and must
+ * not overlap.  Enqueued on stream; returns LBM_EINVAL for a bad lattice,
+ * size or pointer. */
+int lbm_probe_copy(int lattice, int nx, int ny, int nz, const double* d_src, double* d_dst, int pull,
+                   void* stream);
+
 #ifdef __cplusplus
 }
 #endif

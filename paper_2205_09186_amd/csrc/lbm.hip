@@ -1312,4 +1312,26 @@ int lbm_sum(const double* d_x, long n, double* d_scratch, double* h_sum, void* s
     return LBM_OK;
 }
 
+int lbm_probe_copy(int lattice, int nx, int ny, int nz, const double* d_src, double* d_dst, int pull, void* stream)
+{
+    if (!d_src || !d_dst || (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) || nx < 1 || ny < 1 || nz < 1 ||
+        (lattice == LBM_D2Q9 && nz != 1))
+        return fail(nullptr, LBM_EINVAL, "lbm_probe_copy: bad arguments");
+    Grid g{};
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.nxy = (long long)nx * ny;
+    g.N = g.nxy * nz;
+    g.ps = g.N;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const dim3 grid(blocks_for(g.N, 256)), block(256);
+    if (lattice == LBM_D3Q19) {
+        if (pull) hipLaunchKernelGGL((k_probe_copy<1, true>), grid, block, 0, st, d_src, d_dst, g);
+        else hipLaunchKernelGGL((k_probe_copy<1, false>), grid, block, 0, st, d_src, d_dst, g);
+    } else {
+        if (pull) hipLaunchKernelGGL((k_probe_copy<0, true>), grid, block, 0, st, d_src, d_dst, g);
+        else hipLaunchKernelGGL((k_probe_copy<0, false>), grid, block, 0, st, d_src, d_dst, g);
+    }
+    return hip_check(nullptr, hipGetLastError(), "lbm_probe_copy");
+}
+
 }  // extern "C"

@@ -1088,4 +1088,31 @@ __global__ void __launch_bounds__(256) k_compact_x(const double* __restrict__ f,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Memory ceiling of the step's access pattern (a measurement, not a step):
+// Q population arrays of N doubles copied node by node, either aligned
+// (dst_i(x) = src_i(x)) or as the lattice's pull (dst_i(x) = src_i(x - e_i),
+// periodic), with no arithmetic.  The rate it reaches bounds any SoA step
+// that reads and writes every population once.
+// ---------------------------------------------------------------------------
+template <int LAT, bool PULL>
+__global__ void __launch_bounds__(256) k_probe_copy(const double* __restrict__ src, double* __restrict__ dst, Grid g)
+{
+    using L = Lat<LAT>;
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (n >= g.N) return;
+    int x, y, z;
+    coords(n, g, x, y, z);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        long long s = n;
+        if constexpr (PULL) {
+            const int xs = wrapc(x - L::ex(i), g.nx), ys = wrapc(y - L::ey(i), g.ny);
+            const int zs = LAT == 1 ? wrapc(z - L::ez(i), g.nz) : 0;
+            s = (long long)zs * g.nxy + (long long)ys * g.nx + xs;
+        }
+        dst[(long long)i * g.ps + n] = src[(long long)i * g.ps + s];
+    }
+}
+
 }  // namespace lbm

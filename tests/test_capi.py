@@ -109,3 +109,14 @@ def test_coexistence_matches_oracle(orc, Tr):
     assert l == pytest.approx(lo, rel=1e-13)
     with pytest.raises(lbm.LbmError):
         lbm.coexistence(1.2)
+
+
+def test_probe_copy_validates_before_any_launch():
+    """The copy probe rejects a bad lattice, size or pointer with LBM_EINVAL
+    (these checks run before any device work)."""
+    L = lbm.lib()
+    one = C.c_void_p(8)   # never dereferenced: every call below fails validation
+    bad = [(2, 4, 4, 4, one, one), (lbm.D3Q19, 0, 4, 4, one, one), (lbm.D2Q9, 4, 4, 2, one, one),
+           (lbm.D3Q19, 4, 4, 4, None, one), (lbm.D3Q19, 4, 4, 4, one, None)]
+    for lat, nx, ny, nz, s, d in bad:
+        assert L.lbm_probe_copy(lat, nx, ny, nz, s, d, 0, None) == lbm.LBM_EINVAL
