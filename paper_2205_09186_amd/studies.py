@@ -15,7 +15,14 @@
   (``lbm_force``) and its angle deviation from the radial direction (Eq 30) and
   its error against the exact force of that field, as in Figs 5(b)-7.
 
-Run ``python -m paper_2205_09186_amd.studies`` for the tables (JSON on stdout).
+* ``spurious_sweep`` runs the droplet of the benchmark (radius L/4, tanh width
+  10, Tr = 0.7) with every scheme at a small and a large k for a fixed number
+  of steps and reports the spurious current max|v| (Sec 3.3), the mass drift
+  and the rate, or the step at which the run diverged.
+
+Run ``python -m paper_2205_09186_amd.studies`` for the tables (JSON on stdout),
+``python -m paper_2205_09186_amd.studies spurious --lattice D3Q19 --n 256`` for
+the spurious-current sweep.
 """
 from __future__ import annotations
 
@@ -211,7 +218,74 @@ def force_angles(Tr=0.7, n=300, r0=60.0, W=10.0, k=0.16, kappa=0.004,
     return out
 
 
+def spurious_sweep(lattice=lbm.D3Q19, n=256, steps=20000, ks=(0.1, 0.25), Tr=0.7, kappa=0.004,
+                   schemes=("CD2", "CD4", "CD6", "E4", "E6", "E8", "OCFDS4", "CFDS4", "CFDS6", "CFDS8"),
+                   check=1000):
+    """The droplet of the benchmark (R = n/4, W = 10, seeded noise) with each
+    scheme and k for `steps` steps: U = max|v| and mass every `check` steps;
+    a non-finite state or U above the sound speed ends the run (diverged)."""
+    import time
+    import torch
+    from . import inputs
+    shape = (n, n, n) if lattice == lbm.D3Q19 else (n, n)
+    g, l = lbm.coexistence(Tr)
+    rho0 = inputs.droplet(shape, 0.25 * n, 10.0, g, l)
+    out = []
+    for k in ks:
+        for sch in schemes:
+            if sch == "E10" and lattice == lbm.D3Q19:
+                continue
+            p = lbm.Params(lattice=lattice, nx=n, ny=n, nz=(n if lattice == lbm.D3Q19 else 1), Tr=Tr, k=k,
+                           kappa=kappa, scheme=lbm.SCHEMES[sch])
+            sim = lbm.Simulation(p, torch.from_numpy(rho0.reshape(-1)).cuda())
+            if sim.num_variants > 1:
+                sim.tune(steps=3)
+            U0, M0, _ = sim.spurious_max()
+            done, U, M, status, hist = 0, U0, M0, "ran", []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while done < steps:
+                sim.step(min(check, steps - done))
+                done += min(check, steps - done)
+                U, M, _ = sim.spurious_max()
+                hist.append(U)
+                if not math.isfinite(U) or U > CS2 ** 0.5:
+                    status = "diverged"
+                    break
+            wall = time.perf_counter() - t0
+            row = dict(scheme=sch, k=k, kappa=kappa, Tr=Tr, steps=done, status=status, U=U,
+                       mass_rel_drift=abs(M - M0) / M0, mlups=p.n * done / wall / 1e6, U_every_check=hist)
+            print(json.dumps({key: row[key] for key in ("scheme", "k", "kappa", "Tr", "steps", "status", "U",
+                                                        "mass_rel_drift", "mlups")}), file=sys.stderr, flush=True)
+            out.append(row)
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "spurious":
+        import argparse
+        ap = argparse.ArgumentParser()
+        ap.add_argument("cmd")
+        ap.add_argument("--lattice", default="D3Q19", choices=["D2Q9", "D3Q19"])
+        ap.add_argument("--n", type=int, default=256)
+        ap.add_argument("--steps", type=int, default=20000)
+        ap.add_argument("--schemes", default="")
+        ap.add_argument("--ks", default="0.1,0.25")
+        ap.add_argument("--Tr", type=float, default=0.7)
+        ap.add_argument("--kappa", type=float, default=0.004)
+        ap.add_argument("--check", type=int, default=1000)
+        a = ap.parse_args()
+        lat = lbm.D3Q19 if a.lattice == "D3Q19" else lbm.D2Q9
+        kw = dict(lattice=lat, n=a.n, steps=a.steps, ks=tuple(float(x) for x in a.ks.split(",")), Tr=a.Tr,
+                  kappa=a.kappa, check=a.check)
+        if a.schemes:
+            kw["schemes"] = tuple(a.schemes.split(","))
+        json.dump(spurious_sweep(**kw), sys.stdout)
+        print()
+        return
     res = {"derivative_errors_Tr0.6": derivative_errors(), "force_angles_Tr0.7": force_angles()}
     widths = {f"{k:g}": FlatInterface(0.6, k, 0.04).width() for k in (0.1, 0.2, 0.4, 0.8, 1.0)}
     res["width_vs_k_Tr0.6"] = widths
