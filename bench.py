@@ -190,10 +190,12 @@ def main():
     sim.step(args.warmup)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    first = sim.steps_done + 1
     ev0.record(stream)
     sim.step(args.steps)
     ev1.record(stream)
     torch.cuda.synchronize()
+    last = sim.steps_done
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
     mlups = p.n * args.steps / (ms_total * 1e-3) / 1e6
@@ -230,6 +232,9 @@ def main():
         "tuner_ms_per_variant": {str(k): (round(v, 4) if v is not None else None) for k, v in tuned.items()},
         "variant": chosen,
         "spurious_current": U, "mass": M, "status": code,
+        # which steps of the run the timed region covered (the tuner and the
+        # warm-up advance the state first); U and status are taken after them
+        "timed_step_range": [first, last],
     }
     sim.close()
     del sim
