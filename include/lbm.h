@@ -281,7 +281,7 @@ int lbm_sum(const double* d_x, long n, double* d_scratch, double* h_sum, void* s
  * streaming pull (pull != 0, dst_i(x) = src_i(x - e_i), all axes periodic).
  * Both buffers are device memory of Q N doubles owned by the caller and must
  * not overlap.  Enqueued on stream; returns LBM_EINVAL for a bad lattice,
- * size or pointer. */
+ * size (N above 2^38 included) or pointer. */
 int lbm_probe_copy(int lattice, int nx, int ny, int nz, const double* d_src, double* d_dst, int pull,
                    void* stream);
 

@@ -1317,6 +1317,8 @@ int lbm_probe_copy(int lattice, int nx, int ny, int nz, const double* d_src, dou
     if (!d_src || !d_dst || (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) || nx < 1 || ny < 1 || nz < 1 ||
         (lattice == LBM_D2Q9 && nz != 1))
         return fail(nullptr, LBM_EINVAL, "lbm_probe_copy: bad arguments");
+    if ((long long)nx * ny * nz > (1LL << 38))   // keeps the launch's workgroup count within 32 bits
+        return fail(nullptr, LBM_EINVAL, "lbm_probe_copy: grid too large");
     Grid g{};
     g.nx = nx; g.ny = ny; g.nz = nz;
     g.nxy = (long long)nx * ny;

@@ -117,6 +117,6 @@ def test_probe_copy_validates_before_any_launch():
     L = lbm.lib()
     one = C.c_void_p(8)   # never dereferenced: every call below fails validation
     bad = [(2, 4, 4, 4, one, one), (lbm.D3Q19, 0, 4, 4, one, one), (lbm.D2Q9, 4, 4, 2, one, one),
-           (lbm.D3Q19, 4, 4, 4, None, one), (lbm.D3Q19, 4, 4, 4, one, None)]
+           (lbm.D3Q19, 4, 4, 4, None, one), (lbm.D3Q19, 4, 4, 4, one, None), (lbm.D3Q19, 8192, 8192, 8192, one, one)]
     for lat, nx, ny, nz, s, d in bad:
         assert L.lbm_probe_copy(lat, nx, ny, nz, s, d, 0, None) == lbm.LBM_EINVAL
