@@ -1,0 +1,53 @@
+"""The run-level studies on the GPU: the spurious-current sweep (every row
+accounted for, divergence reported, mass conserved in the runs that complete)
+and the run-to-equilibrium helper of the learned-start comparison (its
+convergence rule against the batched kernel's on the same droplet)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_09186_amd import lbm
+    lbm.lib()
+    return lbm
+
+
+def test_spurious_sweep_rows(L):
+    from paper_2205_09186_amd import studies
+    rows = studies.spurious_sweep(lattice=L.D2Q9, n=48, steps=400, ks=(0.16,), Tr=0.8,
+                                  schemes=("CD4", "OCFDS4"), check=100)
+    assert [(r["scheme"], r["k"]) for r in rows] == [("CD4", 0.16), ("OCFDS4", 0.16)]
+    for r in rows:
+        print("case", r["scheme"], r["status"], r["steps"], r["U"], flush=True)
+        assert r["status"] == "ran" and r["steps"] == 400
+        assert len(r["U_every_check"]) == 4 and np.isfinite(r["U"]) and 0 < r["U"] < 0.1
+        assert r["mass_rel_drift"] < 1e-13
+    # a run that goes non-finite is reported at the check that saw it, not carried on
+    bad = studies.spurious_sweep(lattice=L.D2Q9, n=48, steps=3000, ks=(0.1,), Tr=0.6, schemes=("E8",), check=100)
+    assert bad[0]["status"] == "diverged" and bad[0]["steps"] < 3000
+
+
+def test_run_to_equilibrium_matches_batch_rule(L):
+    """The plain-context helper and the batched kernel apply the same rule
+    (U every check_every steps before stepping on; converged at the first
+    t > 0 with |U(t) - U(t - check_every)| < tol), so on the same droplet they
+    stop at the same step with the same U."""
+    from paper_2205_09186_amd import inputs, learned
+    g, l = L.coexistence(0.9)
+    rho0 = inputs.droplet((40, 40), 10, 4.0, g, l)
+    p = L.Params(lattice=L.D2Q9, nx=40, ny=40, Tr=0.9, k=0.16, kappa=0.004, scheme=L.CD4)
+    tol = 1e-6
+    st, steps, U, rl, rg = learned.run_to_equilibrium(p, rho0, max_steps=20000, check_every=50, tol=tol)
+    b = L.Batch([p], [rho0])
+    bst, bsteps, bU = b.run(20000, check_every=50, tol=tol, chunk=20000)
+    print("case run_to_equilibrium", st, steps, U, "batch", bst[0], bsteps[0], bU[0], flush=True)
+    assert st == L.CONVERGED and bst[0] == L.CONVERGED
+    assert steps == bsteps[0]
+    assert abs(U - bU[0]) <= 1e-11
+    assert rl > rg
