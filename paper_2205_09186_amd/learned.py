@@ -337,8 +337,10 @@ def run_to_equilibrium(p: lbm.Params, rho0, max_steps, check_every=100, tol=1e-1
         sim.step(check_every)
         steps += check_every
     if status == lbm.DIVERGED:
+        sim.close()
         return status, steps, U, float("nan"), float("nan")
     r = sim.macros()[0]
+    sim.close()
     c = tuple(s // 2 for s in r.shape)
     return status, steps, U, float(r[c]), float(r[(0,) * r.ndim])
 
