@@ -2,7 +2,9 @@
 
 ``python3 -m paper_2205_09186_amd.profiling run`` performs one plain 1 GiB
 device-to-device copy (the calibration kernel: 1 GiB read, 1 GiB written) and
-then a few steps of the benchmark workload, so one rocprofv3 run covers both.
+then a few steps of the benchmark workload (or, with --probe, a few launches of
+the population copy that measures the access pattern's ceiling), so one
+rocprofv3 run covers both.
 
 ``python3 -m paper_2205_09186_amd.profiling summarize --fetch DIR --write DIR
 --trace DIR`` reads the CSV output of the counter runs (FETCH_SIZE, then
@@ -50,6 +52,22 @@ def run(args):
     lat = lbm.D3Q19 if args.lattice == "D3Q19" else lbm.D2Q9
     n = args.n
     shape = (n, n, n) if lat == lbm.D3Q19 else (n, n)
+    if args.probe:
+        # the population copy that bench.py reports as the ceiling of the
+        # access pattern: aligned, then as the pull, args.steps launches each
+        import ctypes as C
+        nz = n if lat == lbm.D3Q19 else 1
+        q = 19 if lat == lbm.D3Q19 else 9
+        a = torch.rand(q * n * n * nz, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        st = torch.cuda.current_stream()
+        for pull in (0, 1):
+            for _ in range(args.steps):
+                lbm._check(lbm.lib().lbm_probe_copy(lat, n, n, nz, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                                    pull, C.c_void_p(st.cuda_stream)))
+        torch.cuda.synchronize()
+        print(f"profiled the {args.lattice} {n}^{len(shape)} population copy, {args.steps} launches each", flush=True)
+        return
     p = lbm.Params(lattice=lat, nx=n, ny=n, nz=(n if lat == lbm.D3Q19 else 1), Tr=args.Tr, k=args.k,
                    kappa=args.kappa, scheme=lbm.SCHEMES[args.scheme])
     g, l = lbm.coexistence(args.Tr)
@@ -157,6 +175,8 @@ def main():
     r.add_argument("--kappa", type=float, default=0.004)
     r.add_argument("--steps", type=int, default=5)
     r.add_argument("--variant", type=int, default=None, help="launch variant (default: the library's)")
+    r.add_argument("--probe", action="store_true",
+                   help="profile the population copy (lbm_probe_copy) on the grid instead of the step")
     s = sub.add_parser("summarize")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
