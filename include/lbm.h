@@ -102,6 +102,9 @@ size_t lbm_workspace_bytes(const lbm_params* p);
  * Errors: LBM_EINVAL (bad parameters or rho0, or p->wall != 0), LBM_ENOSPC
  * (workspace too small), LBM_EHIP (runtime failure).  On success *out holds
  * the context.  Synchronises the stream before returning. */
+int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device,
+             void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
+
 /* Context with solid nodes: the chemical-potential wetting boundary of the
  * Appendix.  p->wall must be 1 and p->scheme one of CD2, CD4, CD6.
  *   solid     N bytes, nonzero marks a solid node (x fastest, as rho0); read
@@ -118,9 +121,6 @@ size_t lbm_workspace_bytes(const lbm_params* p);
  * variant).  Errors as lbm_init. */
 int lbm_init_wall(const lbm_params* p, const double* rho0, const unsigned char* solid, int on_device,
                   void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
-
-int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device,
-             void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
 
 /* Enqueue nsteps >= 0 time steps on the context's stream and return. */
 int lbm_step(lbm_ctx* c, long nsteps);
