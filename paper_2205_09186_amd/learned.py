@@ -403,6 +403,7 @@ def main():
     ap.add_argument("--eval3d", type=int, default=0,
                     help="also this many 3D (D3Q19) droplets, tanh vs learned start, each run to equilibrium")
     ap.add_argument("--max-steps-3d", type=int, default=60000)
+    ap.add_argument("--tol", type=float, default=1e-10, help="convergence: |U(t) - U(t - 100)| < tol")
     a = ap.parse_args()
     import os
     import torch
@@ -423,12 +424,13 @@ def main():
         hist = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), iters=a.iters, lr=a.lr,
                          batch=a.batch)
         t2 = time.perf_counter()
-    summary, full = evaluate(net, n=a.eval, seed=a.eval_seed, max_steps=a.max_steps) if a.eval > 0 else (None, None)
+    summary, full = (evaluate(net, n=a.eval, seed=a.eval_seed, max_steps=a.max_steps, tol=a.tol) if a.eval > 0
+                     else (None, None))
     if a.dump and full is not None:
         json.dump(full, open(os.path.join(a.dump, "eval_full.json"), "w"))
     summary3d = None
     if a.eval3d > 0:
-        summary3d, rows3d = evaluate_3d(net, n=a.eval3d, seed=a.eval_seed, max_steps=a.max_steps_3d)
+        summary3d, rows3d = evaluate_3d(net, n=a.eval3d, seed=a.eval_seed, max_steps=a.max_steps_3d, tol=a.tol)
         if a.dump:
             json.dump(rows3d, open(os.path.join(a.dump, "eval3d_full.json"), "w"))
     t3 = time.perf_counter()
