@@ -119,3 +119,19 @@ def test_training_reduces_loss(env):
     hist = net.train(Xd, Td, iters=600, batch=2048, lr=3e-3, log_every=100)
     l1 = float(net.grad(Xd, Td)[0].sum().item()) / n
     assert l1 < 0.02 * l0, (l0, l1, hist)
+
+
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 100003, 3 * 2 ** 20 + 7])
+def test_device_sum_is_accurate_and_repeatable(env, n):
+    """lbm_sum (the mass of the learned start's bisection): a fixed-order tree,
+    so two calls give the same bits; against math.fsum of the same doubles it
+    is within the error bound of a pairwise sum of positive terms."""
+    import math
+    torch, lbm, learned, mlp = env
+    rng = np.random.default_rng(n)
+    x = rng.uniform(0.01, 10.0, n)
+    t = torch.from_numpy(x).cuda()
+    a, b = learned.device_sum(t), learned.device_sum(t)
+    assert a == b
+    exact = math.fsum(x)
+    assert abs(a - exact) <= 4 * math.log2(n + 1) * 2.0 ** -53 * exact + 1e-300
