@@ -1128,12 +1128,16 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     b->d_blk_inst = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nblk);
     b->d_partial = reinterpret_cast<double*>(b->ws + off); off = align_up(off + sizeof(double) * B.nblk);
     b->d_lines = reinterpret_cast<BLine*>(b->ws + off);
-    // the grid lines of the compact-scheme instances, rows then columns
+    // the grid lines of the compact-scheme instances, rows then columns; lines
+    // of at most kShortLine points go 64 to an item (one per lane)
     std::vector<BLine> lines;
     for (int i = 0; i < n; ++i) {
         if (!is_compact(ps[i].scheme)) continue;
-        for (int y = 0; y < ps[i].ny; ++y) lines.push_back(BLine{ i, 0, y });
-        for (int x = 0; x < ps[i].nx; ++x) lines.push_back(BLine{ i, 1, x });
+        for (int axis = 0; axis < 2; ++axis) {
+            const int len = axis == 0 ? ps[i].nx : ps[i].ny, count = axis == 0 ? ps[i].ny : ps[i].nx;
+            const int per = len <= kShortLine ? 64 : 1;
+            for (int j = 0; j < count; j += per) lines.push_back(BLine{ i, axis, j, std::min(per, count - j) });
+        }
     }
     b->nlines = (int)lines.size();
     b->nblk_total = (int)blk_inst.size();

@@ -99,9 +99,53 @@ __device__ void b_moments(const BInst& I, const double* S, long long n, int x, i
 
 // One grid line of a compact-scheme instance: along x (axis 0, line = row y)
 // or along y (axis 1, line = column x).
+// A work item of the line stages: cnt = 1 is one line (idx) solved by a
+// wavefront; cnt > 1 is the cnt consecutive lines idx .. idx + cnt - 1 (cnt <=
+// 64) of at most kShortLine points, one per lane.
 struct BLine {
-    int inst, axis, idx;
+    int inst, axis, idx, cnt;
 };
+constexpr int kShortLine = 16;
+
+// Compact derivative (Eq 21) of one short periodic line (4 <= n <= kShortLine)
+// by one thread: both recursions from a zero start, each closed around the
+// line exactly (the value entering the line is the local end / (1 - z^n)).
+template <class Load>
+__device__ void thread_line(const BInst& I, Load&& ld, double* __restrict__ out, long long base, long long sa, int n)
+{
+    const double ha = 0.5 * I.cc.ca, hb = 0.25 * I.cc.cb, hc = I.cc.cc / 6.0, z = I.z;
+    double r[kShortLine + 6];
+#pragma unroll
+    for (int k = 0; k < kShortLine + 6; ++k) {
+        int idx = k - 3;                    // in [-3, n + 2]; n >= 4
+        idx += idx < 0 ? n : 0;
+        idx -= idx >= n ? n : 0;
+        r[k] = k < n + 6 ? ld(base + idx * sa) : 0.0;
+    }
+    double acc = 0.0, pz = 1.0;
+#pragma unroll
+    for (int i = 0; i < kShortLine; ++i) {
+        if (i < n) {
+            acc = ha * (r[i + 4] - r[i + 2]) + hb * (r[i + 5] - r[i + 1]) + hc * (r[i + 6] - r[i]) + z * acc;
+            r[i] = acc;
+            pz *= z;
+        }
+    }
+    const double T = acc / (1.0 - pz);
+    double q = z;
+#pragma unroll
+    for (int i = 0; i < kShortLine; ++i)
+        if (i < n) { r[i] += q * T; q *= z; }
+    acc = 0.0;
+#pragma unroll
+    for (int i = kShortLine - 1; i >= 0; --i)
+        if (i < n) { acc = r[i] + z * acc; r[i] = acc; }
+    const double U = acc / (1.0 - pz);
+    q = z;
+#pragma unroll
+    for (int i = kShortLine - 1; i >= 0; --i)
+        if (i < n) { out[base + i * sa] = I.zscale * (r[i] + q * U); q *= z; }
+}
 
 // Compact derivative (Eq 21) along one periodic line of instance I of the
 // field that ld(o) reads, into out, by one wavefront (wave_line).
@@ -173,18 +217,34 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
                 if (a.st[ln.inst].status != B_RUNNING) continue;
                 const BInst& I = a.inst[ln.inst];
                 const long long N = I.g.N;
-                const long long base = ln.axis == 0 ? (long long)ln.idx * I.g.nx : ln.idx;
                 const long long sa = ln.axis == 0 ? 1 : I.g.nx;
                 const int n = ln.axis == 0 ? I.g.nx : I.g.ny;
-                if (stage == 0) {
+                // the line of this wavefront, or of this lane for a packed item
+                const int li = ln.idx + (ln.cnt > 1 ? lane : 0);
+                const long long base = ln.axis == 0 ? (long long)li * I.g.nx : li;
+                const double* rho = I.rho;
+                const double* lap = I.lap;
+                auto mu_at = [&](long long o) {
+                    return mu_bulk(rho[o], I.eos) - I.eos.kappa * (lap[o] + lap[N + o]);
+                };
+                if (ln.cnt > 1) {
+                    if (lane < ln.cnt) {
+                        if (stage == 0) {
+                            double* g1 = I.grho + ln.axis * N;
+                            thread_line(I, [&](long long o) { return rho[o]; }, g1, base, sa, n);
+                            __threadfence_block();   // the stores above before the loads below
+                            thread_line(I, [&](long long o) { return g1[o]; }, I.lap + ln.axis * N, base, sa, n);
+                        } else {
+                            thread_line(I, mu_at, I.gmu + ln.axis * N, base, sa, n);
+                        }
+                    }
+                } else if (stage == 0) {
                     double* g1 = I.grho + ln.axis * N;
-                    b_line(I, [&](long long o) { return I.rho[o]; }, g1, base, sa, n, lane);
+                    b_line(I, [&](long long o) { return rho[o]; }, g1, base, sa, n, lane);
                     __threadfence_block();   // this wavefront's stores before its loads
                     b_line(I, [&](long long o) { return g1[o]; }, I.lap + ln.axis * N, base, sa, n, lane);
                 } else {
-                    b_line(I, [&](long long o) {
-                        return mu_bulk(I.rho[o], I.eos) - I.eos.kappa * (I.lap[o] + I.lap[N + o]);
-                    }, I.gmu + ln.axis * N, base, sa, n, lane);
+                    b_line(I, mu_at, I.gmu + ln.axis * N, base, sa, n, lane);
                 }
             }
         };
