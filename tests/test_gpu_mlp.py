@@ -135,3 +135,26 @@ def test_device_sum_is_accurate_and_repeatable(env, n):
     assert a == b
     exact = math.fsum(x)
     assert abs(a - exact) <= 4 * math.log2(n + 1) * 2.0 ** -53 * exact + 1e-300
+
+
+def test_shipped_network_gives_a_droplet_profile(env):
+    """The trained parameters shipped with the package: on a 2D droplet at
+    T_r = 0.8 the field is liquid at the centre and gas far away, monotone
+    along a ray, with its mid density within a node and a half of R."""
+    import os
+    torch, lbm, learned, mlp = env
+    path = os.path.join(os.path.dirname(learned.__file__), "learned_net.npy")
+    net = learned.Net(0)
+    net.load(np.load(path))
+    assert net.state().shape == (8705,)
+    g, l = lbm.coexistence(0.8)
+    p = lbm.Params(lattice=lbm.D2Q9, nx=96, ny=96, Tr=0.8, k=0.16, kappa=0.004, scheme=lbm.CD6)
+    R = 24.0
+    rho = net.field(p, R, 0.8, 0.16, lbm.CD6, g, l).cpu().numpy().reshape(96, 96)
+    ray = rho[48, 48:]
+    assert abs(ray[0] - l) < 0.05 * l and abs(ray[-1] - g) < 0.1 * (l - g)
+    assert np.all(np.diff(ray) <= 1e-9 * l)
+    mid = 0.5 * (l + g)
+    j = int(np.nonzero(ray < mid)[0][0])
+    r_mid = (j - 1) + (ray[j - 1] - mid) / (ray[j - 1] - ray[j])
+    assert abs(r_mid - R) < 1.5, r_mid
