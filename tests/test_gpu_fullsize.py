@@ -1,7 +1,7 @@
 """Parity at the benchmark's full sizes, in the launch designs the tuner picks
 from (the fused 2D collide, the 3D ring collide, the ring-free tile collide):
-D3Q19 256^3 and D2Q9 1024^2 droplets (radius L/4, Tr = 0.7, tanh width 10)
-against the oracle on every node after a few steps, and mass conservation
+D3Q19 256^3 and 384^3 and D2Q9 1024^2 droplets (radius L/4, Tr = 0.7, tanh
+width 10) against the oracle on every node after a few steps, and mass conservation
 over a longer run (a property at any size)."""
 import numpy as np
 import pytest
@@ -48,7 +48,7 @@ def _design_variants(L, sim, lat, scheme):
 
 
 @pytest.mark.parametrize("lat,n,scheme,steps", [(1, 256, "CD6", 3), (1, 256, "OCFDS4", 2), (0, 1024, "CD6", 20),
-                                                (0, 1024, "OCFDS4", 10)])
+                                                (0, 1024, "OCFDS4", 10), (1, 384, "CD6", 2)])
 def test_full_size_against_oracle(L, orc, lat, n, scheme, steps):
     import torch
     shape, rho0, kw = _workload(orc, lat, n, L.SCHEMES[scheme])
