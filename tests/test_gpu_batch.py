@@ -106,3 +106,31 @@ def test_batch_retire_inside_a_launch(L):
         s.step(70)
         assert b.instance(i).steps_done == 70
         assert np.abs(b.instance(i).populations() - s.populations()).max() < 1e-11
+
+
+def test_config3_set_matches_plain_runs(L):
+    """The full config-3 set (48 slabs, 48 droplets, six schemes, T_r 0.2-0.95)
+    for 2000 steps in one batch: every instance still running equals its plain
+    run to 1e-11 in the populations; every instance the batch retired as
+    diverged is non-finite in its plain run too."""
+    from paper_2205_09186_amd import sweep
+    descs, params, rhos = sweep.build()
+    b = L.Batch(params, rhos)
+    st, steps, _ = b.run(2000, check_every=100, tol=0.0, chunk=1000)
+    n_run = n_div = 0
+    for i, (p, r) in enumerate(zip(params, rhos)):
+        s = L.Simulation(p, r)
+        if st[i] == L.RUNNING:
+            s.step(2000)
+            d = np.abs(b.instance(i).populations() - s.populations()).max()
+            assert steps[i] == 2000 and d < 1e-11, (i, d)
+            n_run += 1
+        else:
+            assert st[i] == L.DIVERGED, (i, st[i])
+            s.step(int(steps[i]))
+            U, _, _ = s.spurious_max()
+            assert not (np.isfinite(U) and U <= 3 ** -0.5), (i, U)
+            n_div += 1
+        s.close()
+    print("case config-3 set: running", n_run, "diverged", n_div, flush=True)
+    assert n_run >= 40
