@@ -69,6 +69,16 @@ def test_droplet_100x100_2000_steps(L, orc, scheme, Tr):
     print("max diffs", d)
 
 
+# The same 2000-step bar in 3D: a 64^3 droplet (R = 16, tanh width 10, Tr =
+# 0.8, k = 0.16), where the 3D runs are stable (narrow starts and small
+# droplets diverge on both sides in 3D).
+@pytest.mark.parametrize("scheme", ["CD6", "OCFDS4"])
+def test_droplet_64cubed_2000_steps(L, orc, scheme):
+    sim, o = _run_pair(L, orc, L.D3Q19, (64, 64, 64), L.SCHEMES[scheme], 2000, Tr=0.8, W=10.0)
+    d = _compare(sim, o)
+    print("max diffs", d)
+
+
 def test_droplet_100x100_cd2_tr08_diverges_on_both_sides(L, orc):
     """CD2 at Tr = 0.8 (that workload as specified) blows up within a few hundred
     steps in the oracle; the GPU reports the same as a non-finite state."""
