@@ -94,3 +94,41 @@ def test_full_size_mass_conservation(L, orc, lat, n):
     assert code == 0 and np.isfinite(U)
     assert abs(M - M0) <= 1e-13 * M0
     sim.close()
+
+
+def test_full_size_wall_against_oracle(L, orc):
+    """The benchmark's wetting-boundary workload: D3Q19 256^3, an 8-plane solid
+    floor under the droplet, mu_wall the Maxwell gas value k^2 psi'(rho_g),
+    every tile variant against the oracle on every node after 2 steps."""
+    import torch
+    n, steps, k, Tr = 256, 2, 0.1, 0.7
+    shape, rho0, kw = _workload(orc, 1, n, L.CD6)
+    solid = np.zeros(shape, np.uint8)
+    solid[:8] = 1
+    g, _ = orc.maxwell(Tr)
+    Tc, _, _ = orc.pr_critical()
+    mu_wall = k * k * orc.pr_mub(g, Tr * Tc, orc.PR_A * orc.pr_alpha(Tr), orc.PR_B, orc.PR_R)
+    print(f"case full size wall n={n} steps={steps}", flush=True)
+    o = orc.Sim(orc.Params(solid=solid, mu_wall=mu_wall, **kw), rho0)
+    o.step(steps)
+    ro, vxo, vyo, vzo = o.macros()
+    Uo, Mo = o.observables()
+    del o
+    d_rho0 = torch.from_numpy(rho0.reshape(-1)).cuda()
+    probe = L.Simulation(L.Params(wall=1, mu_wall=mu_wall, **kw), d_rho0, solid=solid)
+    nv = probe.num_variants
+    probe.close()
+    del probe
+    assert nv == 2
+    for v in range(nv):
+        print(f"  variant {v}", flush=True)
+        sim = L.Simulation(L.Params(wall=1, mu_wall=mu_wall, **kw), d_rho0, solid=solid)
+        sim.set_variant(v)
+        sim.step(steps)
+        r, vx, vy, vz = sim.macros()
+        d = max(np.abs(r - ro).max(), np.abs(vx - vxo).max(), np.abs(vy - vyo).max(), np.abs(vz - vzo).max())
+        assert d <= TOL, (v, d)
+        assert np.all(r[solid.astype(bool)] == 0.0)
+        U, M, code = sim.spurious_max()
+        assert code == 0 and U == pytest.approx(Uo, abs=TOL) and M == pytest.approx(Mo, rel=1e-13)
+        sim.close()
