@@ -1,5 +1,8 @@
 """Pins of the oracle's lattice kinetics (Sec 2.1), thermodynamics (Sec 2.2) and
 full step against identities and closed forms the paper and mathematics fix."""
+import math
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 from scipy import integrate
@@ -138,6 +141,71 @@ def test_maxwell_two_formulations(orc, Tr):
     assert orc.pr_mub(g1, T, aa) == pytest.approx(orc.pr_mub(l1, T, aa), rel=1e-12)
 
 
+def _golden_maxwell():
+    """(critical point dict, rows (Tr, rho_g, rho_l) as strings) of tests/golden/maxwell_pr.txt."""
+    import os
+    crit, rows = {}, []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "maxwell_pr.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].split()
+            if len(line) == 2:
+                crit[line[0]] = line[1]
+            elif len(line) == 3:
+                rows.append(tuple(line))
+    return crit, rows
+
+
+def _digits_tol(s: str) -> float:
+    """Half a unit in the last significant digit of a printed number, or 1e-9
+    relative when more than nine significant digits are printed."""
+    mant = s.lower().split("e")[0].replace("-", "").replace(".", "").lstrip("0")
+    v = abs(float(s))
+    sig = len(mant)
+    if sig > 9:
+        return 1e-9 * v
+    return 0.51 * 10.0 ** (math.floor(math.log10(v)) - sig + 1)
+
+
+def test_critical_point_against_independent_values(orc):
+    crit, _ = _golden_maxwell()
+    Tc, rc, pc = orc.pr_critical()
+    for name, val in (("Tc", Tc), ("rho_c", rc), ("p_c", pc)):
+        assert abs(val - float(crit[name])) <= _digits_tol(crit[name]), (name, val, crit[name])
+
+
+def test_maxwell_against_independent_table(orc):
+    """Coexistence densities from T_r = 0.95 down to 0.2 against an independent
+    computation from the paper's formulas.  Both of the oracle's Maxwell
+    formulations share p0 and alpha(T), so this is what pins alpha(T)'s
+    acentric polynomial (a slip in it shifts every row by far more than the
+    tolerance)."""
+    _, rows = _golden_maxwell()
+    assert len(rows) == 10
+    for Tr, g_s, l_s in rows:
+        for method in ("mu", "area"):
+            g, l = orc.maxwell(float(Tr), method)
+            assert abs(g - float(g_s)) <= _digits_tol(g_s), (Tr, method, g, g_s)
+            assert abs(l - float(l_s)) <= _digits_tol(l_s), (Tr, method, l, l_s)
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.2, 0.344, 0.5])
+def test_acentric_factor_definition(orc, omega):
+    """Pitzer's definition of the acentric factor, omega = -1 - log10(p_sat/p_c)
+    at T_r = 0.7, is what the temperature function alpha(T) of the
+    Peng-Robinson EOS (Sec 2.2) is fitted to reproduce: with the oracle's alpha
+    the EOS's own saturation pressure gives back the omega it was given, to the
+    few thousandths the correlation achieves."""
+    Tc, _, pc = orc.pr_critical()
+    g, _ = orc.maxwell(0.7, omega=omega)
+    aa = orc.PR_A * orc.pr_alpha(0.7, omega)
+    psat = orc.pr_p0(g, 0.7 * Tc, aa)
+    assert -1.0 - math.log10(psat / pc) == pytest.approx(omega, abs=5e-3)
+    # alpha(Tc) = 1 for any omega, and alpha falls with temperature
+    assert orc.pr_alpha(1.0, omega) == 1.0
+    if omega > 0:
+        assert orc.pr_alpha(0.5, omega) > orc.pr_alpha(0.7, omega) > 1.0
+
+
 def test_maxwell_density_ratio_trend(orc):
     """Sec 3.3: the density ratio grows as the temperature falls; Sec 4 quotes
     ratios up to ~1000 for the droplet runs (T_r = 0.6 is near 850)."""
@@ -223,7 +291,157 @@ def test_spurious_currents_stay_below_sound_speed(orc):
     assert 0 < u < 0.05
 
 
-def _slab_equilibrium(orc, scheme, Tr, steps=24000, H=160):
+# --------------------------------------------------------------------------- #
+# The force that the step applies (Eq 12, Eq 16), read back from one step      #
+# --------------------------------------------------------------------------- #
+# Fourier symbols of the schemes on exp(i q x): the gradient multiplies by
+# i*lam1(q) (Eq 28), the Laplacian by -lam2(q): the matched-order central
+# second difference for the explicit schemes, lam1^2 for the compact ones,
+# whose Laplacian is D(D).
+_CD1 = {"CD2": (1.0, 0.0, 0.0), "CD6": (1.5, -0.6, 0.1)}
+_CD2ND = {"CD2": (-2.0, 1.0), "CD6": (-490 / 180, 270 / 180, -27 / 180, 2 / 180)}
+
+
+def _symbols(orc, name, q):
+    if name in _CD1:
+        a, b, c = _CD1[name]
+        lam1 = a * np.sin(q) + b / 2 * np.sin(2 * q) + c / 3 * np.sin(3 * q)
+        cs = _CD2ND[name]
+        lam2 = -(cs[0] + sum(2 * cs[k] * np.cos(k * q) for k in range(1, len(cs))))
+        return lam1, lam2
+    al, a, b, c = orc.compact_coeffs(orc.SCHEME_NAMES[name])
+    lam1 = (a * np.sin(q) + b / 2 * np.sin(2 * q) + c / 3 * np.sin(3 * q)) / (1 + 2 * al * np.cos(q))
+    return lam1, lam1 ** 2
+
+
+def _step_force(orc, lat, shape, scheme, rho0, k, kappa, tau):
+    """Force applied by one oracle step from rest, read from the populations:
+    the post-collision values at x are the post-streaming values at x + e_i,
+    and their momentum is rho u + F = F (Eq 1, 6, 8: the EDM adds
+    feq(rho, u + F/rho) - feq(rho, u), whose momentum is F)."""
+    nz, ny, nx = shape
+    p = orc.Params(lattice=lat, nx=nx, ny=ny, nz=nz, tau=tau, Tr=0.7, k=k, kappa=kappa,
+                   scheme=orc.SCHEME_NAMES[scheme])
+    s = orc.Sim(p, rho0)
+    s.step(1)
+    e, _ = orc.lattice(lat)
+    f = s.populations().reshape((len(e),) + shape)
+    mom = np.zeros((3,) + shape)
+    rho = np.zeros(shape)
+    for i, (ex, ey, ez) in enumerate(e):
+        fs = np.roll(f[i], (-ez, -ey, -ex), axis=(0, 1, 2))
+        rho += fs
+        mom += np.array([ex, ey, ez])[:, None, None, None] * fs
+    return rho, mom
+
+
+@pytest.mark.parametrize("lat,scheme,axis,m", [(0, "CD2", 1, 1), (0, "CD6", 1, 3), (0, "OCFDS4", 1, 2),
+                                               (1, "CD6", 0, 1), (1, "OCFDS4", 2, 3)])
+def test_step_force_follows_eq12_and_eq16(orc, lat, scheme, axis, m):
+    """On rho = A + B cos(q s) along one axis s, the force of one step is
+    F_s = k^2 P(s) + kappa_hat K(s) + C(s) with
+      K = rho B lam1 lam2 sin(q s)      (from -rho grad(-kappa_hat lap rho)),
+      C = -cs^2 B lam1 sin(q s)         (from cs^2 grad rho),
+    and P = -rho grad(psi'(rho)) independent of k and kappa_hat (Eq 12, 16).
+    Three values of k and two of kappa_hat separate the parts: the k^2
+    dependence (a k in place of k^2 fails the third k), the size and sign of
+    the kappa_hat and cs^2 parts against the closed forms, and the density is
+    unchanged by the collision."""
+    shape = (1, 16, 4) if lat == 0 else (12, 6, 6)
+    if lat == 0:
+        axis_len, ax = shape[1], 1          # y of a (1, ny, nx) array
+    else:
+        axis_len, ax = shape[2 - axis], 2 - axis
+    q = 2 * np.pi * m / axis_len
+    s = np.arange(axis_len)
+    A, B = 3.0, 1.0
+    prof = A + B * np.cos(q * s)
+    bshape = [1, 1, 1]
+    bshape[ax] = axis_len
+    rho0 = np.broadcast_to(prof.reshape(bshape), shape).copy()
+    comp = 1 if lat == 0 else axis           # force component along s
+    ks, kap = (0.1, 0.2, 0.35), (0.004, 0.02)
+    F = {}
+    for k, kp in [(ks[0], kap[0]), (ks[1], kap[0]), (ks[2], kap[0]), (ks[0], kap[1])]:
+        rho, mom = _step_force(orc, lat, shape, scheme, rho0, k, kp, tau=0.8)
+        np.testing.assert_allclose(rho, rho0, rtol=0, atol=1e-14)
+        # no force across the wave
+        for d in range(3):
+            if d != comp:
+                assert np.abs(mom[d]).max() < 1e-15
+        F[(k, kp)] = mom[comp]
+    P = (F[(ks[1], kap[0])] - F[(ks[0], kap[0])]) / (ks[1] ** 2 - ks[0] ** 2)
+    scale = np.abs(F[(ks[2], kap[0])]).max()
+    np.testing.assert_allclose(F[(ks[2], kap[0])], F[(ks[0], kap[0])] + (ks[2] ** 2 - ks[0] ** 2) * P,
+                               rtol=0, atol=1e-12 * scale)
+    lam1, lam2 = _symbols(orc, scheme, q)
+    sin = np.broadcast_to(np.sin(q * s).reshape(bshape), shape)
+    K = (F[(ks[0], kap[1])] - F[(ks[0], kap[0])]) / (kap[1] - kap[0])
+    K_exact = rho0 * B * lam1 * lam2 * sin
+    np.testing.assert_allclose(K, K_exact, rtol=0, atol=1e-9 * np.abs(K_exact).max())
+    C = F[(ks[0], kap[0])] - ks[0] ** 2 * P - kap[0] * K
+    C_exact = -B * lam1 * sin / 3.0
+    np.testing.assert_allclose(C, C_exact, rtol=0, atol=1e-11 * np.abs(C_exact).max())
+    # the EOS part pulls towards the dense phase: P has the sign of -rho' psi''
+    assert np.abs(P).max() > 0
+
+
+# --------------------------------------------------------------------------- #
+# Flat interface against the Maxwell construction (Sec 3.4, Fig 13)             #
+# --------------------------------------------------------------------------- #
+# The paper's flat-interface run: a layer of liquid across the middle of a
+# periodic column of height 400, tau = 0.8, k = 0.1, 150,000 steps.  kappa_hat
+# is not printed; 0.004 is the reading used throughout.  The column is one node
+# wide: the state depends on the height only.
+_SLAB_H, _SLAB_STEPS = 400, 150000
+_SLAB_CASES = [(s, t) for s in ("CD6", "OCFDS4") for t in (0.9, 0.8, 0.7, 0.6)]
+
+
+def _slab_run(args):
+    import oracle as orc
+    scheme, Tr, H, steps, tau = args
+    orc.set_threads(1)          # this worker thread's own OpenMP setting
+    g, l = orc.maxwell(Tr)
+    p = orc.Params(nx=1, ny=H, tau=tau, Tr=Tr, k=0.1, kappa=0.004, scheme=orc.SCHEME_NAMES[scheme])
+    s = orc.Sim(p, inputs.slab((H, 1), 0, 10.0, g, l, amplitude=0.0))
+    s.step(steps)
+    r, vx, vy, _ = s.macros()
+    return (r[H // 2, 0] - l) / l, (r[0, 0] - g) / g, np.abs(vy).max()
+
+
+@pytest.fixture(scope="module")
+def paper_slabs(orc):
+    """The eight flat-interface runs, each on one thread, run side by side."""
+    with ThreadPoolExecutor(max_workers=len(_SLAB_CASES)) as ex:
+        res = list(ex.map(_slab_run, [(s, t, _SLAB_H, _SLAB_STEPS, 0.8) for s, t in _SLAB_CASES]))
+    return dict(zip(_SLAB_CASES, res))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("scheme", ["CD6", "OCFDS4"])
+@pytest.mark.parametrize("Tr", [0.9, 0.8, 0.7])
+def test_flat_interface_coexistence_vs_maxwell(paper_slabs, scheme, Tr):
+    """Sec 3.4 / Fig 13: at the paper's flat-interface geometry both coexistence
+    densities agree with the Maxwell construction: the liquid to 1e-3, the gas
+    to 1e-2 (measured: liquid within 5e-4, gas within 0.06-0.5 %)."""
+    el, eg, U = paper_slabs[(scheme, Tr)]
+    assert U < 1e-4
+    assert abs(el) < 1e-3
+    assert abs(eg) < 1e-2
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("scheme,bound", [("CD6", 0.03), ("OCFDS4", 0.06)])
+def test_flat_interface_gas_offset_at_tr06(paper_slabs, scheme, bound):
+    """At T_r = 0.6 (density ratio ~850) the liquid still agrees to 1e-3 and
+    the gas density lies a few per cent above Maxwell, further for OCFDS4 than
+    for CD6 (measured +1.6 % and +4.1 %): recorded, not claimed as agreement."""
+    el, eg, U = paper_slabs[(scheme, 0.6)]
+    assert abs(el) < 1e-3
+    assert 0.0 < eg < bound
+
+
+def _slab_short(orc, scheme, Tr, steps=24000, H=160):
     g, l = orc.maxwell(Tr)
     p = orc.Params(nx=1, ny=H, Tr=Tr, k=0.1, kappa=0.004, scheme=orc.SCHEME_NAMES[scheme])
     s = orc.Sim(p, inputs.slab((H, 1), 0, 10.0, g, l, amplitude=0.0))
@@ -232,22 +450,9 @@ def _slab_equilibrium(orc, scheme, Tr, steps=24000, H=160):
     return (r[H // 2, 0] - l) / l, (r[0, 0] - g) / g, np.abs(vy).max()
 
 
-@pytest.mark.parametrize("scheme,Tr", [("CD4", 0.7), ("CD6", 0.8), ("OCFDS4", 0.8)])
-def test_flat_interface_liquid_density_vs_maxwell(orc, scheme, Tr):
-    """Sec 3.4 / Fig 13: a flat liquid layer relaxes to a liquid density within
-    1e-3 of the Maxwell construction with the accurate schemes.  Under the SRT
-    reading the gas density settles 15-25 % above the Maxwell value for every
-    scheme (an inconsistency of the forcing, not of the stencil order): that
-    part is recorded, with a loose bound, not claimed as agreement."""
-    el, eg, U = _slab_equilibrium(orc, scheme, Tr)
-    assert U < 2e-5
-    assert abs(el) < 1e-3
-    assert 0.0 < eg < 0.3
-
-
 def test_flat_interface_isotropic_deviates_more(orc):
     """Sec 3.4: the coexistence densities of E4 deviate from the Maxwell curve
-    more than those of the fourth-order schemes."""
-    el4, eg4, _ = _slab_equilibrium(orc, "E4", 0.9)
-    elc, egc, _ = _slab_equilibrium(orc, "CD4", 0.9)
+    more than those of the fourth-order schemes (a trend; a shorter column)."""
+    el4, eg4, _ = _slab_short(orc, "E4", 0.9)
+    elc, egc, _ = _slab_short(orc, "CD4", 0.9)
     assert abs(el4) > 5 * abs(elc)
