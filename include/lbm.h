@@ -273,6 +273,21 @@ int mlp_field(const float* d_params, const float* norm7, const lbm_params* p, do
 size_t lbm_sum_scratch_bytes(long n);
 int lbm_sum(const double* d_x, long n, double* d_scratch, double* h_sum, void* stream);
 
+/* lbm_sum for callers that cannot allocate device memory (code that must not
+ * call hipMalloc: tight serving loops, harnesses that forbid allocation).  The
+ * same kernels and summation order as lbm_sum, hence the same result bit for
+ * bit, but the scratch is a fixed array inside the library: 4 MiB per device,
+ * held until the process ends; nothing is allocated or freed.
+ *   d_x       n device doubles, 1 <= n <= lbm_sum_static_max() (2^26);
+ *             larger n returns LBM_EINVAL with a message, before any launch.
+ *   h_sum     host result.  Synchronises the stream (the device of the stream,
+ *             or the current device for the NULL stream, holds the scratch).
+ * Every call on one device shares that device's scratch: calls that overlap on
+ * one device (other streams, other threads) race and must be serialised by the
+ * caller. */
+size_t lbm_sum_static_max(void);
+int lbm_sum_static(const double* d_x, long n, double* h_sum, void* stream);
+
 /* Memory ceiling of the step's access pattern (measurement helper; no step
  * arithmetic).  Copies the Q population arrays (Q = 9 for LBM_D2Q9, 19 for
  * LBM_D3Q19) of an nx x ny x nz grid (nz = 1 in 2D), each of N = nx ny nz

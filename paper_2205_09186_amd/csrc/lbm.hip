@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -534,6 +535,54 @@ void set_lines(lbm_ctx* c)
     } else {
         c->z = 0.0; c->zscale = 1.0;
     }
+}
+
+}  // namespace
+
+// Static scratch of lbm_sum_static: 2 doubles per 256-value workgroup plus the
+// two results, for at most kStaticSumMaxN values (4 MiB per device, held until
+// the process ends).  Host code never uses this name as an address: each
+// device's copy is reached through the pointer static_sum_scratch() takes from
+// hipGetSymbolAddress with that device current.
+constexpr long long kStaticSumMaxN = 1LL << 26;
+constexpr long long kStaticSumDoubles = 2 * (kStaticSumMaxN / 256) + 2;
+static __device__ __align__(256) double scratch[kStaticSumDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device of stream st (the current device
+// for the null stream), looked up once per device with that device current.
+int static_sum_scratch(hipStream_t st, double** out)
+{
+    int cur = 0, dev = 0;
+    int r = hip_check(nullptr, hipGetDevice(&cur), "hipGetDevice");
+    if (r) return r;
+    dev = cur;
+    if (st) {
+        r = hip_check(nullptr, hipStreamGetDevice(st, &dev), "hipStreamGetDevice");
+        if (r) return r;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, LBM_EINVAL, "lbm_sum_static: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        if (dev != cur) {
+            r = hip_check(nullptr, hipSetDevice(dev), "hipSetDevice");
+            if (r) return r;
+        }
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) (void)hipSetDevice(cur);
+        r = hip_check(nullptr, e, "hipGetSymbolAddress(scratch)");
+        if (r) return r;
+        if (!p) return fail(nullptr, LBM_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
 }
 
 }  // namespace
@@ -1309,6 +1358,36 @@ int lbm_sum(const double* d_x, long n, double* d_scratch, double* h_sum, void* s
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, st, d_scratch, nb, d_scratch + 2 * nb);
     double h[2];
     int r = hip_check(nullptr, hipMemcpyAsync(h, d_scratch + 2 * nb, sizeof(h), hipMemcpyDeviceToHost, st), "sum copy");
+    if (r) return r;
+    r = hip_check(nullptr, hipStreamSynchronize(st), "sum sync");
+    if (r) return r;
+    *h_sum = h[1];
+    return LBM_OK;
+}
+
+// lbm_sum_static: the deterministic sum with its scratch (the per-workgroup
+// partials of k_sum_partials and the two results of k_reduce_final) in a
+// fixed device array, for callers that cannot allocate.
+size_t lbm_sum_static_max(void) { return (size_t)kStaticSumMaxN; }
+
+int lbm_sum_static(const double* d_x, long n, double* h_sum, void* stream)
+{
+    if (!d_x || !h_sum || n < 1) return fail(nullptr, LBM_EINVAL, "lbm_sum_static: bad arguments");
+    if ((long long)n > kStaticSumMaxN)
+        return fail(nullptr, LBM_EINVAL, "lbm_sum_static: n = " + std::to_string(n) + " exceeds the maximum " +
+                                             std::to_string(kStaticSumMaxN) + " of the static scratch");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    double* ws = nullptr;
+    int r = static_sum_scratch(st, &ws);
+    if (r) return r;
+    const long long nb = (n + 255) / 256;
+    // every partial the final reduction reads is written first: nothing needs clearing
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)nb), dim3(256), 0, st, d_x, (long long)n, ws);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, st, ws, nb, ws + 2 * nb);
+    r = hip_check(nullptr, hipGetLastError(), "lbm_sum_static launch");
+    if (r) return r;
+    double h[2];
+    r = hip_check(nullptr, hipMemcpyAsync(h, ws + 2 * nb, sizeof(h), hipMemcpyDeviceToHost, st), "sum copy");
     if (r) return r;
     r = hip_check(nullptr, hipStreamSynchronize(st), "sum sync");
     if (r) return r;

@@ -80,6 +80,8 @@ SYMBOLS = {
                             C.POINTER(C.c_float), C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
     "lbm_sum_scratch_bytes": (C.c_size_t, [C.c_long]),
     "lbm_sum": (C.c_int, [C.c_void_p, C.c_long, C.c_void_p, _D, C.c_void_p]),
+    "lbm_sum_static_max": (C.c_size_t, []),
+    "lbm_sum_static": (C.c_int, [C.c_void_p, C.c_long, _D, C.c_void_p]),
     "lbm_probe_copy": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "lbm_coexistence": (C.c_int, [_P, _D, _D]),
     "lbm_eos": (C.c_int, [_P, C.c_void_p, C.c_long, C.c_void_p, C.c_void_p]),

@@ -120,3 +120,19 @@ def test_probe_copy_validates_before_any_launch():
            (lbm.D3Q19, 4, 4, 4, None, one), (lbm.D3Q19, 4, 4, 4, one, None), (lbm.D3Q19, 8192, 8192, 8192, one, one)]
     for lat, nx, ny, nz, s, d in bad:
         assert L.lbm_probe_copy(lat, nx, ny, nz, s, d, 0, None) == lbm.LBM_EINVAL
+
+
+def test_static_sum_rejects_bad_arguments_without_gpu():
+    """lbm_sum_static refuses a size beyond its fixed scratch, an empty input
+    and NULL pointers before it touches a device."""
+    L = lbm.lib()
+    nmax = L.lbm_sum_static_max()
+    assert nmax == 1 << 26
+    out = C.c_double(-1.0)
+    fake = C.c_void_p(4096)   # never dereferenced: every case fails validation first
+    assert L.lbm_sum_static(fake, nmax + 1, C.byref(out), None) == lbm.LBM_EINVAL
+    assert "exceeds the maximum" in L.lbm_last_error(None).decode()
+    assert L.lbm_sum_static(fake, 0, C.byref(out), None) == lbm.LBM_EINVAL
+    assert L.lbm_sum_static(None, 10, C.byref(out), None) == lbm.LBM_EINVAL
+    assert L.lbm_sum_static(fake, 10, None, None) == lbm.LBM_EINVAL
+    assert out.value == -1.0
