@@ -63,6 +63,8 @@ def kernel_bytes_per_node(kname: str, Q: int, dim: int, scheme: str) -> int:
                 derivative fields (compact schemes), writes Q
       k_mu_march     reads rho, writes mu_hat
       k_force_march  reads rho and mu_hat, writes dim force components
+      k_mf           reads rho, writes dim force components (mu_hat stays
+                     on chip)
     The whole step's figure is (2Q + 2) * 8: populations read and written,
     rho read and written."""
     compact = scheme.startswith(("OCFDS", "CFDS"))
@@ -73,6 +75,7 @@ def kernel_bytes_per_node(kname: str, Q: int, dim: int, scheme: str) -> int:
         "k_collide": (Q + (2 * dim if compact else 2)) + Q,
         "k_mu_march": 2,
         "k_force_march": 2 + dim,
+        "k_mf": 1 + dim,
     }
     return 8 * table.get(kname, 2 * Q + 2)
 
@@ -229,8 +232,10 @@ def main():
                      "step_algorithmic_bytes_per_node": step_bytes,
                      "step_achieved": round(step_gbs, 1), "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
                      "phases_ms": {k: round(v, 4) for k, v in phases}},
-        "tuner_ms_per_variant": {str(k): (round(v, 4) if v is not None else None) for k, v in tuned.items()},
+        "tuner_ms_per_variant": {f"{k} {sim.variant_name(k)}": (round(v, 4) if v is not None else None)
+                                 for k, v in tuned.items()},
         "variant": chosen,
+        "variant_name": sim.variant_name(chosen) if chosen is not None else None,
         "spurious_current": U, "mass": M, "status": code,
         # which steps of the run the timed region covered (the tuner and the
         # warm-up advance the state first); U and status are taken after them

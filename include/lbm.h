@@ -117,8 +117,8 @@ int lbm_init(const lbm_params* p, const double* rho0, int rho0_on_device,
  * reading taken where the paper names no rule).  Solid nodes report rho = 0
  * and v = 0; the observables run over the fluid.  On grids tiled by 64 x 8
  * (nx a multiple of 64, ny of 8) the step runs on the tile collide, one launch
- * variant per tile height; otherwise on the node-parallel kernels (one
- * variant).  Errors as lbm_init. */
+ * variant per tile height and z-segment length; otherwise on the
+ * node-parallel kernels (one variant).  Errors as lbm_init. */
 int lbm_init_wall(const lbm_params* p, const double* rho0, const unsigned char* solid, int on_device,
                   void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
 
@@ -155,6 +155,13 @@ int lbm_step_timed(lbm_ctx* c, long nsteps, double* ms, int cap, int* nphases);
  * the same step; a tuner times them and keeps the fastest. */
 int lbm_num_variants(const lbm_ctx* c);
 int lbm_set_variant(lbm_ctx* c, int v);
+
+/* Name of launch variant v of the context ("" if out of range), e.g.
+ * "ring 64x8 occ3", "tile 64x16 z64" (the ring-free tile collide with its
+ * z-segment length) or "tile 64x16 z64 mf" (the same, with the chemical
+ * potential and the force of Eq 12/16 formed by one march).  The string
+ * stays valid until the next call for this context. */
+const char* lbm_variant_name(lbm_ctx* c, int v);
 
 /* Name of phase k of the last timed step ("" if none). */
 const char* lbm_phase_name(const lbm_ctx* c, int k);

@@ -143,11 +143,16 @@ struct lbm_ctx {
     int cur;        // index of the buffers holding the current state (S and rho)
     long steps;
     std::string err;
+    std::string vname;   // last lbm_variant_name result
     // compact-scheme line geometry per axis
     LineGeom lines[3];
     double z, zscale;
     bool fused;     // fast path: the collide kernel also forms the next density
     int variant = 0;  // launch variant of the fused kernel
+    // tile-collide variants this grid and scheme can run (kTileVariants
+    // entries; the fused chemical-potential/force march only for the CD
+    // schemes in 3D without walls)
+    std::vector<TileVariant> tiles;
     // two-step launch graph replayed by lbm_step (captured on a private stream,
     // launched on the context's stream); graph_cur is the state parity it
     // starts from, graph_variant the launch variant it was captured with
@@ -385,11 +390,29 @@ void launch_step(lbm_ctx* c)
                 launch_mu_march<DIM, SCH>(rho, c->mu, c->g, c->eos, c->stream);
                 mark(c, "k_force_march");
                 launch_force_march<DIM, SCH>(rho, c->mu, c->force, c->g, c->eos, c->stream);
+                const TileVariant& tv = c->tiles[c->variant];
                 mark(c, "k_tile");
-                launch_tile<LAT>(c->variant, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur],
+                launch_tile<LAT>(tv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur],
                                  c->ringsum, c->g, c->rx, c->stream, c->wbits);
                 mark(c, "k_fix");
-                launch_fix<LAT>(c->variant, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
+                launch_fix<LAT>(tv, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
+                mark(c, nullptr);
+                c->cur = 1 - c->cur;
+                return;
+            }
+        }
+        const int rv = CD ? c->variant - kNumFusedVariants : c->variant;
+        const TileVariant* tv = rv >= kNumRingVariants ? &c->tiles[rv - kNumRingVariants] : nullptr;
+        if constexpr (CD && DIM == 3) {
+            if (tv && tv->mf) {
+                // chemical potential and force in one march, then the tile collide
+                mark(c, "k_mf");
+                launch_mf<SCH>(tv->ty, rho, c->force, c->g, c->eos, c->stream);
+                mark(c, "k_tile");
+                launch_tile<LAT>(*tv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->ringsum,
+                                 c->g, c->rx, c->stream);
+                mark(c, "k_fix");
+                launch_fix<LAT>(*tv, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
                 mark(c, nullptr);
                 c->cur = 1 - c->cur;
                 return;
@@ -419,14 +442,12 @@ void launch_step(lbm_ctx* c)
                 compact_deriv(c, c->mu, sink_of(c->force + d * c->g.N, C_FORCE, rho, c->grho + d * c->g.N), d);
             });
         }
-        const int rv = CD ? c->variant - kNumFusedVariants : c->variant;
-        if (rv >= kNumRingVariants) {
+        if (tv) {
             mark(c, "k_tile");
-            const int tv = rv - kNumRingVariants;
-            launch_tile<LAT>(tv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->ringsum, c->g,
+            launch_tile<LAT>(*tv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->ringsum, c->g,
                              c->rx, c->stream);
             mark(c, "k_fix");
-            launch_fix<LAT>(tv, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
+            launch_fix<LAT>(*tv, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
         } else {
             mark(c, "k_ring");
             launch_ring_collide<LAT>(rv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->g, c->rx,
@@ -653,6 +674,15 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
     // pass in 3D, the collide that forms the force itself in 2D (fastest of
     // each on 256^3 and 1024^2); the other schemes have only ring variants
     c->variant = (p->lattice == LBM_D3Q19 && p->scheme <= LBM_CD6 && !p->wall) ? kNumFusedVariants : 0;
+    if (c->ringsum) {
+        const bool mf_ok = p->lattice == LBM_D3Q19 && p->scheme <= LBM_CD6 && !p->wall;
+        for (const TileVariant& v : kTileVariants) {
+            if (!tile_fits(c->g, v.ty)) continue;
+            if (p->lattice == LBM_D2Q9 && v.fz != kTileVariants[0].fz) continue;   // one segment in 2D
+            if (v.mf && !mf_ok) continue;
+            c->tiles.push_back(v);
+        }
+    }
     c->use_graph = std::getenv("LBM_NO_GRAPH") == nullptr;
     if (const char* e = std::getenv("LBM_SEG_MIN_LINES")) c->seg_min_lines_yz = c->seg_min_lines_x = std::atoll(e);
     c->wave_lines = std::getenv("LBM_NO_WAVE_LINES") == nullptr;
@@ -973,8 +1003,8 @@ int lbm_step_timed(lbm_ctx* c, long nsteps, double* ms, int cap, int* nphases)
 int lbm_num_variants(const lbm_ctx* c)
 {
     if (!c || !c->fused) return 1;
-    if (c->g.wl) return num_tile_variants(c->g);   // walls: the tile collide only
-    const int tiles = c->ringsum ? num_tile_variants(c->g) : 0;
+    if (c->g.wl) return (int)c->tiles.size();   // walls: the tile collide only
+    const int tiles = (int)c->tiles.size();
     return (c->p.scheme <= LBM_CD6 ? kNumFusedVariants : 0) + kNumRingVariants + tiles;
 }
 
@@ -990,6 +1020,34 @@ const char* lbm_phase_name(const lbm_ctx* c, int k)
 {
     if (!c || k < 0 || k >= 15 || !c->phase[k]) return "";
     return c->phase[k];
+}
+
+const char* lbm_variant_name(lbm_ctx* c, int v)
+{
+    if (!c || v < 0 || v >= lbm_num_variants(c)) return "";
+    char buf[96];
+    int t = v;
+    if (!c->g.wl) {
+        const bool cd = c->p.scheme <= LBM_CD6;
+        if (cd) {
+            if (t < kNumFusedVariants) {
+                const FusedVariant& f = kFusedVariants[t];
+                std::snprintf(buf, sizeof buf, "fused 64x%d occ%d%s", f.ty, f.occ, f.pipe ? " pipe" : "");
+                return (c->vname = buf).c_str();
+            }
+            t -= kNumFusedVariants;
+        }
+        if (t < kNumRingVariants) {
+            const RingVariant& r = kRingVariants[t];
+            std::snprintf(buf, sizeof buf, "ring %dx%d occ%d%s", r.tx, r.ty, r.occ, r.pf ? " prefetch" : "");
+            return (c->vname = buf).c_str();
+        }
+        t -= kNumRingVariants;
+    }
+    const TileVariant& tv = c->tiles[t];
+    if (c->dim == 3) std::snprintf(buf, sizeof buf, "tile 64x%d z%d%s", tv.ty, tv.fz, tv.mf ? " mf" : "");
+    else std::snprintf(buf, sizeof buf, "tile 64x%d", tv.ty);
+    return (c->vname = buf).c_str();
 }
 
 void lbm_free(lbm_ctx* c)

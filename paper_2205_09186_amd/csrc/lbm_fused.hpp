@@ -580,6 +580,218 @@ inline void launch_force_march(const double* rho, const double* mu, double* F, c
 }
 
 // ---------------------------------------------------------------------------
+// k_mf: the chemical potential and the force of the explicit CD schemes in
+// one z-march (3D).  mu_hat = k^2 psi'(rho) - kappa_hat lap(rho) (Eq 15, 16)
+// never goes to memory: each workgroup computes it on its tile plus an R-wide
+// ring and forms F = -rho grad(mu_hat) + cs^2 grad(rho) (Eq 12) for the tile,
+// reading rho once and writing F.
+// Per plane p of the march:
+//   * rho of plane p is staged in LDS over the tile plus a 2R ring; every
+//     mu_hat cell (tile + R) takes its value into a register queue (planes
+//     p - 2R .. p) and its in-plane Laplacian terms into a second queue
+//     (planes p - R .. p);
+//   * mu_hat of plane p - R follows from the two queues and goes to an LDS
+//     ring of R + 1 planes (in-plane arms of grad mu_hat); the thread's own
+//     column also keeps it in a register queue (z arms);
+//   * rho of plane p - 2R leaves the queues through LDS for the in-plane arms
+//     of grad rho, and F of plane p - 2R is stored.
+// The march starts 2R planes before its segment.  Each thread owns one tile
+// node; the ring cells are dealt out as second cells to the first threads.
+// ---------------------------------------------------------------------------
+template <int SCH, int TY>
+__global__ void __launch_bounds__(64 * TY, TY <= 8 ? 4 : 1)
+k_mf(const double* __restrict__ rho, double* __restrict__ out, Grid g, TileGeom tg, Eos e)
+{
+    constexpr int R = radius(SCH);
+    constexpr int NTH = 64 * TY;
+    constexpr int WP = 64 + 4 * R, HP = TY + 4 * R, CP = WP * HP;   // staged rho: tile + 2R ring
+    constexpr int WM = 64 + 2 * R, HM = TY + 2 * R, CM = WM * HM;   // mu_hat cells: tile + R ring
+    constexpr int NH = CM - NTH;                                   // mu_hat cells outside the tile
+    constexpr int SMC = 1 + (NH + NTH - 1) / NTH;                  // mu_hat cells per thread
+    constexpr int SPP = (CP + NTH - 1) / NTH;                      // staged rho cells per thread
+    constexpr int NSL = R + 1;                                     // mu_hat planes kept in LDS
+    constexpr int QZ = 2 * R + 1;
+    constexpr double cs2 = 1.0 / 3.0;
+    __shared__ double sp[CP];
+    __shared__ double sm[NSL][CM];
+    __shared__ double sr[CM];
+
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nxy = (int)g.nxy;
+    const unsigned N = (unsigned)g.N;
+    int b = blockIdx.x;
+    {
+        const int nb = gridDim.x, per = nb / 8;
+        if (b < per * 8) b = (b % 8) * per + b / 8;
+    }
+    const int tx = b % tg.ntx;
+    const int ty = (b / tg.ntx) % tg.nty;
+    const int sz = b / (tg.ntx * tg.nty);
+    const int x0 = tx * 64, y0 = ty * TY;
+    const int lid = threadIdx.x;
+    const int lx = lid % 64, ly = lid / 64;
+    const bool in = x0 + lx < nx && y0 + ly < ny;
+    const int z0 = sz * tg.mz, z1 = min(z0 + tg.mz, nz);
+
+    // in-plane offsets of the staged rho cells this thread loads
+    unsigned off[SPP];
+#pragma unroll
+    for (int k = 0; k < SPP; ++k) {
+        const int idx = lid + k * NTH;
+        const int hy = idx / WP, hx = idx - hy * WP;
+        off[k] = idx < CP ? (unsigned)(pwrap(y0 - 2 * R + hy, ny) * nx + pwrap(x0 - 2 * R + hx, nx)) : 0u;
+    }
+    // this thread's mu_hat cells: its own node, then ring cells h = lid,
+    // lid + NTH, ... in the order top band, bottom band, side bands
+    int cm[SMC], cq[SMC];
+    bool cv[SMC];
+#pragma unroll
+    for (int s = 0; s < SMC; ++s) {
+        int mr, mc;
+        if (s == 0) {
+            mr = ly + R; mc = lx + R;
+            cv[s] = true;
+        } else {
+            const int h = (s - 1) * NTH + lid;
+            cv[s] = h < NH;
+            if (h < R * WM) { mr = h / WM; mc = h - mr * WM; }
+            else if (h < 2 * R * WM) { const int h2 = h - R * WM; mr = HM - R + h2 / WM; mc = h2 % WM; }
+            else {
+                const int h3 = cv[s] ? h - 2 * R * WM : 0;
+                const int c = h3 % (2 * R);
+                mr = R + h3 / (2 * R);
+                mc = c < R ? c : 64 + c;
+            }
+            if (!cv[s]) { mr = R; mc = R; }
+        }
+        cm[s] = mr * WM + mc;
+        cq[s] = (mr + R) * WP + (mc + R);
+    }
+
+    double rq[SMC][QZ];     // rho of each cell, planes p - 2R .. p (index 0 the oldest)
+    double lq[SMC][R + 1];  // in-plane Laplacian terms of each cell, planes p - R .. p
+    double ro[R];           // own column, planes p - 3R .. p - 2R - 1 (rq[0] continued)
+    double mq[QZ];          // own column mu_hat, planes p - 3R .. p - R
+#pragma unroll
+    for (int s = 0; s < SMC; ++s) {
+#pragma unroll
+        for (int k = 0; k < QZ; ++k) rq[s][k] = 0.0;
+#pragma unroll
+        for (int k = 0; k <= R; ++k) lq[s][k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) ro[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < QZ; ++k) mq[k] = 0.0;
+
+    double sv[SPP];
+    auto fetch = [&](int p) {
+        const unsigned zo = (unsigned)(pwrap(p, nz) * nxy);
+#pragma unroll
+        for (int k = 0; k < SPP; ++k)
+            if (lid + k * NTH < CP) sv[k] = ld32(rho, zo + off[k]);
+    };
+    const int pb = z0 - 2 * R, pe = z1 - 1 + 2 * R;
+    fetch(pb);
+    for (int p = pb; p <= pe; ++p) {
+#pragma unroll
+        for (int k = 0; k < SPP; ++k)
+            if (lid + k * NTH < CP) sp[lid + k * NTH] = sv[k];
+        __syncthreads();
+        if (p < pe) fetch(p + 1);
+        // queues advance by one plane; plane p enters
+#pragma unroll
+        for (int k = 0; k < R - 1; ++k) ro[k] = ro[k + 1];
+        ro[R - 1] = rq[0][0];
+#pragma unroll
+        for (int s = 0; s < SMC; ++s) {
+#pragma unroll
+            for (int k = 0; k < QZ - 1; ++k) rq[s][k] = rq[s][k + 1];
+#pragma unroll
+            for (int k = 0; k < R; ++k) lq[s][k] = lq[s][k + 1];
+            if (cv[s]) {
+                const int o = cq[s];
+                const double v = sp[o];
+                double a = 2.0 * d2(SCH, 0) * v;
+#pragma unroll
+                for (int m = 1; m <= R; ++m) {
+                    const double w = d2(SCH, m);
+                    a += w * (sp[o + m] + sp[o - m]);
+                    a += w * (sp[o + m * WP] + sp[o - m * WP]);
+                }
+                rq[s][QZ - 1] = v;
+                lq[s][R] = a;
+            }
+        }
+        // mu_hat of plane p - R (Eq 16)
+        if (p >= z0) {
+            double (*M)[CM] = sm + pwrap(p - R, NSL);
+#pragma unroll
+            for (int s = 0; s < SMC; ++s) {
+                if (!cv[s]) continue;
+                const double c = rq[s][R];
+                double acc = lq[s][0] + d2(SCH, 0) * c;
+#pragma unroll
+                for (int m = 1; m <= R; ++m) acc += d2(SCH, m) * (rq[s][R + m] + rq[s][R - m]);
+                const double mu = mu_bulk(c, e) - e.kappa * acc;
+                (*M)[cm[s]] = mu;
+                if (s == 0) {
+#pragma unroll
+                    for (int k = 0; k < QZ - 1; ++k) mq[k] = mq[k + 1];
+                    mq[QZ - 1] = mu;
+                }
+            }
+        }
+        // rho of plane p - 2R for the in-plane arms of grad rho
+        const int z = p - 2 * R;
+        if (z >= z0) {
+#pragma unroll
+            for (int s = 0; s < SMC; ++s)
+                if (cv[s]) sr[cm[s]] = rq[s][0];
+        }
+        __syncthreads();
+        // F of plane z (Eq 12)
+        if (z >= z0 && in) {
+            const double* M = sm[pwrap(z, NSL)];
+            const int o = cm[0];
+            double grx = 0.0, gry = 0.0, grz = 0.0, gmx = 0.0, gmy = 0.0, gmz = 0.0;
+#pragma unroll
+            for (int m = 1; m <= R; ++m) {
+                const double w = d1(SCH, m);
+                grx += w * (sr[o + m] - sr[o - m]);
+                gry += w * (sr[o + m * WM] - sr[o - m * WM]);
+                gmx += w * (M[o + m] - M[o - m]);
+                gmy += w * (M[o + m * WM] - M[o - m * WM]);
+                grz += w * (rq[0][m] - ro[R - m]);
+                gmz += w * (mq[R + m] - mq[R - m]);
+            }
+            const double r = rq[0][0];
+            const unsigned n = (unsigned)(z * nxy + (y0 + ly) * nx + x0 + lx);
+            st32(out, n, -r * gmx + cs2 * grx);
+            st32(out + N, n, -r * gmy + cs2 * gry);
+            st32(out + 2 * (size_t)N, n, -r * gmz + cs2 * grz);
+        }
+    }
+}
+
+// Segment length of the k_mf march: the 2R planes it reads before its
+// segment are a smaller share of a long one.
+constexpr int kMfZ = 64;
+
+template <int SCH>
+inline void launch_mf(int ty, const double* rho, double* F, const Grid& g, const Eos& e, hipStream_t st)
+{
+    TileGeom t;
+    t.ntx = (g.nx + 63) / 64;
+    t.nty = (g.ny + ty - 1) / ty;
+    t.mz = kMfZ;
+    t.nsz = (g.nz + kMfZ - 1) / kMfZ;
+    const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
+    if (ty == 16) hipLaunchKernelGGL((k_mf<SCH, 16>), dim3(nb), dim3(64 * 16), 0, st, rho, F, g, t, e);
+    else hipLaunchKernelGGL((k_mf<SCH, 8>), dim3(nb), dim3(64 * 8), 0, st, rho, F, g, t, e);
+}
+
+// ---------------------------------------------------------------------------
 // Collision of one node (Eq 1 SRT or D2Q9 MRT, Eq 6, Eq 8) from its pulled
 // populations and force; each post-collision value goes to emit(i, o) as soon
 // as it is formed.  FULL: SRT with tau = 1, where f* = feq(rho, u + du).
@@ -828,9 +1040,9 @@ k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
     const int x = tx * 64 + lx, y = ty * TY + ly;
     const int xm = wrapc(x - 1, nx), xp = wrapc(x + 1, nx);
     const int yc = y * nx, ym = wrapc(y - 1, ny) * nx, yp = wrapc(y + 1, ny) * nx;
-    const int z0 = LAT == 1 ? sz * FZ : 0;
-    const int z1 = LAT == 1 ? min(z0 + FZ, nz) : 1;
-    const int MZT = LAT == 1 ? FZ : 1;   // ring-sum planes per segment
+    const int z0 = LAT == 1 ? sz * tg.mz : 0;
+    const int z1 = LAT == 1 ? min(z0 + tg.mz, nz) : 1;
+    const int MZT = LAT == 1 ? tg.mz : 1;   // ring-sum planes per segment
     double* rs = ringsum + (size_t)b * MZT * TR::NR;
     const bool ring = lid < TR::NR;
     int rcx = 0, rcy = 0;
@@ -986,42 +1198,42 @@ __global__ void __launch_bounds__(256) k_fix(double* __restrict__ rho_next, cons
     st32(rho_next, n, acc);
 }
 
-// Tile heights of the tile collide.  The taller tile halves the edge share
-// (16% of the nodes instead of 29%) at one 1024-thread workgroup per CU.
-// kTileTY, the lowest, sizes the ring-sum buffer: it has the most ring cells
-// per node, and every grid the taller tile fits is tiled by it too.
-constexpr int kTileTYs[] = { 8, 16 };
-constexpr int kNumTileVariants = 2;
-constexpr int kTileTY = kTileTYs[0];
-
-inline int num_tile_variants(const Grid& g)
-{
-    int n = 0;
-    for (int v = 0; v < kNumTileVariants; ++v) n += tile_fits(g, kTileTYs[v]) ? 1 : 0;
-    return n;
-}
+// Launch variants of the tile collide: tile height, z planes per segment, and
+// whether the chemical potential and the force come from one march (k_mf) or
+// from the two marches (k_march).  The taller tile halves the edge share (16%
+// of the nodes instead of 29%) at one 1024-thread workgroup per CU; the longer
+// segment halves the two planes each segment pulls beyond its own.  The ring-
+// sum buffer has one slot per ring cell and plane of the lowest tile, for the
+// planes of the longest segment.
+struct TileVariant { int ty, fz, mf; };
+constexpr TileVariant kTileVariants[] = { {8, 32, 0}, {16, 32, 0}, {8, 64, 0}, {16, 64, 0},
+                                          {16, 32, 1}, {16, 64, 1}, {8, 64, 1} };
+constexpr int kNumTileVariants = 7;
+constexpr int kTileTY = 8;
+constexpr int kTileMaxFZ = 64;
 
 inline size_t ringsum_doubles(const Grid& g, bool three_d)
 {
-    const size_t ntile = (size_t)(g.nx / 64) * (g.ny / kTileTY) * (three_d ? (g.nz + FZ - 1) / FZ : 1);
-    return ntile * (three_d ? FZ : 1) * TileRing<kTileTY>::NR;
+    const size_t ntile = (size_t)(g.nx / 64) * (g.ny / kTileTY);
+    const size_t planes = three_d ? (size_t)((g.nz + kTileMaxFZ - 1) / kTileMaxFZ) * kTileMaxFZ : 1;
+    return ntile * planes * TileRing<kTileTY>::NR;
 }
 
-inline TileGeom tile_geom(const Grid& g, bool three_d, int ty)
+inline TileGeom tile_geom(const Grid& g, bool three_d, int ty, int fz)
 {
     TileGeom t;
     t.ntx = g.nx / 64;
     t.nty = g.ny / ty;
-    t.nsz = three_d ? (g.nz + FZ - 1) / FZ : 1;
-    t.mz = FZ;
+    t.nsz = three_d ? (g.nz + fz - 1) / fz : 1;
+    t.mz = three_d ? fz : 1;
     return t;
 }
 
 template <int LAT, int TY>
 inline void launch_tile_ty(const double* S, double* Sn, const double* F, double* rho_next, double* ringsum,
-                           const Grid& g, const Relax& rx, hipStream_t st, const unsigned* wb)
+                           const Grid& g, const Relax& rx, int fz, hipStream_t st, const unsigned* wb)
 {
-    const TileGeom t = tile_geom(g, LAT == 1, TY);
+    const TileGeom t = tile_geom(g, LAT == 1, TY, fz);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
     const bool full = rx.omo == 0.0 && !rx.mrt;
     if (wb) {
@@ -1041,29 +1253,29 @@ inline void launch_tile_ty(const double* S, double* Sn, const double* F, double*
 }
 
 template <int TY>
-inline void launch_fix_ty(double* rho_next, const double* ringsum, const Grid& g, bool three_d, hipStream_t st)
+inline void launch_fix_ty(double* rho_next, const double* ringsum, const Grid& g, bool three_d, int fz,
+                          hipStream_t st)
 {
-    const TileGeom t = tile_geom(g, three_d, TY);
-    const int mzt = three_d ? FZ : 1;
-    const long long items = (long long)t.ntx * t.nty * t.nsz * mzt * TileRing<TY>::NB;
+    const TileGeom t = tile_geom(g, three_d, TY, fz);
+    const long long items = (long long)t.ntx * t.nty * t.nsz * t.mz * TileRing<TY>::NB;
     hipLaunchKernelGGL((k_fix<TY>), dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, rho_next, ringsum,
-                       g, t, mzt);
-}
-
-// tv: tile variant, 0 .. num_tile_variants(g) - 1
-template <int LAT>
-inline void launch_tile(int tv, const double* S, double* Sn, const double* F, double* rho_next, double* ringsum,
-                        const Grid& g, const Relax& rx, hipStream_t st, const unsigned* wb = nullptr)
-{
-    if (tv == 1) launch_tile_ty<LAT, kTileTYs[1]>(S, Sn, F, rho_next, ringsum, g, rx, st, wb);
-    else launch_tile_ty<LAT, kTileTYs[0]>(S, Sn, F, rho_next, ringsum, g, rx, st, wb);
+                       g, t, t.mz);
 }
 
 template <int LAT>
-inline void launch_fix(int tv, double* rho_next, const double* ringsum, const Grid& g, hipStream_t st)
+inline void launch_tile(const TileVariant& v, const double* S, double* Sn, const double* F, double* rho_next,
+                        double* ringsum, const Grid& g, const Relax& rx, hipStream_t st,
+                        const unsigned* wb = nullptr)
 {
-    if (tv == 1) launch_fix_ty<kTileTYs[1]>(rho_next, ringsum, g, LAT == 1, st);
-    else launch_fix_ty<kTileTYs[0]>(rho_next, ringsum, g, LAT == 1, st);
+    if (v.ty == 16) launch_tile_ty<LAT, 16>(S, Sn, F, rho_next, ringsum, g, rx, v.fz, st, wb);
+    else launch_tile_ty<LAT, 8>(S, Sn, F, rho_next, ringsum, g, rx, v.fz, st, wb);
+}
+
+template <int LAT>
+inline void launch_fix(const TileVariant& v, double* rho_next, const double* ringsum, const Grid& g, hipStream_t st)
+{
+    if (v.ty == 16) launch_fix_ty<16>(rho_next, ringsum, g, LAT == 1, v.fz, st);
+    else launch_fix_ty<8>(rho_next, ringsum, g, LAT == 1, v.fz, st);
 }
 
 struct RingVariant { int tx, ty, occ, pf; };

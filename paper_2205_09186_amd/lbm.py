@@ -54,6 +54,7 @@ SYMBOLS = {
     "lbm_steps_done": (C.c_long, [C.c_void_p]),
     "lbm_step_timed": (C.c_int, [C.c_void_p, C.c_long, _D, C.c_int, C.POINTER(C.c_int)]),
     "lbm_phase_name": (C.c_char_p, [C.c_void_p, C.c_int]),
+    "lbm_variant_name": (C.c_char_p, [C.c_void_p, C.c_int]),
     "lbm_num_variants": (C.c_int, [C.c_void_p]),
     "lbm_set_variant": (C.c_int, [C.c_void_p, C.c_int]),
     "lbm_free": (None, [C.c_void_p]),
@@ -259,6 +260,10 @@ class Simulation:
 
     def set_variant(self, v: int) -> None:
         _check(lib().lbm_set_variant(self.ctx, int(v)), self.ctx)
+
+    def variant_name(self, v: int) -> str:
+        """What launch variant v is, e.g. 'tile 64x16 z64 mf'."""
+        return lib().lbm_variant_name(self.ctx, int(v)).decode()
 
     def tune(self, steps: int = 5):
         """Time every launch variant of the step kernel on this grid (the state

@@ -34,16 +34,16 @@ def _workload(orc, lat, n, scheme):
 
 def _design_variants(L, sim, lat, scheme):
     """One launch variant of each design the context offers: k_fused (CD
-    schemes), the first ring variant, and the tile collide if present."""
-    nv = sim.num_variants
-    cd = scheme in (L.CD2, L.CD4, L.CD6)
-    fused = 7 if cd else 0
+    schemes), the first ring variant, the tile collide with the two stencil
+    marches and, where offered, with the one chemical-potential/force march."""
+    names = [sim.variant_name(v) for v in range(sim.num_variants)]
     out = []
-    if cd:
-        out.append(0)
-    out.append(fused)
-    if nv > fused + 3:
-        out.append(nv - 1)
+    for kind in ("fused", "ring"):
+        first = [v for v, n in enumerate(names) if n.startswith(kind)]
+        out += first[:1]
+    tiles = [v for v, n in enumerate(names) if n.startswith("tile") and not n.endswith(" mf")]
+    mf = [v for v, n in enumerate(names) if n.endswith(" mf")]
+    out += tiles[-1:] + mf[:1]
     return out
 
 
@@ -61,10 +61,11 @@ def test_full_size_against_oracle(L, orc, lat, n, scheme, steps):
     d_rho0 = torch.from_numpy(rho0.reshape(-1)).cuda()
     probe = L.Simulation(L.Params(**kw), d_rho0)
     variants = _design_variants(L, probe, lat, L.SCHEMES[scheme])
+    probe_names = [probe.variant_name(v) for v in range(probe.num_variants)]
     probe.close()
     del probe
     for v in variants:
-        print(f"  variant {v}", flush=True)
+        print(f"  variant {v} {probe_names[v]}", flush=True)
         sim = L.Simulation(L.Params(**kw), d_rho0)
         sim.set_variant(v)
         sim.step(steps)
@@ -117,9 +118,10 @@ def test_full_size_wall_against_oracle(L, orc):
     d_rho0 = torch.from_numpy(rho0.reshape(-1)).cuda()
     probe = L.Simulation(L.Params(wall=1, mu_wall=mu_wall, **kw), d_rho0, solid=solid)
     nv = probe.num_variants
+    names = [probe.variant_name(v) for v in range(nv)]
     probe.close()
     del probe
-    assert nv == 2
+    assert names == ["tile 64x8 z32", "tile 64x16 z32", "tile 64x8 z64", "tile 64x16 z64"], names
     for v in range(nv):
         print(f"  variant {v}", flush=True)
         sim = L.Simulation(L.Params(wall=1, mu_wall=mu_wall, **kw), d_rho0, solid=solid)

@@ -258,6 +258,30 @@ def test_graph_replay_equals_plain_launches(L, orc, lat, shape, scheme, monkeypa
     assert np.array_equal(a.populations(), b.populations())
 
 
+@pytest.mark.parametrize("shape,scheme,steps", [((5, 8, 64), "CD6", 12), ((70, 16, 64), "CD2", 8),
+                                                ((130, 8, 64), "CD4", 6), ((9, 16, 128), "CD6", 10)])
+def test_mf_march_against_oracle(L, orc, shape, scheme, steps):
+    """The one-march chemical potential and force (k_mf) with each tile
+    variant that uses it: z extents shorter than its 2R lead (the planes wrap
+    more than once), one segment, and several segments with a short last one."""
+    g, l = orc.maxwell(0.9)
+    rho0 = inputs.droplet(shape, min(shape[1:]) / 3, 4.0, g, l)
+    nz, ny, nx = shape
+    kw = dict(lattice=1, nx=nx, ny=ny, nz=nz, tau=1.0, Tr=0.9, k=0.16, kappa=0.004, scheme=L.SCHEMES[scheme])
+    probe = L.Simulation(L.Params(**kw), rho0)
+    mf = [v for v in range(probe.num_variants) if probe.variant_name(v).endswith(" mf")]
+    assert mf, [probe.variant_name(v) for v in range(probe.num_variants)]
+    o = orc.Sim(orc.Params(**kw), rho0)
+    o.step(steps)
+    for v in mf:
+        print(f"case mf shape={shape} scheme={scheme} variant={probe.variant_name(v)}", flush=True)
+        s = L.Simulation(L.Params(**kw), rho0)
+        s.set_variant(v)
+        assert [n for n, _ in s.step_timed(1)] == ["k_mf", "k_tile", "k_fix"]
+        s.step(steps - 1)
+        _compare(s, o)
+
+
 @pytest.mark.parametrize("lat,shape,scheme,tau,coll", [
     (1, (20, 16, 128), "CD6", 1.0, 0), (1, (12, 8, 64), "CD4", 0.8, 0), (1, (9, 24, 192), "OCFDS4", 1.0, 0),
     (1, (10, 16, 64), "E8", 1.0, 0), (0, (40, 64), "CD6", 1.0, 0), (0, (16, 192), "CD2", 0.9, 0),
@@ -280,7 +304,16 @@ def test_tile_design(L, orc, lat, shape, scheme, tau, coll):
         names[v] = [n for n, _ in s.step_timed(1)]
     tiles = [v for v, n in names.items() if n[-2:] == ["k_tile", "k_fix"]]
     ring = [v for v, n in names.items() if n[-1] == "k_ring"][0]
-    assert len(tiles) == (2 if ny % 16 == 0 else 1), names   # tile heights 8 and 16
+    # tile heights 8 and 16; in 3D z segments of 32 and 64 planes, and for the
+    # CD schemes the fused chemical-potential/force march (64x16 z32, z64; 64x8 z64)
+    heights = 2 if ny % 16 == 0 else 1
+    if lat == 0:
+        expect = heights
+    else:
+        expect = 2 * heights + ((3 if heights == 2 else 1) if scheme in ("CD2", "CD4", "CD6") else 0)
+    assert len(tiles) == expect, names
+    mf = [v for v, n in names.items() if n[0] == "k_mf"]
+    assert len(mf) == (expect - 2 * heights if lat == 1 else 0), names
     b = L.Simulation(p, rho0)
     b.set_variant(ring)
     b.step(40)
