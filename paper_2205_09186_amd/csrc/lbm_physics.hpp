@@ -173,8 +173,11 @@ struct Eos {
 // relative), then e ln2 added with ln2 split into a 42-bit head (e * head is
 // exact) and a tail.  About a third of the instructions of the library log,
 // within a few ulp of it; the chemical potential evaluates two per node.
+// Outside its domain (x <= 0 or NaN) the result is NaN, as the library log's,
+// so a state driven to a negative density reports itself non-finite.
 __host__ __device__ __forceinline__ double log_pos(double x)
 {
+    if (!(x > 0.0)) return __builtin_nan("");
     int ex;
     double m = frexp(x, &ex);   // m in [0.5, 1)
     if (m < 0.70710678118654752440) { m += m; ex -= 1; }

@@ -134,3 +134,53 @@ def test_config3_set_matches_plain_runs(L):
         s.close()
     print("case config-3 set: running", n_run, "diverged", n_div, flush=True)
     assert n_run >= 40
+
+
+def _oracle_fields(orc, p, rho0, steps):
+    o = orc.Sim(orc.Params(lattice=orc.D2Q9, nx=p.nx, ny=p.ny, tau=p.tau, Tr=p.Tr, k=p.k, kappa=p.kappa,
+                           scheme=p.scheme), rho0)
+    o.step(steps)
+    r, vx, vy, _ = o.macros()
+    return r, vx, vy
+
+
+def test_batch_matches_oracle_300_steps(L, orc):
+    """Every instance of a mixed batch (slabs and droplets; CD2, CD4, CD6, E4,
+    E8, OCFDS4) after 300 steps of the persistent kernel against the oracle,
+    node by node: rho and v = u + F/(2 rho) to 1e-11."""
+    ps, rs = _build(L, _specs(L))
+    b = L.Batch(ps, rs)
+    st, steps, _ = b.run(300, check_every=100, tol=0.0, chunk=120)
+    assert list(st) == [L.RUNNING] * len(ps) and list(steps) == [300] * len(ps)
+    for i, (p, r) in enumerate(zip(ps, rs)):
+        ro, vxo, vyo = _oracle_fields(orc, p, r, 300)
+        ra, vxa, vya, _ = b.instance(i).macros()
+        d = max(np.abs(ra - ro).max(), np.abs(vxa - vxo).max(), np.abs(vya - vyo).max())
+        print(f"case batch instance {i} {_specs(L)[i][0]} scheme={p.scheme}: max|diff| = {d:.2e}", flush=True)
+        assert d <= 1e-11, (i, d)
+
+
+# Ten instances of the config-3 set that stay finite for 2000 steps in the
+# oracle: slabs and droplets, CD4, CD6 and OCFDS4, T_r 0.65-0.92.
+CONFIG3_ORACLE_SET = [4, 9, 16, 24, 38, 55, 61, 62, 90, 93]
+
+
+def test_config3_instances_match_oracle_2000_steps(L, orc):
+    """The full config-3 set (96 uneven instances) in one batch for 2000 steps;
+    ten of its instances against the oracle node by node, rho and v to 1e-11."""
+    from paper_2205_09186_amd import sweep
+    descs, params, rhos = sweep.build()
+    b = L.Batch(params, rhos)
+    st, steps, _ = b.run(2000, check_every=100, tol=0.0, chunk=1000)
+    kinds = set()
+    for i in CONFIG3_ORACLE_SET:
+        d, p, r = descs[i], params[i], rhos[i]
+        assert st[i] == L.RUNNING and steps[i] == 2000, (i, st[i], steps[i])
+        ro, vxo, vyo = _oracle_fields(orc, p, r, 2000)
+        ra, vxa, vya, _ = b.instance(i).macros()
+        dd = max(np.abs(ra - ro).max(), np.abs(vxa - vxo).max(), np.abs(vya - vyo).max())
+        print(f"case config-3 instance {i} {d['kind']} {p.nx}x{p.ny} {sweep.NAMES[p.scheme]} Tr={d['Tr']:.3f}: "
+              f"max|diff| = {dd:.2e}", flush=True)
+        assert dd <= 1e-11, (i, dd)
+        kinds.add((d["kind"], sweep.NAMES[p.scheme]))
+    assert {("slab", "OCFDS4"), ("slab", "CD6"), ("droplet", "OCFDS4"), ("droplet", "CD6")} <= kinds

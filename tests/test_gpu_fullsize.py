@@ -47,7 +47,7 @@ def _design_variants(L, sim, lat, scheme):
     return out
 
 
-@pytest.mark.parametrize("lat,n,scheme,steps", [(1, 256, "CD6", 3), (1, 256, "OCFDS4", 2), (0, 1024, "CD6", 20),
+@pytest.mark.parametrize("lat,n,scheme,steps", [(1, 256, "CD6", 50), (1, 256, "OCFDS4", 2), (0, 1024, "CD6", 20),
                                                 (0, 1024, "OCFDS4", 10), (1, 384, "CD6", 2), (1, 256, "E8", 2)])
 def test_full_size_against_oracle(L, orc, lat, n, scheme, steps):
     import torch

@@ -165,7 +165,8 @@ def test_wall_fixed_point_uniform_fluid(L, orc):
                                                          (1, (20, 32, 64), "CD6", 3.0, 0)])
 def test_wall_tile_collide(L, orc, lat, shape, scheme, mu_rel, coll, monkeypatch):
     """Grids tiled by 64 x 8 take the tile collide with bounce-back (every tile
-    height) against the oracle and against the node-parallel path."""
+    height and z-segment length) against the oracle and against the
+    node-parallel path."""
     solid, rho0 = _case(orc, lat, shape, 5 if lat == 0 else 4, ball=True, seed=2)
     nz, ny, nx = ((1,) + tuple(shape)) if lat == 0 else tuple(shape)
     kw = dict(lattice=lat, nx=nx, ny=ny, nz=nz, tau=1.0 if not coll else 0.9, Tr=0.8, k=0.16, kappa=0.004,
@@ -181,7 +182,8 @@ def test_wall_tile_collide(L, orc, lat, shape, scheme, mu_rel, coll, monkeypatch
     o.step(steps)
     probe = L.Simulation(L.Params(wall=1, **kw), rho0, solid=solid)
     nv = probe.num_variants
-    assert nv == (2 if ny % 16 == 0 else 1)
+    # tile heights 8 and 16; in 3D z segments of 32 and 64 planes
+    assert nv == (2 if ny % 16 == 0 else 1) * (2 if lat == 1 else 1)
     assert [n for n, _ in probe.step_timed(1)][-2:] == ["k_tile", "k_fix"]
     for v in range(nv):
         sim = L.Simulation(L.Params(wall=1, **kw), rho0, solid=solid)

@@ -1,0 +1,85 @@
+"""Accuracy of the series logarithm the chemical potential uses on the GPU
+(log_pos in csrc/lbm_physics.hpp), compiled for the host with g++ and compared
+with the x86 extended-precision logl on arguments spread over the whole double
+range, dense near 1 and around the reduction boundary sqrt(1/2).  Its domain is
+the positive doubles; it returns NaN for x <= 0 and NaN, as the library log."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2205_09186_amd", "csrc")
+
+HARNESS = r"""
+#include "lbm_physics.hpp"
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+static double ulp_err(double x)
+{
+    const long double ref = logl((long double)x);
+    const double got = lbm::log_pos(x);
+    const double r = (double)ref;
+    if (r == 0.0) return got == 0.0 ? 0.0 : 1e30;
+    const double u = std::nextafter(std::fabs(r), INFINITY) - std::fabs(r);
+    return (double)(std::fabs((long double)got - ref) / (long double)u);
+}
+
+int main()
+{
+    uint64_t s = 0x2205091862205091ULL;
+    auto next = [&]() { s ^= s << 13; s ^= s >> 7; s ^= s << 17; return s; };
+    double worst = 0.0, wx = 0.0;
+    auto take = [&](double x) { const double e = ulp_err(x); if (e > worst) { worst = e; wx = x; } };
+    long n = 0;
+    // log-uniform over 2^-1000 .. 2^1000
+    for (int i = 0; i < 2000000; ++i, ++n) {
+        const double t = (double)(next() >> 11) * 0x1p-53;
+        take(std::ldexp(1.0 + t, (int)(next() % 2001) - 1000));
+    }
+    // near 1, where the relative accuracy of a logarithm is hardest to keep
+    for (int k = 1; k <= 15; ++k)
+        for (int i = 0; i < 20000; ++i, ++n) {
+            const double t = (double)(next() >> 11) * 0x1p-53 * 2.0 - 1.0;
+            take(1.0 + t * std::pow(10.0, -k));
+        }
+    // around the reduction boundary m = sqrt(1/2) and the densities of the method
+    for (int i = 0; i < 200000; ++i, ++n) {
+        const double t = (double)(next() >> 11) * 0x1p-53 * 2.0 - 1.0;
+        take(std::ldexp(0.70710678118654752440 * (1.0 + 1e-6 * t), (int)(next() % 41) - 20));
+        take(1e-16 + 11.0 * (double)(next() >> 11) * 0x1p-53);
+        n++;
+    }
+    const double nan_neg = lbm::log_pos(-1.5), nan_zero = lbm::log_pos(0.0), nan_mzero = lbm::log_pos(-0.0);
+    const double nan_nan = lbm::log_pos(std::nan(""));
+    std::printf("%ld %.6f %.17g %d %d %d %d\n", n, worst, wx, (int)std::isnan(nan_neg), (int)std::isnan(nan_zero),
+                (int)std::isnan(nan_mzero), (int)std::isnan(nan_nan));
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("logpos")
+    src = d / "h.cpp"
+    src.write_text(HARNESS)
+    exe = d / "h"
+    subprocess.run(["g++", "-std=c++17", "-O2", "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return out
+
+
+def test_log_pos_within_two_ulp(harness):
+    n, worst, wx = int(harness[0]), float(harness[1]), float(harness[2])
+    print(f"log_pos: {n} arguments, worst {worst:.3f} ulp at x = {wx!r}")
+    assert n > 2_500_000
+    assert worst <= 2.0, (worst, wx)
+
+
+def test_log_pos_nan_outside_its_domain(harness):
+    assert harness[3:] == ["1", "1", "1", "1"]
