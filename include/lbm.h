@@ -222,10 +222,28 @@ size_t lbm_batch_workspace_bytes(const lbm_params* ps, int n);
 int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n,
                    void* d_workspace, size_t ws_bytes, void* hip_stream, lbm_batch** out);
 
-/* Workgroups of the cooperative launch (1..lbm_batch_max_grid; default the
- * maximum that can be resident); a tuner picks the fastest. */
+/* Workgroups of the cooperative launch (1..lbm_batch_max_grid, the most that
+ * can be resident for the current block size; that maximum is the default). */
 int lbm_batch_set_grid(lbm_batch* b, int workgroups);
 int lbm_batch_max_grid(const lbm_batch* b);
+
+/* Node-block size of the batched kernel: each work item of a phase is this
+ * many consecutive nodes of one instance, one per thread, and it is also the
+ * workgroup size.  256, 512 (default) or 1024; anything else is LBM_EINVAL.
+ * Setting it rebuilds the node-block tables (synchronises) and resets the
+ * workgroup count to the maximum for that size.  Results do not depend on
+ * either setting; a tuner times the combinations and keeps the fastest. */
+int lbm_batch_set_block(lbm_batch* b, int nodes);
+int lbm_batch_block(const lbm_batch* b);
+
+/* How the chunks are launched: "graph: captured cooperative launch" (each
+ * chunk replays a hipGraph holding the cooperative launch and the status
+ * read-back, one graph per chunk length, check interval, tolerance, block and
+ * workgroup count), "graph: cooperative kernel node (...)" where stream
+ * capture of a cooperative launch fails but a graph node with the
+ * cooperative attribute is accepted, or "plain cooperative launches (...)"
+ * with the reason (set LBM_NO_GRAPH to choose it). */
+const char* lbm_batch_launch_mode(const lbm_batch* b);
 
 /* Advance running instances by up to nsteps steps, in launches of at most
  * `chunk` steps; stops early once every instance has retired.  Host outputs
@@ -274,6 +292,18 @@ int mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int s
  * distance scale), feat3 the scaled (Tr, k, scheme).  d_rho: N doubles. */
 int mlp_field(const float* d_params, const float* norm7, const lbm_params* p, double cx, double cy, double cz,
               double R, const float* feat3, double rho_g, double rho_l, double* d_rho, void* stream);
+
+/* Total density of a learned initial field moved to target_mass without
+ * touching its bulk plateaus: every node gains (target - M) w / W, with M the
+ * total of the n device densities d_rho, w = phi (1 - phi), phi = (rho -
+ * rho_g)/(rho_l - rho_g) clamped to [0, 1] (zero on both plateaus) and W the
+ * sum of w.  The residual goes to the interface, where the profile is least
+ * certain; a field without interface nodes (W = 0) is left unchanged.  Sums
+ * in a fixed order (deterministic); d_scratch holds lbm_sum_scratch_bytes(n)
+ * bytes.  Enqueued on stream, no synchronisation.  LBM_EINVAL for n < 1, NULL
+ * pointers, rho_l <= rho_g or a non-finite argument. */
+int lbm_interface_mass(double* d_rho, long n, double rho_g, double rho_l, double target_mass, double* d_scratch,
+                       void* stream);
 
 /* Deterministic sum of n device doubles (scratch: lbm_sum_scratch_bytes(n)).
  * Synchronises. */

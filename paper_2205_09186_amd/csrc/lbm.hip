@@ -752,6 +752,19 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
     } else if (rc_ == LBM_OK) {
         rc_ = hip_check(c, hipMemcpyAsync(c->rhob[1], rho0, sizeof(double) * N, hipMemcpyDeviceToDevice,
                                           c->stream), "copy rho0");
+        // the same range check on the device: nodes outside (0, 1/b), counted
+        if (rc_ == LBM_OK) {
+            hipLaunchKernelGGL(k_check_rho, dim3((unsigned)L.nparts), dim3(256), 0, c->stream, c->rhob[1], wl, N,
+                               rho_max, c->partial);
+            hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->stream, c->partial, L.nparts, c->result);
+            double h[2] = { 0.0, 0.0 };
+            rc_ = hip_check(c, hipMemcpyAsync(h, c->result, sizeof(h), hipMemcpyDeviceToHost, c->stream),
+                            "rho0 check copy");
+            if (rc_ == LBM_OK) rc_ = hip_check(c, hipStreamSynchronize(c->stream), "rho0 check sync");
+            if (rc_ == LBM_OK && h[1] != 0.0)
+                rc_ = fail(c, LBM_EINVAL, "rho0 on device: " + std::to_string((long long)h[1]) +
+                                              " node(s) not finite or outside (0, 1/b)");
+        }
     }
     if (rc_ == LBM_OK) {
         // populations from rho0, then rho of that state (what the step reads)
@@ -767,14 +780,7 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
         rc_ = hip_check(c, hipGetLastError(), "init launch");
     }
     if (rc_ == LBM_OK) rc_ = hip_check(c, hipStreamSynchronize(c->stream), "init sync");
-    if (rc_ == LBM_OK && rho0_on_device) {
-        // a device rho0 is validated through the observables of the initial state
-        double um, ms;
-        int r2 = lbm_spurious_max(c, &um, &ms);
-        if (r2 == LBM_ENONFINITE) rc_ = fail(c, LBM_EINVAL, "rho0 on device is not finite");
-        else if (r2 != LBM_OK) rc_ = r2;
-    }
-    if (rc_ != LBM_OK) { delete c; return rc_; }
+    if (rc_ != LBM_OK) { lbm_free(c); return rc_; }
     *out = c;
     return LBM_OK;
 }
@@ -1114,11 +1120,23 @@ struct lbm_batch {
     int* d_blk_inst = nullptr;
     double* d_partial = nullptr;
     BLine* d_lines = nullptr;
+    int* d_flag = nullptr;      // set by k_batch if a launch was not cooperative
+    BState* h_st = nullptr;     // pinned host copies read after every chunk
+    int* h_flag = nullptr;
     int nblk_total = 0;
     int nlines = 0;
     int has_compact = 0;
-    int grid = 0;          // workgroups of the cooperative launch (0: all resident)
-    int max_grid = 0;
+    int block = kBatchDefaultBlock;   // nodes per node-block item = threads per workgroup
+    int grid = 0;                     // workgroups of the cooperative launch
+    int max_grid_of[kNumBatchBlocks] = {};
+    // chunk launches captured as graphs: the cooperative kernel and the two
+    // status read-backs, one graph per (chunk length, check interval,
+    // tolerance, workgroups, block); replayed on the batch's stream
+    struct Graph { int todo, check, grid, block; double tol; hipGraphExec_t exec; };
+    std::vector<Graph> graphs;
+    hipStream_t cap_stream = nullptr;
+    bool use_graph = true;
+    std::string mode = "plain cooperative launches";
     std::string err;
 };
 
@@ -1143,7 +1161,8 @@ bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
         B.inst_off[i] = off;
         off = align_up(off + layout_of(&ps[i]).total);
         const long long N = (long long)ps[i].nx * ps[i].ny;
-        B.nblk += (int)((N + BNODES - 1) / BNODES);
+        // node-block tables sized for the smallest block
+        B.nblk += (int)((N + kBatchMinBlock - 1) / kBatchMinBlock);
         if (is_compact(ps[i].scheme)) {
             if (std::max(ps[i].nx, ps[i].ny) > 64 * kLineSeg) {
                 *why = "compact-scheme instances of the batched sweep take lines of at most 1024 nodes";
@@ -1158,6 +1177,7 @@ bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
     off = align_up(off + sizeof(int) * B.nblk);
     off = align_up(off + sizeof(double) * B.nblk);
     off = align_up(off + sizeof(BLine) * std::max(1, B.nlines));
+    off = align_up(off + sizeof(int));
     B.total = off;
     return true;
 }
@@ -1167,6 +1187,134 @@ int bfail(lbm_batch* b, int code, const std::string& msg)
     if (b) b->err = msg;
     g_thread_error = msg;
     return code;
+}
+
+int batch_block_index(int block)
+{
+    for (int k = 0; k < kNumBatchBlocks; ++k)
+        if (kBatchBlocks[k] == block) return k;
+    return -1;
+}
+
+const void* batch_kernel(int block)
+{
+    switch (block) {
+    case 256: return reinterpret_cast<const void*>(k_batch<256>);
+    case 1024: return reinterpret_cast<const void*>(k_batch<1024>);
+    default: return reinterpret_cast<const void*>(k_batch<512>);
+    }
+}
+
+// Node-block items of every instance for the batch's block size, uploaded
+// with the instance table; synchronises.
+hipError_t batch_tables(lbm_batch* b)
+{
+    std::vector<int> blk_inst;
+    for (int i = 0; i < b->n; ++i) {
+        BInst& I = b->inst[i];
+        I.blk0 = (int)blk_inst.size();
+        I.nblk = (int)((I.g.N + b->block - 1) / b->block);
+        for (int k = 0; k < I.nblk; ++k) blk_inst.push_back(i);
+        I.part0 = I.blk0;
+    }
+    b->nblk_total = (int)blk_inst.size();
+    hipError_t e = hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * b->n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_blk_inst, blk_inst.data(), sizeof(int) * blk_inst.size(),
+                                            hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    return e;
+}
+
+void drop_graphs(lbm_batch* b)
+{
+    for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+}
+
+// The kernel node of a graph carries the cooperative launch attribute, or
+// gets it; anything else is refused (the graph is not used).
+hipError_t ensure_cooperative(hipGraph_t g)
+{
+    size_t num = 0;
+    hipError_t e = hipGraphGetNodes(g, nullptr, &num);
+    if (e != hipSuccess) return e;
+    std::vector<hipGraphNode_t> nodes(num);
+    e = hipGraphGetNodes(g, nodes.data(), &num);
+    int kernels = 0;
+    for (size_t k = 0; k < num && e == hipSuccess; ++k) {
+        hipGraphNodeType t;
+        e = hipGraphNodeGetType(nodes[k], &t);
+        if (e != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+        ++kernels;
+        hipKernelNodeAttrValue v{};
+        e = hipGraphKernelNodeGetAttribute(nodes[k], hipKernelNodeAttributeCooperative, &v);
+        if (e == hipSuccess && !v.cooperative) {
+            v.cooperative = 1;
+            e = hipGraphKernelNodeSetAttribute(nodes[k], hipKernelNodeAttributeCooperative, &v);
+            if (e == hipSuccess) e = hipGraphKernelNodeGetAttribute(nodes[k], hipKernelNodeAttributeCooperative, &v);
+            if (e == hipSuccess && !v.cooperative) e = hipErrorNotSupported;
+        }
+    }
+    if (e == hipSuccess && kernels != 1) e = hipErrorInvalidValue;
+    return e;
+}
+
+// One chunk as a graph: the cooperative kernel, then the status and flag
+// read-backs into the pinned host buffers.  First by stream capture of the
+// cooperative launch; where the runtime cannot capture it, by building the
+// graph from a kernel node with the cooperative attribute.
+hipError_t batch_graph(lbm_batch* b, const BatchArgs& a, hipGraphExec_t* out, std::string& how)
+{
+    const void* kfn = batch_kernel(b->block);
+    BatchArgs aa = a;
+    void* args[] = { &aa };
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t l = hipLaunchCooperativeKernel(kfn, dim3(b->grid), dim3(b->block), args, 0, b->cap_stream);
+        if (l == hipSuccess)
+            l = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost, b->cap_stream);
+        if (l == hipSuccess)
+            l = hipMemcpyAsync(b->h_flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost, b->cap_stream);
+        e = hipStreamEndCapture(b->cap_stream, &g);
+        if (e == hipSuccess) e = l;
+        if (e == hipSuccess && !g) e = hipErrorInvalidValue;
+        if (e == hipSuccess) e = ensure_cooperative(g);
+        how = "graph: captured cooperative launch";
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        g = nullptr;
+        const std::string first = hipGetErrorString(e);
+        e = hipGraphCreate(&g, 0);
+        hipGraphNode_t kn = nullptr, m1 = nullptr, m2 = nullptr;
+        if (e == hipSuccess) {
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void*>(kfn);
+            kp.gridDim = dim3(b->grid);
+            kp.blockDim = dim3(b->block);
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            e = hipGraphAddKernelNode(&kn, g, nullptr, 0, &kp);
+        }
+        if (e == hipSuccess) {
+            hipKernelNodeAttrValue v{};
+            v.cooperative = 1;
+            e = hipGraphKernelNodeSetAttribute(kn, hipKernelNodeAttributeCooperative, &v);
+        }
+        if (e == hipSuccess)
+            e = hipGraphAddMemcpyNode1D(&m1, g, &kn, 1, b->h_st, b->d_st, sizeof(BState) * b->n,
+                                        hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipGraphAddMemcpyNode1D(&m2, g, &m1, 1, b->h_flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = ensure_cooperative(g);
+        how = "graph: cooperative kernel node (stream capture of the cooperative launch failed: " + first + ")";
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
 }
 
 }  // namespace
@@ -1201,7 +1349,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     b->ws = static_cast<char*>(d_workspace);
     b->ctx.assign(n, nullptr);
     b->inst.resize(n);
-    std::vector<int> blk_inst;
+    b->use_graph = std::getenv("LBM_NO_GRAPH") == nullptr;
     int rc = LBM_OK;
     for (int i = 0; i < n && rc == LBM_OK; ++i) {
         lbm_ctx* c = nullptr;
@@ -1222,10 +1370,6 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         I.cc = compact_scheme(ps[i].scheme);
         I.z = c->z; I.zscale = c->zscale;
         I.K = c->lines[0].K;
-        I.blk0 = (int)blk_inst.size();
-        I.nblk = (int)((c->g.N + BNODES - 1) / BNODES);
-        for (int k = 0; k < I.nblk; ++k) blk_inst.push_back(i);
-        I.part0 = I.blk0;
         if (is_compact(ps[i].scheme)) b->has_compact = 1;
     }
     if (rc != LBM_OK) { std::string e = b->err; lbm_batch_free(b); return bfail(nullptr, rc, e); }
@@ -1234,7 +1378,8 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     b->d_st = reinterpret_cast<BState*>(b->ws + off); off = align_up(off + sizeof(BState) * n);
     b->d_blk_inst = reinterpret_cast<int*>(b->ws + off); off = align_up(off + sizeof(int) * B.nblk);
     b->d_partial = reinterpret_cast<double*>(b->ws + off); off = align_up(off + sizeof(double) * B.nblk);
-    b->d_lines = reinterpret_cast<BLine*>(b->ws + off);
+    b->d_lines = reinterpret_cast<BLine*>(b->ws + off); off = align_up(off + sizeof(BLine) * std::max(1, B.nlines));
+    b->d_flag = reinterpret_cast<int*>(b->ws + off);
     // the grid lines of the compact-scheme instances, rows then columns; lines
     // of at most kShortLine points go 64 to an item (one per lane)
     std::vector<BLine> lines;
@@ -1247,28 +1392,32 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         }
     }
     b->nlines = (int)lines.size();
-    b->nblk_total = (int)blk_inst.size();
     std::vector<BState> st(n);
     for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.stop = -1; x.U = 0.0; x.U_prev = 0.0; }
-    hipError_t e = hipSuccess;
-    if (!lines.empty())
+    static const int zero = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_st), sizeof(BState) * n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_flag), sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) *b->h_flag = 0;
+    if (e == hipSuccess && !lines.empty())
         e = hipMemcpyAsync(b->d_lines, lines.data(), sizeof(BLine) * lines.size(), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_st, st.data(), sizeof(BState) * n, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_blk_inst, blk_inst.data(), sizeof(int) * blk_inst.size(),
-                                            hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    int per_cu = 0, dev = 0, ncu = 0;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BNODES, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = batch_tables(b);
+    int dev = 0, ncu = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    for (int k = 0; k < kNumBatchBlocks && e == hipSuccess; ++k) {
+        int per_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(kBatchBlocks[k]), kBatchBlocks[k], 0);
+        b->max_grid_of[k] = std::max(1, per_cu * ncu);
+    }
+    if (e == hipSuccess && b->use_graph) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         std::string m = std::string("batch setup: ") + hipGetErrorString(e);
         lbm_batch_free(b);
         return bfail(nullptr, LBM_EHIP, m);
     }
-    b->max_grid = std::max(1, per_cu * ncu);
-    b->grid = b->max_grid;
+    b->grid = b->max_grid_of[batch_block_index(b->block)];
     *out = b;
     return LBM_OK;
 }
@@ -1276,20 +1425,39 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
 int lbm_batch_set_grid(lbm_batch* b, int workgroups)
 {
     if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
-    if (workgroups < 1 || workgroups > b->max_grid) return bfail(b, LBM_EINVAL, "workgroups out of range");
+    if (workgroups < 1 || workgroups > lbm_batch_max_grid(b)) return bfail(b, LBM_EINVAL, "workgroups out of range");
     b->grid = workgroups;
     return LBM_OK;
 }
 
-int lbm_batch_max_grid(const lbm_batch* b) { return b ? b->max_grid : 0; }
+int lbm_batch_max_grid(const lbm_batch* b) { return b ? b->max_grid_of[batch_block_index(b->block)] : 0; }
+
+int lbm_batch_set_block(lbm_batch* b, int nodes)
+{
+    if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
+    const int k = batch_block_index(nodes);
+    if (k < 0) return bfail(b, LBM_EINVAL, "block must be 256, 512 or 1024 nodes");
+    if (nodes == b->block) return LBM_OK;
+    b->block = nodes;
+    const hipError_t e = batch_tables(b);
+    if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("batch tables: ") + hipGetErrorString(e));
+    b->grid = b->max_grid_of[k];
+    return LBM_OK;
+}
+
+int lbm_batch_block(const lbm_batch* b) { return b ? b->block : 0; }
+
+const char* lbm_batch_launch_mode(const lbm_batch* b) { return b ? b->mode.c_str() : ""; }
 
 int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long chunk, int* status, long* steps,
                   double* umax)
 {
     if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
-    if (nsteps < 0 || check_every < 1 || chunk < 1 || !(tol >= 0.0)) return bfail(b, LBM_EINVAL, "bad run arguments");
-    std::vector<BState> st(b->n);
+    if (nsteps < 0 || check_every < 1 || chunk < 1 || chunk > (1L << 30) || check_every > (1L << 30) ||
+        !(tol >= 0.0))
+        return bfail(b, LBM_EINVAL, "bad run arguments");
     long done = 0;
+    bool ran = false;
     while (done < nsteps) {
         const long todo = std::min(chunk, nsteps - done);
         BatchArgs a;
@@ -1303,25 +1471,73 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
         a.nsteps = (int)todo;
         a.check_every = (int)check_every;
         a.tol = tol;
-        void* args[] = { &a };
-        hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_batch), dim3(b->grid),
-                                                  dim3(BNODES), args, 0, b->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(st.data(), b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost,
-                                                b->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        a.not_cooperative = b->d_flag;
+        hipError_t e = hipSuccess;
+        bool replayed = false;
+        if (b->use_graph) {
+            lbm_batch::Graph* gr = nullptr;
+            for (auto& g : b->graphs)
+                if (g.todo == (int)todo && g.check == (int)check_every && g.tol == tol && g.grid == b->grid &&
+                    g.block == b->block)
+                    gr = &g;
+            if (!gr) {
+                hipGraphExec_t ex = nullptr;
+                std::string how;
+                const hipError_t ge = batch_graph(b, a, &ex, how);
+                if (ge == hipSuccess) {
+                    b->graphs.push_back({ (int)todo, (int)check_every, b->grid, b->block, tol, ex });
+                    gr = &b->graphs.back();
+                    b->mode = how;
+                } else {
+                    (void)hipGetLastError();
+                    b->use_graph = false;
+                    b->mode = std::string("plain cooperative launches (no graph: ") + hipGetErrorString(ge) + ")";
+                }
+            }
+            if (gr) {
+                e = hipGraphLaunch(gr->exec, b->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+                if (e == hipSuccess && *b->h_flag) {
+                    // the replay did not launch cooperatively: the kernel
+                    // returned at once, so this chunk runs again below
+                    static const int zero = 0;
+                    e = hipMemcpyAsync(b->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
+                    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+                    drop_graphs(b);
+                    b->use_graph = false;
+                    b->mode = "plain cooperative launches (a graph replay was not cooperative)";
+                } else {
+                    replayed = e == hipSuccess;
+                }
+            }
+        }
+        if (e == hipSuccess && !replayed) {
+            void* args[] = { &a };
+            e = hipLaunchCooperativeKernel(batch_kernel(b->block), dim3(b->grid), dim3(b->block), args, 0, b->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost,
+                                                    b->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        }
         if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+        ran = true;
         done += todo;
         bool running = false;
-        for (const auto& x : st) running |= x.status == B_RUNNING;
+        for (int i = 0; i < b->n; ++i) running |= b->h_st[i].status == B_RUNNING;
         if (!running) break;
+    }
+    if (!ran) {
+        // no step asked for: report the current state
+        const hipError_t e = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost, b->stream);
+        if (e != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)
+            return bfail(b, LBM_EHIP, "batch status copy");
     }
     for (int i = 0; i < b->n; ++i) {
         lbm_ctx* c = b->ctx[i];
-        c->steps = (long)st[i].steps;
-        c->cur = (int)(st[i].steps & 1);
-        if (status) status[i] = st[i].status;
-        if (steps) steps[i] = (long)st[i].steps;
-        if (umax) umax[i] = st[i].U;
+        c->steps = (long)b->h_st[i].steps;
+        c->cur = (int)(b->h_st[i].steps & 1);
+        if (status) status[i] = b->h_st[i].status;
+        if (steps) steps[i] = (long)b->h_st[i].steps;
+        if (umax) umax[i] = b->h_st[i].U;
     }
     return LBM_OK;
 }
@@ -1337,6 +1553,10 @@ const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str()
 void lbm_batch_free(lbm_batch* b)
 {
     if (!b) return;
+    drop_graphs(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->h_st) (void)hipHostFree(b->h_st);
+    if (b->h_flag) (void)hipHostFree(b->h_flag);
     for (auto* c : b->ctx) lbm_free(c);
     delete b;
 }
@@ -1421,6 +1641,22 @@ int lbm_sum(const double* d_x, long n, double* d_scratch, double* h_sum, void* s
     if (r) return r;
     *h_sum = h[1];
     return LBM_OK;
+}
+
+int lbm_interface_mass(double* d_rho, long n, double rho_g, double rho_l, double target_mass, double* d_scratch,
+                       void* stream)
+{
+    if (!d_rho || !d_scratch || n < 1 || !(rho_l > rho_g) || !std::isfinite(rho_g) || !std::isfinite(rho_l) ||
+        !std::isfinite(target_mass))
+        return fail(nullptr, LBM_EINVAL, "lbm_interface_mass: bad arguments");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const long long nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_mass_partials, dim3((unsigned)nb), dim3(256), 0, st, d_rho, (long long)n, rho_g, rho_l,
+                       d_scratch);
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(1024), 0, st, d_scratch, nb, d_scratch + 2 * nb);
+    hipLaunchKernelGGL(k_mass_apply, dim3((unsigned)nb), dim3(256), 0, st, d_rho, (long long)n, rho_g, rho_l,
+                       d_scratch + 2 * nb, target_mass);
+    return hip_check(nullptr, hipGetLastError(), "lbm_interface_mass");
 }
 
 // lbm_sum_static: the deterministic sum with its scratch (the per-workgroup

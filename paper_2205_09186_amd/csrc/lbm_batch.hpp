@@ -48,7 +48,13 @@ struct BState {             // per instance, updated by the kernel
     double U, U_prev;
 };
 
-constexpr int BNODES = 512;   // nodes per node-block item (one per thread), threads per workgroup
+// Node-block sizes of the batched kernel: nodes per node-block item (one per
+// thread) and threads per workgroup.  A tuner picks one with the workgroup
+// count; 512 is the default.
+constexpr int kBatchBlocks[] = { 256, 512, 1024 };
+constexpr int kNumBatchBlocks = 3;
+constexpr int kBatchDefaultBlock = 512;
+constexpr int kBatchMinBlock = 256;
 
 // ---------------------------------------------------------------------------
 // per-node bodies with runtime scheme dispatch
@@ -174,14 +180,23 @@ struct BatchArgs {
     int nsteps;
     int check_every;
     double tol;
+    int* not_cooperative;     // set (and nothing else done) if the launch was not cooperative
 };
 
 __device__ __forceinline__ void bar(cooperative_groups::grid_group& gg) { gg.sync(); }
 
+template <int BNODES>
 __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
 {
     namespace cg = cooperative_groups;
     cg::grid_group gg = cg::this_grid();
+    // the grid barriers below exist only in a cooperative launch: any other
+    // launch (a graph replay that lost the attribute) reports itself and
+    // returns before the first barrier, with the state untouched
+    if (!gg.is_valid()) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *a.not_cooperative = 1;
+        return;
+    }
     using L = Lat<0>;
     __shared__ double red[BNODES / 64];
 

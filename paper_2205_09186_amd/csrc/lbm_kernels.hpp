@@ -474,6 +474,22 @@ __global__ void __launch_bounds__(256) k_macros(const double* __restrict__ S,
     if (threadIdx.x == 0) { partial[2 * blockIdx.x] = vmax; partial[2 * blockIdx.x + 1] = msum; }
 }
 
+// Nodes whose initial density lies outside (0, rmax) (NaN included), solid
+// nodes (wl != 0) skipped: per-block counts in the sum slot of the partials.
+__global__ void __launch_bounds__(256) k_check_rho(const double* __restrict__ rho,
+                                                   const unsigned char* __restrict__ wl, long long N, double rmax,
+                                                   double* __restrict__ partial)
+{
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    double mx = 0.0, bad = 0.0;
+    if (n < N && !(wl && wl[n])) {
+        const double r = rho[n];
+        bad = (r > 0.0 && r < rmax) ? 0.0 : 1.0;
+    }
+    block_reduce<256>(mx, bad);
+    if (threadIdx.x == 0) { partial[2 * blockIdx.x] = 0.0; partial[2 * blockIdx.x + 1] = bad; }
+}
+
 __global__ void __launch_bounds__(1024) k_reduce_final(const double* __restrict__ partial, long long nparts,
                                                        double* __restrict__ out)
 {

@@ -223,4 +223,65 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__
     if (threadIdx.x == 0) { partial[2 * blockIdx.x] = 0.0; partial[2 * blockIdx.x + 1] = sm; }
 }
 
+// Interface mass: the weight w = phi (1 - phi) of a node, phi = (rho -
+// rho_g)/(rho_l - rho_g) clamped to [0, 1], is zero on both plateaus.
+__device__ __forceinline__ double iface_w(double r, double rg, double rl)
+{
+    const double phi = fmin(fmax((r - rg) / (rl - rg), 0.0), 1.0);
+    return phi * (1.0 - phi);
+}
+
+// Two sums over a workgroup in a fixed order (wavefront tree, then waves in
+// order); thread 0 holds the result.
+template <int BS>
+__device__ __forceinline__ void block_sum2(double& a, double& b)
+{
+    __shared__ double sa[BS / 64], sb[BS / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+    if (ln == 0) { sa[wv] = a; sb[wv] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = sa[0]; b = sb[0];
+        for (int k = 1; k < BS / 64; ++k) { a += sa[k]; b += sb[k]; }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mass_partials(const double* __restrict__ rho, long long N, double rg,
+                                                       double rl, double* __restrict__ partial)
+{
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    double m = 0.0, w = 0.0;
+    if (n < N) { m = rho[n]; w = iface_w(m, rg, rl); }
+    block_sum2<256>(m, w);
+    if (threadIdx.x == 0) { partial[2 * blockIdx.x] = m; partial[2 * blockIdx.x + 1] = w; }
+}
+
+__global__ void __launch_bounds__(1024) k_mass_final(const double* __restrict__ partial, long long nb,
+                                                     double* __restrict__ out)
+{
+    double m = 0.0, w = 0.0;
+    for (long long k = threadIdx.x; k < nb; k += 1024) {
+        m += partial[2 * k];
+        w += partial[2 * k + 1];
+    }
+    block_sum2<1024>(m, w);
+    if (threadIdx.x == 0) { out[0] = m; out[1] = w; }
+}
+
+// rho += (target - M) w / W on every node (M, W in tot); nothing where W = 0.
+__global__ void __launch_bounds__(256) k_mass_apply(double* __restrict__ rho, long long N, double rg, double rl,
+                                                    const double* __restrict__ tot, double target)
+{
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    const double W = tot[1];
+    if (n >= N || !(W > 0.0)) return;
+    const double r = rho[n];
+    rho[n] = r + (target - tot[0]) * (iface_w(r, rg, rl) / W);
+}
+
 }  // namespace lbm

@@ -65,6 +65,9 @@ SYMBOLS = {
                                  C.POINTER(C.c_void_p)]),
     "lbm_batch_set_grid": (C.c_int, [C.c_void_p, C.c_int]),
     "lbm_batch_max_grid": (C.c_int, [C.c_void_p]),
+    "lbm_batch_set_block": (C.c_int, [C.c_void_p, C.c_int]),
+    "lbm_batch_block": (C.c_int, [C.c_void_p]),
+    "lbm_batch_launch_mode": (C.c_char_p, [C.c_void_p]),
     "lbm_batch_run": (C.c_int, [C.c_void_p, C.c_long, C.c_long, C.c_double, C.c_long, C.POINTER(C.c_int),
                                 C.POINTER(C.c_long), _D]),
     "lbm_batch_instance": (C.c_void_p, [C.c_void_p, C.c_int]),
@@ -81,6 +84,8 @@ SYMBOLS = {
                             C.POINTER(C.c_float), C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
     "lbm_sum_scratch_bytes": (C.c_size_t, [C.c_long]),
     "lbm_sum": (C.c_int, [C.c_void_p, C.c_long, C.c_void_p, _D, C.c_void_p]),
+    "lbm_interface_mass": (C.c_int, [C.c_void_p, C.c_long, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                     C.c_void_p]),
     "lbm_sum_static_max": (C.c_size_t, []),
     "lbm_sum_static": (C.c_int, [C.c_void_p, C.c_long, _D, C.c_void_p]),
     "lbm_probe_copy": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
@@ -402,6 +407,20 @@ class Batch:
         if code != LBM_OK:
             raise LbmError(code, lib().lbm_batch_last_error(self.h).decode())
 
+    @property
+    def block(self) -> int:
+        return int(lib().lbm_batch_block(self.h))
+
+    def set_block(self, nodes: int) -> None:
+        """Node-block size (256, 512, 1024); resets the workgroup count."""
+        code = lib().lbm_batch_set_block(self.h, int(nodes))
+        if code != LBM_OK:
+            raise LbmError(code, lib().lbm_batch_last_error(self.h).decode())
+
+    @property
+    def launch_mode(self) -> str:
+        return lib().lbm_batch_launch_mode(self.h).decode()
+
     def run(self, nsteps: int, check_every: int = 100, tol: float = 1e-10, chunk: int = 1000, progress=None):
         """Advance; returns (status[n], steps[n], U[n]) numpy arrays.  With a
         progress callback the run is issued chunk by chunk and the callback
@@ -427,21 +446,28 @@ class Batch:
         ctx = lib().lbm_batch_instance(self.h, int(i))
         return _View(C.c_void_p(ctx), self.params[i], self.device, self)
 
-    def tune(self, steps: int = 50, candidates=None):
-        """Time the cooperative launch at several workgroup counts (the state
-        advances) and keep the fastest.  Returns {workgroups: ms per step}."""
+    def tune(self, steps: int = 50, blocks=(256, 512, 1024)):
+        """Time the launch for every node-block size and, for each, the most
+        resident workgroups and a half and a quarter of them (the state
+        advances); keep the fastest.  Each combination runs once untimed (its
+        launch graph is captured then) and once timed.
+        Returns {"block/workgroups": ms per step}."""
         import time
-        mg = self.max_grid
-        cands = candidates or sorted({mg, max(1, mg // 2), max(1, mg // 4)})
         res = {}
-        for wg in cands:
-            self.set_grid(wg)
-            self.torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            self.run(steps, check_every=10 ** 9, tol=0.0, chunk=steps)
-            res[wg] = (time.perf_counter() - t0) * 1e3 / steps
+        for bn in blocks:
+            self.set_block(bn)
+            mg = self.max_grid
+            for wg in sorted({mg, max(1, mg // 2), max(1, mg // 4)}):
+                self.set_grid(wg)
+                self.run(steps, check_every=10 ** 9, tol=0.0, chunk=steps)
+                self.torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                self.run(steps, check_every=10 ** 9, tol=0.0, chunk=steps)
+                res[f"{bn}/{wg}"] = (time.perf_counter() - t0) * 1e3 / steps
         best = min(res, key=res.get)
-        self.set_grid(best)
+        bn, wg = (int(x) for x in best.split("/"))
+        self.set_block(bn)
+        self.set_grid(wg)
         return res
 
     def close(self):

@@ -150,9 +150,13 @@ def device_sum(x) -> float:
     return s.value
 
 
-def mass_matched_field(net: Net, p: lbm.Params, R0, Tr, k, scheme, rho_g, rho_l, target_mass, iters=60):
-    """Bisection on the radius so that the learned field has the target mass.
-    Returns (rho0 device tensor or None, radius)."""
+def mass_matched_field(net: Net, p: lbm.Params, R0, Tr, k, scheme, rho_g, rho_l, target_mass, iters=60,
+                       rel_tol=1e-10):
+    """Bisection on the radius so that the learned field has the target mass,
+    then lbm_interface_mass for the residual the FP32 network leaves (only
+    interface nodes change; the bulk densities stay as the network set them).
+    Returns (rho0 device tensor, radius), or (None, R0) when the target is not
+    bracketed or the mass still misses it by more than rel_tol."""
     lo, hi = 0.25 * R0, min(p.nx, p.ny) * 0.5
     f_lo = device_sum(net.field(p, lo, Tr, k, scheme, rho_g, rho_l)) - target_mass
     f_hi = device_sum(net.field(p, hi, Tr, k, scheme, rho_g, rho_l)) - target_mass
@@ -167,9 +171,15 @@ def mass_matched_field(net: Net, p: lbm.Params, R0, Tr, k, scheme, rho_g, rho_l,
             hi = mid
     R = 0.5 * (lo + hi)
     rho = net.field(p, R, Tr, k, scheme, rho_g, rho_l)
-    # the last bit of mass (discrete radius steps) goes into a uniform scaling
-    m = device_sum(rho)
-    rho.mul_(target_mass / m)
+    # the network evaluates in FP32, so the mass moves in small steps with R:
+    # the library puts the last residual into the interface nodes
+    import torch
+    scratch = torch.empty(int(lbm.lib().lbm_sum_scratch_bytes(rho.numel())) // 8 + 1, dtype=torch.float64,
+                          device=rho.device)
+    lbm._check(lbm.lib().lbm_interface_mass(_ptr(rho), rho.numel(), float(rho_g), float(rho_l), float(target_mass),
+                                            _ptr(scratch), C.c_void_p(torch.cuda.current_stream(rho.device).cuda_stream)))
+    if not abs(device_sum(rho) - target_mass) <= rel_tol * abs(target_mass):
+        return None, R0
     return rho, R
 
 

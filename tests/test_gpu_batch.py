@@ -184,3 +184,49 @@ def test_config3_instances_match_oracle_2000_steps(L, orc):
         assert dd <= 1e-11, (i, dd)
         kinds.add((d["kind"], sweep.NAMES[p.scheme]))
     assert {("slab", "OCFDS4"), ("slab", "CD6"), ("droplet", "OCFDS4"), ("droplet", "CD6")} <= kinds
+
+
+def test_batch_graph_replay_equals_plain_launches(L, monkeypatch):
+    """The chunk launches replayed from captured graphs against plain
+    cooperative launches: after every chunk (a remainder chunk included, so two
+    graphs are used, each replayed several times with host work between) the
+    status, step counts, U and populations are bitwise equal."""
+    ps, rs = _build(L, _specs(L))
+    g = L.Batch(ps, rs)
+    monkeypatch.setenv("LBM_NO_GRAPH", "1")
+    p = L.Batch(ps, rs)
+    monkeypatch.delenv("LBM_NO_GRAPH")
+    for k, n in enumerate((70, 70, 70, 40, 70, 70)):
+        a = g.run(n, check_every=50, tol=0.0, chunk=70)
+        b = p.run(n, check_every=50, tol=0.0, chunk=70)
+        print(f"case batch graph chunk {k}: {g.launch_mode} | {p.launch_mode}", flush=True)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), k
+        for i in range(len(ps)):
+            assert np.array_equal(g.instance(i).populations(), p.instance(i).populations()), (k, i)
+    assert g.launch_mode.startswith("graph"), g.launch_mode
+    assert p.launch_mode.startswith("plain"), p.launch_mode
+
+
+def test_batch_block_sizes_give_the_same_state(L):
+    """The node-block size (256, 512, 1024) and the workgroup count change
+    which workgroup updates which node, not the arithmetic: bitwise equal."""
+    ps, rs = _build(L, _specs(L))
+    ref = None
+    for bn in (256, 512, 1024):
+        b = L.Batch(ps, rs)
+        b.set_block(bn)
+        assert b.block == bn
+        b.set_grid(max(1, b.max_grid // 3))
+        st = b.run(160, check_every=40, tol=0.0, chunk=80)
+        f = [b.instance(i).populations() for i in range(len(ps))]
+        print(f"case batch block {bn}: max grid {b.max_grid}", flush=True)
+        if ref is None:
+            ref = (st, f)
+        else:
+            for x, y in zip(st, ref[0]):
+                assert np.array_equal(x, y), bn
+            for x, y in zip(f, ref[1]):
+                assert np.array_equal(x, y), bn
+    with pytest.raises(L.LbmError):
+        b.set_block(300)

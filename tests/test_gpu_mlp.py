@@ -158,3 +158,43 @@ def test_shipped_network_gives_a_droplet_profile(env):
     j = int(np.nonzero(ray < mid)[0][0])
     r_mid = (j - 1) + (ray[j - 1] - mid) / (ray[j - 1] - ray[j])
     assert abs(r_mid - R) < 1.5, r_mid
+
+
+def test_interface_mass_moves_only_the_interface(env):
+    """lbm_interface_mass: the total reaches the target to rounding, nodes on
+    either plateau keep their value bit for bit, interface nodes change in
+    proportion to phi (1 - phi), and a second call on the same input gives
+    the same field (fixed summation order)."""
+    import ctypes as C
+    from paper_2205_09186_amd import inputs
+    torch, lbm, learned, mlp = env
+    g, l = 0.197079412818, 7.20404871599
+    r0 = inputs.droplet((150, 130), 40.0, 10.0, g, l, amplitude=0.0)
+    # plateaus exactly at the coexistence values, a tanh interface between
+    r0[r0 < g + 1e-3 * (l - g)] = g
+    r0[r0 > l - 1e-3 * (l - g)] = l
+    h = r0.reshape(-1)
+    target = float(h.sum()) * (1 + 3e-7)
+    outs = []
+    for _ in range(2):
+        d = torch.from_numpy(h.copy()).cuda()
+        scratch = torch.empty(int(lbm.lib().lbm_sum_scratch_bytes(d.numel())) // 8 + 1, dtype=torch.float64,
+                              device="cuda")
+        st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        lbm._check(lbm.lib().lbm_interface_mass(C.c_void_p(d.data_ptr()), d.numel(), g, l, target,
+                                                C.c_void_p(scratch.data_ptr()), st))
+        outs.append(d.cpu().numpy())
+    a, b = outs
+    assert np.array_equal(a, b)
+    assert abs(learned.device_sum(torch.from_numpy(a).cuda()) - target) <= 1e-13 * target
+    phi = np.clip((h - g) / (l - g), 0.0, 1.0)
+    w = phi * (1 - phi)
+    flat = w == 0.0
+    assert flat.sum() > h.size // 2 and np.array_equal(a[flat], h[flat])
+    # a - h = c w with one constant c, to the rounding of the sum r + c w
+    c = np.median((a - h)[~flat] / w[~flat])
+    assert c > 0
+    assert np.abs((a - h) - c * w).max() <= 4 * np.spacing(l)
+    # bad arguments are refused before any launch
+    assert lbm.lib().lbm_interface_mass(C.c_void_p(d.data_ptr()), d.numel(), l, g, target,
+                                        C.c_void_p(scratch.data_ptr()), st) == lbm.LBM_EINVAL

@@ -349,3 +349,19 @@ def test_tile_design(L, orc, lat, shape, scheme, tau, coll):
         a.step(40)
         assert np.abs(a.populations() - b.populations()).max() < 1e-13, v
         _compare(a, o)
+
+
+def test_device_rho0_outside_its_range_is_refused(L):
+    """A device rho0 goes through the same range check as a host one: a single
+    node that is not finite or lies outside (0, 1/b) gives LBM_EINVAL."""
+    import torch
+    p = L.Params(lattice=L.D2Q9, nx=40, ny=36, Tr=0.8, scheme=L.CD4)
+    good = torch.full((p.n,), 3.0, dtype=torch.float64, device="cuda")
+    L.Simulation(p, good).close()
+    for bad in (-1.0, 0.0, 10.5, float("nan"), float("inf")):
+        r = good.clone()
+        r[777] = bad
+        print(f"case device rho0 with one node at {bad}", flush=True)
+        with pytest.raises(L.LbmError) as e:
+            L.Simulation(p, r)
+        assert e.value.code == L.LBM_EINVAL and "outside (0, 1/b)" in str(e.value)
