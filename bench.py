@@ -92,7 +92,7 @@ def kernel_source_hash() -> str:
 def traffic_record(kernel: str, workload: str, variant=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources, this workload and this launch
-    variant; else None."""
+    variant (by name, as lbm_variant_name gives it); else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -104,6 +104,18 @@ def traffic_record(kernel: str, workload: str, variant=None):
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
+
+
+def cpu_model() -> str:
+    """Model name of the host CPU (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(args, p, rho0, solid=None):
@@ -120,7 +132,7 @@ def cpu_baseline(args, p, rho0, solid=None):
     dt = time.perf_counter() - t0
     del sim
     return {"value": round(p.n * args.cpu_steps / dt / 1e6, 4), "unit": "MLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": oracle.num_threads(), "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"same {p.nx}x{p.ny}x{p.nz} grid and inputs, {args.cpu_steps} steps after 1 warm-up, "
                       f"{dt:.2f} s wall time, OpenMP over nodes"}
 
@@ -217,7 +229,8 @@ def main():
     if args.wall > 0:
         workload += f" wall={args.wall}"
     chosen = min((v for v in tuned if tuned[v] is not None), key=lambda v: tuned[v], default=None)
-    traffic = traffic_record(kname, workload, chosen)
+    chosen_name = sim.variant_name(chosen) if chosen is not None else None
+    traffic = traffic_record(kname, workload, chosen_name)
     out = {
         "metric": "MLUPS D3Q19 FP64 (% HBM roofline)" if lat == lbm.D3Q19 else "MLUPS D2Q9 FP64",
         "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -225,7 +238,8 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload, "lattice": args.lattice, "grid": list(shape), "scheme": args.scheme,
                    "Tr": args.Tr, "k": args.k, "kappa": args.kappa, "tau": 1.0, "nodes": p.n},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "scope": f"dominant kernel {kname} (step_frac: the whole step)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kname, "kernel_ms": round(kernel_ms, 4),
                      "algorithmic_bytes_per_node": kbytes, "nodes_per_launch": p.n,
@@ -235,7 +249,7 @@ def main():
         "tuner_ms_per_variant": {f"{k} {sim.variant_name(k)}": (round(v, 4) if v is not None else None)
                                  for k, v in tuned.items()},
         "variant": chosen,
-        "variant_name": sim.variant_name(chosen) if chosen is not None else None,
+        "variant_name": chosen_name,
         "spurious_current": U, "mass": M, "status": code,
         # which steps of the run the timed region covered (the tuner and the
         # warm-up advance the state first); U and status are taken after them

@@ -325,6 +325,57 @@ def droplet_set_3d(n, seed, r_frac=(0.22, 0.32), tr_range=(0.65, 0.85), k_range=
     return out
 
 
+def big_droplet(net: Net, scheme: int, L: int = 384, R: float = 80.0, Tr: float = 0.8, k: float = 0.1,
+                max_steps: int = 40000, check_every: int = 100, tol: float = 1e-10, report_every: int = 2000):
+    """The config-5 geometry (D3Q19 L^3 periodic, droplet of radius R at the
+    centre) from the tanh start of Eq 26 (width 10) and from the learned start
+    (same mass), each run on a plain context until |U(t) - U(t - 100)| < tol
+    or max_steps.  Returns one row per start: status, steps, U, rho_l at the
+    centre, rho_g at the corner, MLUPS of the stepping, and the U history."""
+    import torch
+    g, l = lbm.coexistence(Tr)
+    p = lbm.Params(lattice=lbm.D3Q19, nx=L, ny=L, nz=L, Tr=Tr, k=k, kappa=0.004, scheme=scheme)
+    r_t = inputs.droplet((L, L, L), R, 10.0, g, l, instance_id=30000 + scheme, relative=True)
+    rho, _ = mass_matched_field(net, p, R, Tr, k, scheme, g, l, float(r_t.sum()))
+    rows = {}
+    for name, r0 in (("tanh", r_t), ("learned", rho if rho is not None else r_t)):
+        sim = lbm.Simulation(p, torch.from_numpy(r0.reshape(-1)).cuda() if isinstance(r0, np.ndarray) else r0)
+        # the fastest collide on 256^3 and 384^3 (no tuner: it would advance the state)
+        names = [sim.variant_name(v) for v in range(sim.num_variants)]
+        if "tile 64x16 z64" in names:
+            sim.set_variant(names.index("tile 64x16 z64"))
+        steps, U_prev, status, hist, t_step = 0, None, lbm.RUNNING, [], 0.0
+        while True:
+            U = float(sim.spurious_max()[0])
+            if steps % report_every == 0:
+                hist.append((steps, U))
+                log(f"big droplet {L}^3 scheme {scheme} {name}: step {steps} U {U:.6e}")
+            if not np.isfinite(U) or U > 3 ** -0.5:
+                status = lbm.DIVERGED
+                break
+            if U_prev is not None and abs(U - U_prev) < tol:
+                status = lbm.CONVERGED
+                break
+            if steps >= max_steps:
+                break
+            U_prev = U
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(check_every)
+            torch.cuda.synchronize()
+            t_step += time.perf_counter() - t0
+            steps += check_every
+        r = sim.macros()[0] if status != lbm.DIVERGED else None
+        rows[name] = dict(status=int(status), steps=steps, U=U, fallback=rho is None and name == "learned",
+                          rho_l=float(r[L // 2, L // 2, L // 2]) if r is not None else None,
+                          rho_g=float(r[0, 0, 0]) if r is not None else None,
+                          mlups=p.n * steps / t_step / 1e6 if t_step > 0 else None, history=hist)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return dict(L=L, R=R, Tr=Tr, k=k, scheme=scheme, rho_g_maxwell=g, rho_l_maxwell=l, runs=rows)
+
+
 def run_to_equilibrium(p: lbm.Params, rho0, max_steps, check_every=100, tol=1e-10):
     """One plain context from rho0 under the convergence rule of the batched
     sweep: U = max|v| is taken every check_every steps before stepping on;
@@ -414,7 +465,18 @@ def main():
                     help="also this many 3D (D3Q19) droplets, tanh vs learned start, each run to equilibrium")
     ap.add_argument("--max-steps-3d", type=int, default=60000)
     ap.add_argument("--tol", type=float, default=1e-10, help="convergence: |U(t) - U(t - 100)| < tol")
+    ap.add_argument("--big", default="", help="comma-separated schemes: the config-5 droplet (D3Q19 384^3, R 80) "
+                                              "at --big-Tr from the tanh and the learned start")
+    ap.add_argument("--big-Tr", type=float, default=0.8)
+    ap.add_argument("--big-n", type=int, default=384)
     a = ap.parse_args()
+    if a.big:
+        net = Net(0)
+        net.load(np.load(a.load))
+        res = [big_droplet(net, lbm.SCHEMES[sname], L=a.big_n, R=80.0 * a.big_n / 384, Tr=a.big_Tr,
+                           max_steps=a.max_steps_3d, tol=a.tol) for sname in a.big.split(",")]
+        print(json.dumps(res))
+        return
     import os
     import torch
     t0 = time.perf_counter()

@@ -73,7 +73,10 @@ def run(args):
     g, l = lbm.coexistence(args.Tr)
     sim = lbm.Simulation(p, torch.from_numpy(inputs.droplet(shape, 0.25 * n, 10.0, g, l).reshape(-1)).cuda())
     if args.variant is not None:
-        sim.set_variant(args.variant)
+        names = [sim.variant_name(v) for v in range(sim.num_variants)]
+        if args.variant not in names:
+            sys.exit(f"no launch variant named {args.variant!r}; this workload has {names}")
+        sim.set_variant(names.index(args.variant))
     sim.step(args.steps)
     torch.cuda.synchronize()
     print(f"profiled {workload_name(args.lattice, n, args.Tr, args.scheme, args.k)} variant {args.variant} "
@@ -174,7 +177,8 @@ def main():
     r.add_argument("--k", type=float, default=0.1)
     r.add_argument("--kappa", type=float, default=0.004)
     r.add_argument("--steps", type=int, default=5)
-    r.add_argument("--variant", type=int, default=None, help="launch variant (default: the library's)")
+    r.add_argument("--variant", default=None,
+                   help="launch variant by name, e.g. 'tile 64x16 z64' (default: the library's)")
     r.add_argument("--probe", action="store_true",
                    help="profile the population copy (lbm_probe_copy) on the grid instead of the step")
     s = sub.add_parser("summarize")
@@ -183,7 +187,7 @@ def main():
     s.add_argument("--trace", required=True)
     s.add_argument("--workload", required=True)
     s.add_argument("--kernel", default="k_ring")
-    s.add_argument("--variant", type=int, default=None, help="launch variant the counter runs used")
+    s.add_argument("--variant", default=None, help="name of the launch variant the counter runs used")
     s.add_argument("--commands", default="")
     s.add_argument("--out", required=True)
     a = ap.parse_args()

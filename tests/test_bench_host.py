@@ -29,6 +29,11 @@ def test_algorithmic_bytes_per_node():
     assert bench.kernel_bytes_per_node("k_mu_march", 19, 3, "CD6") == 16
     assert bench.kernel_bytes_per_node("k_force_march", 19, 3, "CD6") == 40
     assert bench.kernel_bytes_per_node("k_collide", 19, 3, "OCFDS4") == 8 * (19 + 6 + 19)
+    assert bench.kernel_bytes_per_node("k_mf", 19, 3, "CD6") == 32
+
+
+def test_cpu_model_is_named():
+    assert bench.cpu_model() != ""
 
 
 def test_traffic_record_lookup():
@@ -43,5 +48,5 @@ def test_traffic_record_lookup():
         else:
             assert got is None          # stale: taken on other kernel sources
         # another launch variant never borrows this record
-        assert bench.traffic_record(kernel, workload, 999) is None
+        assert bench.traffic_record(kernel, workload, "no such variant") is None
 
