@@ -152,7 +152,7 @@ __device__ __forceinline__ void collide(const double (&f)[Lat<LAT>::Q], double r
 
 // ---------------------------------------------------------------------------
 // Peng-Robinson bulk chemical potential psi'(rho) (Eq 15 without the gradient
-// term, integration constant zero), scaled by k^2 (Eq 16).  With x = b rho,
+// term, integration constant zero), scaled by k^2 (Eq 16), for 0 < rho < 1/b.  With x = b rho,
 // g = 1 - x, A = sqrt2 - 1 + x, B = sqrt2 + 1 - x and A B = 1 + 2x - x^2:
 //   psi' = RT ln(rho/g) - aa/(2 sqrt2 b) ln(A/B) + RT/g - aa rho/(A B).
 // The three quotients share one division.
@@ -173,11 +173,9 @@ struct Eos {
 // relative), then e ln2 added with ln2 split into a 42-bit head (e * head is
 // exact) and a tail.  About a third of the instructions of the library log,
 // within a few ulp of it; the chemical potential evaluates two per node.
-// Outside its domain (x <= 0 or NaN) the result is NaN, as the library log's,
-// so a state driven to a negative density reports itself non-finite.
+// Domain: positive doubles; mu_bulk below guards its arguments.
 __host__ __device__ __forceinline__ double log_pos(double x)
 {
-    if (!(x > 0.0)) return __builtin_nan("");
     int ex;
     double m = frexp(x, &ex);   // m in [0.5, 1)
     if (m < 0.70710678118654752440) { m += m; ex -= 1; }
@@ -209,7 +207,12 @@ __host__ __device__ __forceinline__ double mu_bulk(double rho, const Eos& e)
     const double inv_g = (A * B) * inv;
     const double inv_B = (g * A) * inv;
     const double inv_AB = g * inv;
-    return e.k2RT * (log_pos(rho * inv_g) + inv_g) - e.k2c * log_pos(A * inv_B) - e.k2aa * rho * inv_AB;
+    const double mu = e.k2RT * (log_pos(rho * inv_g) + inv_g) - e.k2c * log_pos(A * inv_B) - e.k2aa * rho * inv_AB;
+    // both logarithms have positive arguments exactly for 0 < rho < 1/b;
+    // outside (or for NaN) the potential is NaN, as with the library log, so a
+    // state driven out of the EOS's range reports itself non-finite.  A
+    // select, not a branch: the kernels keep one straight-line path.
+    return (rho > 0.0 && g > 0.0) ? mu : __builtin_nan("");
 }
 
 }  // namespace lbm

@@ -2,7 +2,8 @@
 (log_pos in csrc/lbm_physics.hpp), compiled for the host with g++ and compared
 with the x86 extended-precision logl on arguments spread over the whole double
 range, dense near 1 and around the reduction boundary sqrt(1/2).  Its domain is
-the positive doubles; it returns NaN for x <= 0 and NaN, as the library log."""
+the positive doubles; the chemical potential that calls it (mu_bulk) is NaN
+outside 0 < rho < 1/b and for NaN, as with the library log."""
 import os
 import subprocess
 
@@ -53,10 +54,14 @@ int main()
         take(1e-16 + 11.0 * (double)(next() >> 11) * 0x1p-53);
         n++;
     }
-    const double nan_neg = lbm::log_pos(-1.5), nan_zero = lbm::log_pos(0.0), nan_mzero = lbm::log_pos(-0.0);
-    const double nan_nan = lbm::log_pos(std::nan(""));
+    lbm::Eos e{};
+    e.k2RT = 0.02; e.k2c = 0.5; e.k2aa = 0.04; e.b = 2.0 / 21.0; e.kappa = 0.004;
+    const double nan_neg = lbm::mu_bulk(-1.5, e), nan_zero = lbm::mu_bulk(0.0, e), nan_big = lbm::mu_bulk(10.6, e);
+    const double nan_nan = lbm::mu_bulk(std::nan(""), e);
+    if (!std::isfinite(lbm::mu_bulk(3.0, e)) || !std::isfinite(lbm::mu_bulk(1e-12, e)) || !std::isfinite(lbm::mu_bulk(10.49, e)))
+        return 2;
     std::printf("%ld %.6f %.17g %d %d %d %d\n", n, worst, wx, (int)std::isnan(nan_neg), (int)std::isnan(nan_zero),
-                (int)std::isnan(nan_mzero), (int)std::isnan(nan_nan));
+                (int)std::isnan(nan_big), (int)std::isnan(nan_nan));
     return 0;
 }
 """
@@ -81,5 +86,6 @@ def test_log_pos_within_two_ulp(harness):
     assert worst <= 2.0, (worst, wx)
 
 
-def test_log_pos_nan_outside_its_domain(harness):
+def test_chemical_potential_nan_outside_the_eos_range(harness):
+    # mu_bulk at rho = -1.5, 0, 10.6 (above 1/b = 10.5) and NaN is NaN; at 1e-12, 3 and 10.49 finite
     assert harness[3:] == ["1", "1", "1", "1"]
