@@ -110,11 +110,19 @@ def _calibration(d, counter):
     return max(vals) if vals else None
 
 
+def _base(name: str) -> str:
+    """Kernel name without return type, namespace, template arguments and
+    parameter list ("void lbm::k_tile<1, 16, true, false>(...)" -> "k_tile")."""
+    return name.split("<")[0].split("(")[0].replace("void ", "").replace("lbm::", "").strip()
+
+
 def _match(means, key):
-    for k, v in means.items():
-        if key in k:
-            return k, v
-    return None, None
+    """Counter mean of the kernel whose base name equals that of key (several
+    instantiations of one kernel share it: their means are averaged)."""
+    vals = [v for k, v in means.items() if _base(k) == _base(key)]
+    if not vals:
+        return None, None
+    return _base(key), sum(vals) / len(vals)
 
 
 def summarize(args):
@@ -147,7 +155,7 @@ def summarize(args):
             scaled = (fv * f_scale + wv * w_scale) * 1024.0
         lines.append(f"| {name[:70]} | {r.get('Calls')} | {avg_us:.1f} | {fv if fv is None else round(fv)} | "
                      f"{wv if wv is None else round(wv)} | {scaled if scaled is None else round(scaled)} |")
-        short = name.split("<")[0].split("(")[0].replace("void ", "").replace("lbm::", "")
+        short = _base(name)
         if scaled is not None:
             rec[short] = {"avg_us": avg_us, "bytes": scaled}
     dom = args.kernel
