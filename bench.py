@@ -13,8 +13,10 @@ dominant kernel (its algorithmic bytes per node times the nodes of one launch,
 over its average launch duration from HIP events on the step's stream, against
 the 8 TB/s HBM3E peak), the same for the whole step ((2Q+2)*8 bytes per node),
 both also as fractions of the measured rate of a plain copy of the Q
-population arrays on the same grid (aligned, and as the streaming pull), and
-the CPU oracle timed on a bounded sample of the same workload.
+population arrays on the same grid (aligned, and as the streaming pull), the
+metric's second part (steps to equilibrium from the learned start against the
+tanh start, 16 held-out D2Q9 droplets on the batched kernel), and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -45,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps timed for the CPU baseline (about 15 s on 16 host threads at 256^3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the steps-to-equilibrium comparison of the learned and the tanh start")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--wall", type=int, default=0,
                     help="solid floor this many nodes thick under the droplet (wetting boundary; 0 = periodic)")
@@ -172,6 +176,20 @@ def copy_ceiling(lat, shape, reps=10):
     return out
 
 
+def learned_vs_tanh():
+    """The metric's second part: steps to equilibrium from the shipped
+    network's start against the tanh start, on 16 held-out D2Q9 droplets run
+    by the batched kernel to |U(t) - U(t - 100)| < 1e-12."""
+    from paper_2205_09186_amd import learned, lbm
+    try:
+        sm, _ = learned.gain(n=16, seed=60, lmax=128, tol=1e-12)
+    except lbm.LbmError as e:
+        return {"error": str(e)}
+    sm["workload"] = ("16 held-out D2Q9 droplets, L 64-128, R 12-50, six schemes each at a T_r where SRT runs, "
+                      "k 0.1-0.25, kappa-hat 0.004; steady when |U(t) - U(t - 100)| < 1e-12")
+    return {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in sm.items()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -264,6 +282,8 @@ def main():
     ceil["kernel_frac_of_pull_copy"] = round(achieved / ceil["pull_copy_GBps"], 4)
     ceil["step_frac_of_pull_copy"] = round(step_gbs / ceil["pull_copy_GBps"], 4)
     out["roofline"]["ceiling"] = ceil
+    if not args.no_learned:
+        out["learned_vs_tanh"] = learned_vs_tanh()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args, p, rho0, solid)
     print(json.dumps(out), flush=True)

@@ -248,7 +248,12 @@ const char* lbm_batch_launch_mode(const lbm_batch* b);
 /* Advance running instances by up to nsteps steps, in launches of at most
  * `chunk` steps; stops early once every instance has retired.  Host outputs
  * (n entries each, any may be NULL): status (LBM_RUNNING/CONVERGED/DIVERGED),
- * completed steps, and U at the last check.  Synchronises. */
+ * completed steps, and U at the last check.  Synchronises.  LBM_EHIP if the
+ * runtime refuses the cooperative launch (ROCm does while another process
+ * holds the device), or runs it without the grid barrier (the kernel then
+ * returns at once); no step of that launch is taken.  A graph replay that did
+ * not run the kernel to its end (a completion count the kernel keeps shows
+ * it) is retried as a plain cooperative launch. */
 int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long chunk,
                   int* status, long* steps, double* umax);
 

@@ -1120,7 +1120,11 @@ struct lbm_batch {
     int* d_blk_inst = nullptr;
     double* d_partial = nullptr;
     BLine* d_lines = nullptr;
-    int* d_flag = nullptr;      // set by k_batch if a launch was not cooperative
+    // d_flag[0]: set by k_batch if a launch was not cooperative; d_flag[1]:
+    // launches that k_batch completed (h_flag: their read-back), against
+    // `launches`, the count the host expects
+    int* d_flag = nullptr;
+    unsigned launches = 0;
     BState* h_st = nullptr;     // pinned host copies read after every chunk
     int* h_flag = nullptr;
     int nblk_total = 0;
@@ -1177,7 +1181,7 @@ bool batch_layout(const lbm_params* ps, int n, BatchLayout& B, const char** why)
     off = align_up(off + sizeof(int) * B.nblk);
     off = align_up(off + sizeof(double) * B.nblk);
     off = align_up(off + sizeof(BLine) * std::max(1, B.nlines));
-    off = align_up(off + sizeof(int));
+    off = align_up(off + 2 * sizeof(int));
     B.total = off;
     return true;
 }
@@ -1275,7 +1279,7 @@ hipError_t batch_graph(lbm_batch* b, const BatchArgs& a, hipGraphExec_t* out, st
         if (l == hipSuccess)
             l = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost, b->cap_stream);
         if (l == hipSuccess)
-            l = hipMemcpyAsync(b->h_flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost, b->cap_stream);
+            l = hipMemcpyAsync(b->h_flag, b->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, b->cap_stream);
         e = hipStreamEndCapture(b->cap_stream, &g);
         if (e == hipSuccess) e = l;
         if (e == hipSuccess && !g) e = hipErrorInvalidValue;
@@ -1308,7 +1312,8 @@ hipError_t batch_graph(lbm_batch* b, const BatchArgs& a, hipGraphExec_t* out, st
             e = hipGraphAddMemcpyNode1D(&m1, g, &kn, 1, b->h_st, b->d_st, sizeof(BState) * b->n,
                                         hipMemcpyDeviceToHost);
         if (e == hipSuccess)
-            e = hipGraphAddMemcpyNode1D(&m2, g, &m1, 1, b->h_flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost);
+            e = hipGraphAddMemcpyNode1D(&m2, g, &m1, 1, b->h_flag, b->d_flag, 2 * sizeof(int),
+                                        hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = ensure_cooperative(g);
         how = "graph: cooperative kernel node (stream capture of the cooperative launch failed: " + first + ")";
     }
@@ -1394,14 +1399,14 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     b->nlines = (int)lines.size();
     std::vector<BState> st(n);
     for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.stop = -1; x.U = 0.0; x.U_prev = 0.0; }
-    static const int zero = 0;
+    static const int zero[2] = { 0, 0 };
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_st), sizeof(BState) * n, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_flag), sizeof(int), hipHostMallocDefault);
-    if (e == hipSuccess) *b->h_flag = 0;
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_flag), 2 * sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) b->h_flag[0] = b->h_flag[1] = 0;
     if (e == hipSuccess && !lines.empty())
         e = hipMemcpyAsync(b->d_lines, lines.data(), sizeof(BLine) * lines.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_st, st.data(), sizeof(BState) * n, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_flag, zero, 2 * sizeof(int), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = batch_tables(b);
     int dev = 0, ncu = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
@@ -1472,6 +1477,7 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
         a.check_every = (int)check_every;
         a.tol = tol;
         a.not_cooperative = b->d_flag;
+        a.launches = reinterpret_cast<unsigned*>(b->d_flag + 1);
         hipError_t e = hipSuccess;
         bool replayed = false;
         if (b->use_graph) {
@@ -1497,17 +1503,20 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
             if (gr) {
                 e = hipGraphLaunch(gr->exec, b->stream);
                 if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-                if (e == hipSuccess && *b->h_flag) {
-                    // the replay did not launch cooperatively: the kernel
-                    // returned at once, so this chunk runs again below
+                if (e == hipSuccess && (b->h_flag[0] || (unsigned)b->h_flag[1] != b->launches + 1)) {
+                    // the replay did not launch cooperatively (the kernel
+                    // returned at once) or did not run the kernel to its end:
+                    // no step was taken, so this chunk runs again below
                     static const int zero = 0;
                     e = hipMemcpyAsync(b->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
                     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+                    b->h_flag[0] = 0;
                     drop_graphs(b);
                     b->use_graph = false;
-                    b->mode = "plain cooperative launches (a graph replay was not cooperative)";
-                } else {
-                    replayed = e == hipSuccess;
+                    b->mode = "plain cooperative launches (a graph replay did not run the kernel cooperatively)";
+                } else if (e == hipSuccess) {
+                    b->launches++;
+                    replayed = true;
                 }
             }
         }
@@ -1516,9 +1525,28 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
             e = hipLaunchCooperativeKernel(batch_kernel(b->block), dim3(b->grid), dim3(b->block), args, 0, b->stream);
             if (e == hipSuccess) e = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost,
                                                     b->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(b->h_flag, b->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+            if (e == hipSuccess && (b->h_flag[0] || (unsigned)b->h_flag[1] != b->launches + 1)) {
+                // the kernel found no grid barrier and returned at once, or
+                // did not run: no step of this launch was taken
+                static const int zero = 0;
+                b->h_flag[0] = 0;
+                (void)hipMemcpyAsync(b->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
+                (void)hipStreamSynchronize(b->stream);
+                return bfail(b, LBM_EHIP, "the runtime did not run the batch kernel as a cooperative launch "
+                                          "(no grid barrier, or no run); no step was taken");
+            }
+            if (e == hipSuccess) b->launches++;
         }
-        if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+        if (e != hipSuccess) {
+            // the error is returned, not left for the caller's next runtime
+            // call (this runtime refuses cooperative launches, for one, while
+            // another process holds the device)
+            (void)hipGetLastError();
+            return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+        }
         ran = true;
         done += todo;
         bool running = false;

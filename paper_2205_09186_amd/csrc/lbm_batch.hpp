@@ -181,6 +181,7 @@ struct BatchArgs {
     int check_every;
     double tol;
     int* not_cooperative;     // set (and nothing else done) if the launch was not cooperative
+    unsigned* launches;       // completed launches: one more at the end of each
 };
 
 __device__ __forceinline__ void bar(cooperative_groups::grid_group& gg) { gg.sync(); }
@@ -370,6 +371,9 @@ __global__ void __launch_bounds__(BNODES) k_batch(BatchArgs a)
         else if (S.stop >= 0) S.steps += S.stop;
         S.stop = -1;
     }
+    // the host compares this count with the launches it made: a launch that
+    // did not run to here (or at all) shows as a missing count
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.launches += 1u;
 }
 
 }  // namespace lbm

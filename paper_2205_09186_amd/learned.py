@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import ctypes as C
 import json
+import os
 import sys
 import time
 
@@ -309,6 +310,76 @@ def evaluate(net: Net, n=64, seed=7, max_steps=30000, check_every=100, tol=1e-10
     return summary, out
 
 
+NET_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "learned_net.npy")
+
+
+def gain(net: Net = None, n: int = 16, seed: int = 60, lmax: int = 128, tol: float = 1e-12,
+         max_steps: int = 300000, check_every: int = 100, chunk: int = 20000):
+    """What the learned start gains over the tanh start (Eq 26, width 10):
+    n held-out D2Q9 droplets (a seed disjoint from the training and earlier
+    evaluation sets; each scheme in the temperature range where it runs under
+    SRT) from both starts, mass-matched, run by the batched kernel until
+    |U(t) - U(t - check_every)| < tol.  Droplets that end as droplets from
+    both starts (centre density above 1.5 x the corner's) are compared: the
+    ratio of steps, the final U and the centre (rho_l) and corner (rho_g)
+    densities.  Returns (summary, rows)."""
+    import torch
+    if net is None:
+        net = Net(0)
+        net.load(np.load(NET_PATH))
+    specs = droplet_set(n, seed=seed, lmax=lmax)
+    ps, rs = _tanh_batch(specs)
+    starts, fallback = [], 0
+    for p, r, d in zip(ps, rs, specs):
+        g, l = lbm.coexistence(d["Tr"])
+        rho, _ = mass_matched_field(net, p, d["R"], d["Tr"], d["k"], d["scheme"], g, l, float(r.sum()))
+        if rho is None or not bool(torch.isfinite(rho).all()):
+            fallback += 1
+            starts.append(r)
+        else:
+            starts.append(rho.cpu().numpy().reshape(r.shape))
+    res = {}
+    for name, rhos in (("tanh", rs), ("learned", starts)):
+        b = lbm.Batch(ps, rhos)
+        t0 = time.perf_counter()
+        st, steps, U = b.run(max_steps, check_every=check_every, tol=tol, chunk=chunk)
+        wall = time.perf_counter() - t0
+        dens = []
+        for i, d in enumerate(specs):
+            rr = b.instance(i).macros()[0]
+            dens.append((float(rr[d["L"] // 2, d["L"] // 2]), float(rr[0, 0])))
+        res[name] = (st, steps, U, dens, wall, b.launch_mode)
+        b.close()
+    t, lrn = res["tanh"], res["learned"]
+    rows = []
+    for i, d in enumerate(specs):
+        row = dict(L=d["L"], R=d["R"], scheme=int(d["scheme"]), Tr=d["Tr"], k=d["k"],
+                   status=(int(t[0][i]), int(lrn[0][i])), steps=(int(t[1][i]), int(lrn[1][i])))
+        ok = t[0][i] == lbm.CONVERGED and lrn[0][i] == lbm.CONVERGED
+        if ok and t[3][i][0] > 1.5 * t[3][i][1] and lrn[3][i][0] > 1.5 * lrn[3][i][1]:
+            row.update(ratio=lrn[1][i] / t[1][i], dU=abs(lrn[2][i] - t[2][i]) / abs(t[2][i]),
+                       dl=abs(lrn[3][i][0] - t[3][i][0]) / t[3][i][0],
+                       dg=abs(lrn[3][i][1] - t[3][i][1]) / t[3][i][1])
+        rows.append(row)
+    cmp_ = [r for r in rows if "ratio" in r]
+    ratio = np.array([r["ratio"] for r in cmp_])
+    dU = np.array([r["dU"] for r in cmp_])
+    summary = dict(
+        droplets=n, fallback=fallback, compared=len(cmp_),
+        steps_ratio_median=float(np.median(ratio)) if cmp_ else None,
+        learned_fewer_steps=int((ratio < 1).sum()),
+        steps_saved_total=(float(1 - sum(int(x) for x in lrn[1]) / sum(int(x) for x in t[1]))
+                           if sum(int(x) for x in t[1]) > 0 else None),
+        U_reldiff_median=float(np.median(dU)) if cmp_ else None,
+        U_reldiff_max=float(dU.max()) if cmp_ else None,
+        U_within_1e6=int((dU <= 1e-6).sum()),
+        rho_l_reldiff_max=max((r["dl"] for r in cmp_), default=None),
+        rho_g_reldiff_max=max((r["dg"] for r in cmp_), default=None),
+        wall_s={"tanh": round(t[4], 2), "learned": round(lrn[4], 2)},
+        launch={"tanh": t[5], "learned": lrn[5]})
+    return summary, rows
+
+
 def droplet_set_3d(n, seed, r_frac=(0.22, 0.32), tr_range=(0.65, 0.85), k_range=(0.1, 0.25), sides=(96, 128)):
     """Seeded 3D droplets (D3Q19, L^3 periodic) for the learned start in 3D.
     The radius is a fraction of the box: smaller droplets evaporate into the
@@ -477,7 +548,6 @@ def main():
                            max_steps=a.max_steps_3d, tol=a.tol) for sname in a.big.split(",")]
         print(json.dumps(res))
         return
-    import os
     import torch
     t0 = time.perf_counter()
     if a.dump:

@@ -1,6 +1,10 @@
 """Batched sweep (cooperative persistent kernel) against independent plain runs
 of each instance, retirement of converged / diverged instances, and launch
 size independence."""
+import os
+import subprocess
+import sys
+
 import numpy as np
 import pytest
 
@@ -230,3 +234,48 @@ def test_batch_block_sizes_give_the_same_state(L):
                 assert np.array_equal(x, y), bn
     with pytest.raises(L.LbmError):
         b.set_block(300)
+
+
+_SECOND_PROCESS = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+from paper_2205_09186_amd import inputs, lbm
+g, l = lbm.coexistence(0.8)
+ps = [lbm.Params(lattice=lbm.D2Q9, nx=48, ny=48, Tr=0.8, k=0.16, kappa=0.004, scheme=lbm.CD4)]
+b = lbm.Batch(ps, [inputs.droplet((48, 48), 12, 4.0, g, l)])
+try:
+    st, steps, _ = b.run(200, check_every=100, tol=0.0, chunk=100)
+    print("ran", int(steps[0]), int(st[0]), b.launch_mode, flush=True)
+except lbm.LbmError as e:
+    print("refused", e, flush=True)
+# the refusal is not left behind for the next runtime call
+import torch
+x = torch.ones(4, device="cuda")
+print("after", float(x.sum()), flush=True)
+"""
+
+
+def test_batch_in_a_second_process_runs_or_reports(L):
+    """While this process holds the device (and a batch of its own), a batch
+    in a second process either takes every step it is asked for or reports
+    the refused cooperative launch as LbmError; it never returns with the
+    steps silently not taken, and leaves no error behind."""
+    ps, rs = _build(L, _specs(L)[:2])
+    mine = L.Batch(ps, rs)
+    mine.run(50, check_every=50, tol=0.0, chunk=50)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-u", "-c", _SECOND_PROCESS, root], capture_output=True, text=True,
+                         timeout=180)
+    print("case batch in a second process:", out.stdout.strip(), flush=True)
+    assert out.returncode == 0, out.stderr[-2000:]
+    lines = out.stdout.strip().splitlines()
+    first = lines[0].split()
+    assert first[0] in ("ran", "refused")
+    if first[0] == "ran":
+        assert first[1] == "200" and first[2] == str(L.RUNNING)
+    else:
+        assert "cooperative" in lines[0] or "batch launch" in lines[0]
+    assert lines[-1] == "after 4.0"
+    # this process's batch is unaffected
+    st, steps, _ = mine.run(50, check_every=50, tol=0.0, chunk=50)
+    assert list(steps) == [100, 100]

@@ -18,9 +18,12 @@ def test_bench_json_line():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    # --no-learned: the learned-start comparison runs on the batched kernel's
+    # cooperative launches, which the runtime refuses in a second process
+    # while this one holds the device (test_gpu_learned_gain runs it here)
     out = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--n", "64", "--steps", "5",
-                          "--warmup", "2", "--cpu-steps", "1"], capture_output=True, text=True, timeout=240,
-                         cwd=ROOT)
+                          "--warmup", "2", "--cpu-steps", "1", "--no-learned"], capture_output=True, text=True,
+                         timeout=240, cwd=ROOT)
     print(out.stderr[-2000:], flush=True)
     assert out.returncode == 0
     lines = [l for l in out.stdout.splitlines() if l.strip()]
