@@ -193,8 +193,8 @@ def learned_vs_tanh():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU runs are not part "
-                                   "of it)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 (the library has no multi-GPU "
+                                   "path)", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
