@@ -144,6 +144,28 @@ int lbm_populations(lbm_ctx* c, double* f, int out_on_device);
 /* Number of completed steps of the context. */
 long lbm_steps_done(const lbm_ctx* c);
 
+/* Checkpoint and restart.  The state between two steps is the populations
+ * of Eq 1 after the collision, held at their source nodes (the next step
+ * streams them as it pulls), and the density of Eq 7 from which the next
+ * step's chemical potential (Eq 16) starts.  A state image is a 64-byte
+ * header (eight int64: magic, layout version, lattice, nx, ny, nz, completed
+ * steps, spare), then those Q*N populations (f[q*N + node], x fastest) and
+ * the N densities, FP64.  It is this library's own layout, not the
+ * post-streaming populations that lbm_populations gives.
+ *
+ * lbm_state_bytes: the size of an image of c (0 if c is NULL).
+ * lbm_save_state: writes the image to host (on_device == 0) or device memory
+ *   of at least lbm_state_bytes bytes, owned by the caller.  Synchronises.
+ * lbm_load_state: replaces c's state and step count by an image that
+ *   lbm_save_state wrote for the same lattice and grid size (the other
+ *   parameters may differ); stepping on then continues bitwise as the saved
+ *   run would have, for any launch variant.  LBM_EINVAL if the header is not
+ *   an image of this lattice and size, LBM_ESTATE for a batch instance (the
+ *   batch owns its state).  Synchronises. */
+size_t lbm_state_bytes(const lbm_ctx* c);
+int lbm_save_state(lbm_ctx* c, void* out, int on_device);
+int lbm_load_state(lbm_ctx* c, const void* in, int on_device);
+
 /* Profiling: run nsteps >= 1 steps with a HIP event on the context's stream at
  * every phase boundary of the step (a phase is one kernel on the fused path).
  * ms[k] (k < cap) receives the mean duration of phase k per step and

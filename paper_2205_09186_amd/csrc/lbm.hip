@@ -160,6 +160,7 @@ struct lbm_ctx {
     hipStream_t cap_stream = nullptr;
     int graph_cur = -1, graph_variant = -1;
     bool use_graph = true;
+    bool in_batch = false;   // an instance of a batch (stepped by the batched kernel)
     // fewest lines for which the compact line solves take the segmented
     // kernels (lanes across neighbouring lines, coalesced): along y and z
     // where there are enough lines to fill the chip (fewer lines go one
@@ -976,6 +977,78 @@ int lbm_populations(lbm_ctx* c, double* f, int out_on_device)
 
 long lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
 
+namespace {
+
+// Header of a state image: magic, layout version, lattice, nx, ny, nz,
+// completed steps, one spare word.
+constexpr long long kStateMagic = 0x4554415453424C4CLL;   // "LLBSTATE" read as little-endian bytes
+constexpr long long kStateVersion = 1;
+constexpr size_t kStateHeader = 64;
+
+}  // namespace
+
+size_t lbm_state_bytes(const lbm_ctx* c)
+{
+    if (!c) return 0;
+    return kStateHeader + sizeof(double) * ((size_t)c->Q + 1) * (size_t)c->g.N;
+}
+
+int lbm_save_state(lbm_ctx* c, void* out, int on_device)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (!out) return fail(c, LBM_EINVAL, "out is NULL");
+    const long long hdr[8] = { kStateMagic, kStateVersion, c->p.lattice, c->p.nx, c->p.ny, c->p.nz, c->steps, 0 };
+    char* o = static_cast<char*>(out);
+    const size_t N = (size_t)c->g.N;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    int r = LBM_OK;
+    if (on_device)
+        r = hip_check(c, hipMemcpyAsync(o, hdr, sizeof hdr, hipMemcpyHostToDevice, c->stream), "state header");
+    else
+        std::memcpy(o, hdr, sizeof hdr);
+    // the Q population arrays (stored with the padded stride) packed one after another
+    if (r == LBM_OK)
+        r = hip_check(c, hipMemcpy2DAsync(o + kStateHeader, N * sizeof(double), c->S[c->cur],
+                                          (size_t)c->g.ps * sizeof(double), N * sizeof(double), (size_t)c->Q, kind,
+                                          c->stream), "state populations");
+    if (r == LBM_OK)
+        r = hip_check(c, hipMemcpyAsync(o + kStateHeader + sizeof(double) * c->Q * N, c->rhob[c->cur],
+                                        sizeof(double) * N, kind, c->stream), "state density");
+    if (r == LBM_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "state sync");
+    return r;
+}
+
+int lbm_load_state(lbm_ctx* c, const void* in, int on_device)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (!in) return fail(c, LBM_EINVAL, "in is NULL");
+    if (c->in_batch) return fail(c, LBM_ESTATE, "a batch instance's state belongs to the batch");
+    const char* i = static_cast<const char*>(in);
+    long long hdr[8];
+    if (on_device) {
+        int r = hip_check(c, hipMemcpyAsync(hdr, i, sizeof hdr, hipMemcpyDeviceToHost, c->stream), "state header");
+        if (r == LBM_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "state header sync");
+        if (r) return r;
+    } else {
+        std::memcpy(hdr, i, sizeof hdr);
+    }
+    if (hdr[0] != kStateMagic || hdr[1] != kStateVersion) return fail(c, LBM_EINVAL, "not a state image");
+    if (hdr[2] != c->p.lattice || hdr[3] != c->p.nx || hdr[4] != c->p.ny || hdr[5] != c->p.nz)
+        return fail(c, LBM_EINVAL, "state image of another lattice or grid size");
+    if (hdr[6] < 0) return fail(c, LBM_EINVAL, "state image with a negative step count");
+    const size_t N = (size_t)c->g.N;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    int r = hip_check(c, hipMemcpy2DAsync(c->S[c->cur], (size_t)c->g.ps * sizeof(double), i + kStateHeader,
+                                          N * sizeof(double), N * sizeof(double), (size_t)c->Q, kind, c->stream),
+                      "state populations");
+    if (r == LBM_OK)
+        r = hip_check(c, hipMemcpyAsync(c->rhob[c->cur], i + kStateHeader + sizeof(double) * c->Q * N,
+                                        sizeof(double) * N, kind, c->stream), "state density");
+    if (r == LBM_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "state sync");
+    if (r == LBM_OK) c->steps = (long)hdr[6];
+    return r;
+}
+
 int lbm_step_timed(lbm_ctx* c, long nsteps, double* ms, int cap, int* nphases)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
@@ -1362,6 +1435,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         rc = lbm_init(&ps[i], rho0s[i], 0, b->ws + B.inst_off[i], sz, hip_stream, &c);
         if (rc != LBM_OK) { b->err = "instance " + std::to_string(i) + ": " + g_thread_error; break; }
         c->fused = false;
+        c->in_batch = true;
         drop_branches(c);     // instances are stepped by the batched kernel
         b->ctx[i] = c;
         BInst& I = b->inst[i];

@@ -52,6 +52,9 @@ SYMBOLS = {
     "lbm_spurious_max": (C.c_int, [C.c_void_p, _D, _D]),
     "lbm_populations": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "lbm_steps_done": (C.c_long, [C.c_void_p]),
+    "lbm_state_bytes": (C.c_size_t, [C.c_void_p]),
+    "lbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "lbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "lbm_step_timed": (C.c_int, [C.c_void_p, C.c_long, _D, C.c_int, C.POINTER(C.c_int)]),
     "lbm_phase_name": (C.c_char_p, [C.c_void_p, C.c_int]),
     "lbm_variant_name": (C.c_char_p, [C.c_void_p, C.c_int]),
@@ -287,6 +290,26 @@ class Simulation:
     def steps_done(self) -> int:
         return int(lib().lbm_steps_done(self.ctx))
 
+    def save_state(self, device: bool = False):
+        """State image (lbm_save_state): a host numpy uint8 array, or with
+        device=True a torch uint8 tensor on the context's device."""
+        nbytes = int(lib().lbm_state_bytes(self.ctx))
+        if device:
+            img = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+            _check(lib().lbm_save_state(self.ctx, C.c_void_p(img.data_ptr()), 1), self.ctx)
+        else:
+            img = np.empty(nbytes, np.uint8)
+            _check(lib().lbm_save_state(self.ctx, img.ctypes.data_as(C.c_void_p), 0), self.ctx)
+        return img
+
+    def load_state(self, img) -> None:
+        """Restore an image from save_state (host array or device tensor)."""
+        if hasattr(img, "data_ptr") and img.is_cuda:
+            _check(lib().lbm_load_state(self.ctx, C.c_void_p(img.data_ptr()), 1), self.ctx)
+        else:
+            a = np.ascontiguousarray(img, dtype=np.uint8)
+            _check(lib().lbm_load_state(self.ctx, a.ctypes.data_as(C.c_void_p), 0), self.ctx)
+
     def macros(self):
         """(rho, vx, vy, vz) host arrays shaped like the grid (vz None in 2D)."""
         return _macros(self)
@@ -369,6 +392,8 @@ _View.macros = _macros
 _View.spurious_max = _spurious
 _View.populations = _populations
 _View.steps_done = property(lambda self: int(lib().lbm_steps_done(self.ctx)))
+_View.save_state = Simulation.save_state
+_View.load_state = Simulation.load_state
 
 RUNNING, CONVERGED, DIVERGED = 0, 1, 2
 
