@@ -397,12 +397,14 @@ def droplet_set_3d(n, seed, r_frac=(0.22, 0.32), tr_range=(0.65, 0.85), k_range=
 
 
 def big_droplet(net: Net, scheme: int, L: int = 384, R: float = 80.0, Tr: float = 0.8, k: float = 0.1,
-                max_steps: int = 40000, check_every: int = 100, tol: float = 1e-10, report_every: int = 2000):
+                max_steps: int = 40000, check_every: int = 100, tol: float = 1e-10, report_every: int = 2000,
+                starts=("tanh", "learned")):
     """The config-5 geometry (D3Q19 L^3 periodic, droplet of radius R at the
     centre) from the tanh start of Eq 26 (width 10) and from the learned start
     (same mass), each run on a plain context until |U(t) - U(t - 100)| < tol
-    or max_steps.  Returns one row per start: status, steps, U, rho_l at the
-    centre, rho_g at the corner, MLUPS of the stepping, and the U history."""
+    or max_steps (starts: which of the two to run).  Returns one row per
+    start: status, steps, U, rho_l at the centre, rho_g at the corner, MLUPS
+    of the stepping, and the U history."""
     import torch
     g, l = lbm.coexistence(Tr)
     p = lbm.Params(lattice=lbm.D3Q19, nx=L, ny=L, nz=L, Tr=Tr, k=k, kappa=0.004, scheme=scheme)
@@ -410,6 +412,8 @@ def big_droplet(net: Net, scheme: int, L: int = 384, R: float = 80.0, Tr: float 
     rho, _ = mass_matched_field(net, p, R, Tr, k, scheme, g, l, float(r_t.sum()))
     rows = {}
     for name, r0 in (("tanh", r_t), ("learned", rho if rho is not None else r_t)):
+        if name not in starts:
+            continue
         sim = lbm.Simulation(p, torch.from_numpy(r0.reshape(-1)).cuda() if isinstance(r0, np.ndarray) else r0)
         # the fastest collide on 256^3 and 384^3 (no tuner: it would advance the state)
         names = [sim.variant_name(v) for v in range(sim.num_variants)]
@@ -540,12 +544,15 @@ def main():
                                               "at --big-Tr from the tanh and the learned start")
     ap.add_argument("--big-Tr", type=float, default=0.8)
     ap.add_argument("--big-n", type=int, default=384)
+    ap.add_argument("--big-start", default="both", choices=["both", "tanh", "learned"],
+                    help="run the config-5 droplet from this start only")
     a = ap.parse_args()
     if a.big:
         net = Net(0)
         net.load(np.load(a.load))
+        starts = ("tanh", "learned") if a.big_start == "both" else (a.big_start,)
         res = [big_droplet(net, lbm.SCHEMES[sname], L=a.big_n, R=80.0 * a.big_n / 384, Tr=a.big_Tr,
-                           max_steps=a.max_steps_3d, tol=a.tol) for sname in a.big.split(",")]
+                           max_steps=a.max_steps_3d, tol=a.tol, starts=starts) for sname in a.big.split(",")]
         print(json.dumps(res))
         return
     import torch
