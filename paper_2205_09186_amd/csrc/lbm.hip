@@ -1014,7 +1014,9 @@ int lbm_save_state(lbm_ctx* c, void* out, int on_device)
     if (r == LBM_OK)
         r = hip_check(c, hipMemcpyAsync(o + kStateHeader + sizeof(double) * c->Q * N, c->rhob[c->cur],
                                         sizeof(double) * N, kind, c->stream), "state density");
-    if (r == LBM_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "state sync");
+    // always drained before returning: the header copy reads this frame
+    const hipError_t se = hipStreamSynchronize(c->stream);
+    if (r == LBM_OK) r = hip_check(c, se, "state sync");
     return r;
 }
 
@@ -1027,7 +1029,8 @@ int lbm_load_state(lbm_ctx* c, const void* in, int on_device)
     long long hdr[8];
     if (on_device) {
         int r = hip_check(c, hipMemcpyAsync(hdr, i, sizeof hdr, hipMemcpyDeviceToHost, c->stream), "state header");
-        if (r == LBM_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "state header sync");
+        const hipError_t se = hipStreamSynchronize(c->stream);
+        if (r == LBM_OK) r = hip_check(c, se, "state header sync");
         if (r) return r;
     } else {
         std::memcpy(hdr, i, sizeof hdr);
@@ -1044,7 +1047,9 @@ int lbm_load_state(lbm_ctx* c, const void* in, int on_device)
     if (r == LBM_OK)
         r = hip_check(c, hipMemcpyAsync(c->rhob[c->cur], i + kStateHeader + sizeof(double) * c->Q * N,
                                         sizeof(double) * N, kind, c->stream), "state density");
-    if (r == LBM_OK) r = hip_check(c, hipStreamSynchronize(c->stream), "state sync");
+    // always drained before returning, so the caller may release the image
+    const hipError_t se = hipStreamSynchronize(c->stream);
+    if (r == LBM_OK) r = hip_check(c, se, "state sync");
     if (r == LBM_OK) c->steps = (long)hdr[6];
     return r;
 }

@@ -9,7 +9,9 @@ in [max(64, 2R + 64), 256]); Tr uniform in [0.2, 0.95]; k uniform in [0.1,
 relative noise +-1e-6 (absolute noise would make the gas density negative
 below Tr ~ 0.45).  Each
 instance runs until |U(t) - U(t - 100)| < 1e-10 (checked every 100 steps),
-until it diverges, or until the step cap.
+until it diverges, or until the step cap.  --collision mrt runs every
+instance with the MRT collision of Eq 3-5 (the paper's own runs) instead of
+BGK.
 
 ``python -m paper_2205_09186_amd.sweep`` prints one JSON summary.
 """
@@ -27,7 +29,8 @@ SCHEMES6 = [lbm.CD2, lbm.CD4, lbm.CD6, lbm.E4, lbm.E8, lbm.OCFDS4]
 NAMES = {v: k for k, v in lbm.SCHEMES.items()}
 
 
-def build(n_slabs=48, n_drops=48, seed=0, kappa=0.004, width=10.0, tr_range=(0.2, 0.95), k_range=(0.1, 0.25)):
+def build(n_slabs=48, n_drops=48, seed=0, kappa=0.004, width=10.0, tr_range=(0.2, 0.95), k_range=(0.1, 0.25),
+          collision=0):
     descs = inputs.sweep_instances(n_slabs, n_drops, seed=seed, n_schemes=6, tr_range=tr_range, k_range=k_range)
     params, rhos = [], []
     for d in descs:
@@ -40,7 +43,7 @@ def build(n_slabs=48, n_drops=48, seed=0, kappa=0.004, width=10.0, tr_range=(0.2
             r = inputs.droplet((d["ny"], d["nx"]), d["radius"], width, g, l, instance_id=d["instance_id"],
                                relative=True)
         params.append(lbm.Params(lattice=lbm.D2Q9, nx=d["nx"], ny=d["ny"], Tr=d["Tr"], k=d["k"], kappa=kappa,
-                                 scheme=d["scheme"]))
+                                 scheme=d["scheme"], collision=collision))
         rhos.append(r)
     return descs, params, rhos
 
@@ -84,8 +87,12 @@ def main():
     ap.add_argument("--slabs", type=int, default=48)
     ap.add_argument("--drops", type=int, default=48)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--collision", default="srt", choices=["srt", "mrt"],
+                    help="BGK (Eq 1 with one rate) or the D2Q9 MRT of Eq 3-5")
     a = ap.parse_args()
-    res = run(max_steps=a.max_steps, chunk=a.chunk, n_slabs=a.slabs, n_drops=a.drops, seed=a.seed)
+    res = run(max_steps=a.max_steps, chunk=a.chunk, n_slabs=a.slabs, n_drops=a.drops, seed=a.seed,
+              collision=1 if a.collision == "mrt" else 0)
+    res["collision"] = a.collision
     res["mlups"] = res["node_updates"] / res["wall_s"] / 1e6
     print(json.dumps(res))
 
