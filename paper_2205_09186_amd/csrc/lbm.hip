@@ -30,7 +30,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t S0, S1, rho0, rho1, mu, force, ringsum, grho, gmu, lap, wtmp, wl, wb, partial, result, total;
+    size_t S0, S1, rho0, rho1, mu, force, ringsum, zring, grho, gmu, lap, wtmp, wl, wb, partial, result, total;
     long long nparts;
 };
 
@@ -109,6 +109,8 @@ Layout layout_of(const lbm_params* p)
         Grid g{};
         g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
         L.ringsum = take(sizeof(double) * ringsum_doubles(g, dim == 3));
+        // the z-ring segments of the 3D tile collide (64x16 tiles, no walls)
+        if (dim == 3 && !p->wall && p->ny % kZringTY == 0) L.zring = take(sizeof(double) * zring_doubles(g));
     }
     if (p->wall) {
         L.wl = take(N);
@@ -139,6 +141,7 @@ struct lbm_ctx {
     char* ws;
     Layout L;
     double *S[2], *rhob[2], *mu, *force, *ringsum, *grho, *gmu, *lap, *wtmp, *partial, *result;
+    double* zring = nullptr;     // z-ring segment ends of the tile collide (zr variants)
     unsigned* wbits = nullptr;   // wetting boundary: per-node bounce-back mask of the fast path
     int cur;        // index of the buffers holding the current state (S and rho)
     long steps;
@@ -411,9 +414,9 @@ void launch_step(lbm_ctx* c)
                 launch_mf<SCH>(tv->ty, rho, c->force, c->g, c->eos, c->stream);
                 mark(c, "k_tile");
                 launch_tile<LAT>(*tv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->ringsum,
-                                 c->g, c->rx, c->stream);
+                                 c->g, c->rx, c->stream, nullptr, c->zring);
                 mark(c, "k_fix");
-                launch_fix<LAT>(*tv, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
+                launch_fix<LAT>(*tv, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream, c->zring);
                 mark(c, nullptr);
                 c->cur = 1 - c->cur;
                 return;
@@ -446,9 +449,9 @@ void launch_step(lbm_ctx* c)
         if (tv) {
             mark(c, "k_tile");
             launch_tile<LAT>(*tv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->ringsum, c->g,
-                             c->rx, c->stream);
+                             c->rx, c->stream, nullptr, c->zring);
             mark(c, "k_fix");
-            launch_fix<LAT>(*tv, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream);
+            launch_fix<LAT>(*tv, c->rhob[1 - c->cur], c->ringsum, c->g, c->stream, c->zring);
         } else {
             mark(c, "k_ring");
             launch_ring_collide<LAT>(rv, c->S[c->cur], c->S[1 - c->cur], c->force, c->rhob[1 - c->cur], c->g, c->rx,
@@ -656,6 +659,8 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
     c->mu = reinterpret_cast<double*>(c->ws + L.mu);
     c->force = c->g.N < (1LL << 29) ? reinterpret_cast<double*>(c->ws + L.force) : nullptr;
     c->ringsum = (c->force && tile_fits(c->g, kTileTY)) ? reinterpret_cast<double*>(c->ws + L.ringsum) : nullptr;
+    c->zring = (c->ringsum && c->dim == 3 && !p->wall && p->ny % kZringTY == 0)
+                   ? reinterpret_cast<double*>(c->ws + L.zring) : nullptr;
     const bool compact = is_compact(p->scheme);
     c->grho = compact ? reinterpret_cast<double*>(c->ws + L.grho) : nullptr;
     c->gmu = compact ? reinterpret_cast<double*>(c->ws + L.gmu) : nullptr;
@@ -681,6 +686,7 @@ int init_ctx(const lbm_params* p, const double* rho0, const unsigned char* solid
             if (!tile_fits(c->g, v.ty)) continue;
             if (p->lattice == LBM_D2Q9 && v.fz != kTileVariants[0].fz) continue;   // one segment in 2D
             if (v.mf && !mf_ok) continue;
+            if (v.zr && !c->zring) continue;
             c->tiles.push_back(v);
         }
     }
@@ -1129,7 +1135,8 @@ const char* lbm_variant_name(lbm_ctx* c, int v)
         t -= kNumRingVariants;
     }
     const TileVariant& tv = c->tiles[t];
-    if (c->dim == 3) std::snprintf(buf, sizeof buf, "tile 64x%d z%d%s", tv.ty, tv.fz, tv.mf ? " mf" : "");
+    if (c->dim == 3)
+        std::snprintf(buf, sizeof buf, "tile 64x%d z%d%s%s", tv.ty, tv.fz, tv.mf ? " mf" : "", tv.zr ? " zr" : "");
     else std::snprintf(buf, sizeof buf, "tile 64x%d", tv.ty);
     return (c->vname = buf).c_str();
 }

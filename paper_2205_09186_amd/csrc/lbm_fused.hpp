@@ -1016,12 +1016,18 @@ inline bool tile_fits(const Grid& g, int ty) { return g.nx % 64 == 0 && g.ny % t
 // whose source is solid, its own post-collision value of the opposite
 // direction (halfway bounce-back), and adds those same values to its
 // rho(t+1); solid nodes do not collide and send nothing.
-template <int LAT, int TY, bool FULL, bool WALL = false>
+// ZR (3D, no walls): a segment marches its own planes only.  What its first
+// plane sends down (into the last plane of the segment below) and what its last
+// plane sends up go to zring, slots 0 and 1 of the tile (NTH in-tile values,
+// then NR ring cells), and k_fix_zr adds them, instead of every segment
+// pulling and colliding one extra plane at each end.
+template <int LAT, int TY, bool FULL, bool WALL = false, bool ZR = false>
 __global__ void __launch_bounds__(64 * TY, TY <= 8 ? 2 : 1)
 k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __restrict__ F,
        double* __restrict__ rho_next, double* __restrict__ ringsum, Grid g, TileGeom tg, Relax rx,
-       const unsigned* __restrict__ wb = nullptr)
+       const unsigned* __restrict__ wb = nullptr, double* __restrict__ zring = nullptr)
 {
+    static_assert(!ZR || (LAT == 1 && !WALL), "z-ring segments are for the 3D collide without walls");
     using L = Lat<LAT>;
     using TR = TileRing<TY>;
     constexpr int Q = L::Q;
@@ -1078,7 +1084,7 @@ k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
     };
 
     double acc_m1 = 0.0, acc_0 = 0.0, racc_m1 = 0.0, racc_0 = 0.0;
-    const int zb = LAT == 1 ? z0 - 1 : 0, ze = LAT == 1 ? z1 : 0;
+    const int zb = LAT == 1 ? (ZR ? z0 : z0 - 1) : 0, ze = LAT == 1 ? (ZR ? z1 - 1 : z1) : 0;
     // the mask is loaded one plane ahead of the pulls it steers
     if constexpr (WALL) bits_next = wb[(LAT == 1 ? pwrap(zb, nz) : 0) * nxy + yc + x];
     pull_plane(LAT == 1 ? pwrap(zb, nz) : 0);
@@ -1150,6 +1156,11 @@ k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
             if (zr - 1 >= z0 && zr - 1 < z1) {
                 st32(rho_next, (unsigned)((zr - 1) * nxy + yc + x), acc_m1);
                 if (ring) rs[(zr - 1 - z0) * TR::NR + lid] = racc_m1;
+            } else if (ZR && zr == zb) {
+                // what the first plane sends into the last plane of the segment below
+                double* zd = zring + (size_t)b * 2 * (NTH + TR::NR);
+                zd[lid] = acc_m1;
+                if (ring) zd[NTH + lid] = racc_m1;
             }
             acc_m1 = acc_0 + a_0;
             acc_0 = a_p1;
@@ -1159,6 +1170,15 @@ k_tile(const double* __restrict__ S, double* __restrict__ Sn, const double* __re
             rho_next[yc + x] = a_0;
             if (ring) rs[lid] = r_0;
         }
+    }
+    if constexpr (ZR) {
+        // what the last plane sends into the first plane of the segment above,
+        // and the last plane itself without what that plane sends down
+        double* zu = zring + ((size_t)b * 2 + 1) * (NTH + TR::NR);
+        zu[lid] = acc_0;
+        if (ring) zu[NTH + lid] = racc_0;
+        st32(rho_next, (unsigned)(ze * nxy + yc + x), acc_m1);
+        if (ring) rs[(ze - z0) * TR::NR + lid] = racc_m1;
     }
 }
 
@@ -1202,6 +1222,82 @@ __global__ void __launch_bounds__(256) k_fix(double* __restrict__ rho_next, cons
     st32(rho_next, n, acc);
 }
 
+// The fix of the z-ring segments: per tile segment, every node of its first
+// and last plane, and the edge nodes of the planes between.  A node adds, in
+// this order, the ring sums the neighbouring tiles of its segment left for it
+// (edge nodes), then on the first plane what the segment below sent up (its own
+// tile's in-tile value, then the neighbouring tiles' ring cells), then on the
+// last plane what the segment above sent down (the same way).
+template <int TY>
+__global__ void __launch_bounds__(256) k_fix_zr(double* __restrict__ rho_next, const double* __restrict__ ringsum,
+                                               const double* __restrict__ zring, Grid g, TileGeom tg, int mzt)
+{
+    using TR = TileRing<TY>;
+    constexpr int NTH = 64 * TY, ZW = NTH + TR::NR;
+    // one row of the grid per tile segment, its items along x
+    const int per = 2 * NTH + (mzt - 2) * TR::NB;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= per) return;
+    const int tile = blockIdx.y;
+    const int tx = tile % tg.ntx, ty = (tile / tg.ntx) % tg.nty, sz = tile / (tg.ntx * tg.nty);
+    const int z0 = sz * mzt, planes = min(mzt, g.nz - z0);
+    int zl, lx, ly;
+    if (j < 2 * NTH) {
+        const int which = j / NTH, lid = j - which * NTH;
+        if (which == 1 && planes == 1) return;   // one plane: the first-plane item takes both ends
+        zl = which == 0 ? 0 : planes - 1;
+        lx = lid % 64;
+        ly = lid / 64;
+    } else {
+        const int i = j - 2 * NTH;
+        zl = 1 + i / TR::NB;
+        if (zl >= planes - 1) return;
+        const int e = i % TR::NB;
+        if (e < 64) { lx = e; ly = 0; }
+        else if (e < 128) { lx = e - 64; ly = TY - 1; }
+        else if (e < 128 + TY - 2) { lx = 0; ly = 1 + e - 128; }
+        else { lx = 63; ly = 1 + e - 128 - (TY - 2); }
+    }
+    const bool edge = lx == 0 || lx == 63 || ly == 0 || ly == TY - 1;
+    const unsigned n = (unsigned)((z0 + zl) * (int)g.nxy + (ty * TY + ly) * g.nx + tx * 64 + lx);
+    const int txs[3] = { tx == 0 ? tg.ntx - 1 : tx - 1, tx, tx + 1 == tg.ntx ? 0 : tx + 1 };
+    const int tys[3] = { ty == 0 ? tg.nty - 1 : ty - 1, ty, ty + 1 == tg.nty ? 0 : ty + 1 };
+    double acc = ld32(rho_next, n);
+    if (edge) {
+#pragma unroll
+        for (int dty = -1; dty <= 1; ++dty)
+#pragma unroll
+            for (int dtx = -1; dtx <= 1; ++dtx) {
+                if (dtx == 0 && dty == 0) continue;
+                const int k = TR::index(lx - 64 * dtx, ly - TY * dty);
+                if (k < 0) continue;
+                const int tn = (sz * tg.nty + tys[dty + 1]) * tg.ntx + txs[dtx + 1];
+                acc += ringsum[((size_t)tn * mzt + zl) * TR::NR + k];
+            }
+    }
+    // slot 1 of the segment below (first plane), slot 0 of the segment above (last plane)
+#pragma unroll
+    for (int end = 0; end < 2; ++end) {
+        if (end == 0 ? zl != 0 : zl != planes - 1) continue;
+        const int so = end == 0 ? (sz == 0 ? tg.nsz - 1 : sz - 1) : (sz + 1 == tg.nsz ? 0 : sz + 1);
+        const int slot = end == 0 ? 1 : 0;
+        acc += zring[((size_t)((so * tg.nty + ty) * tg.ntx + tx) * 2 + slot) * ZW + ly * 64 + lx];
+        if (edge) {
+#pragma unroll
+            for (int dty = -1; dty <= 1; ++dty)
+#pragma unroll
+                for (int dtx = -1; dtx <= 1; ++dtx) {
+                    if (dtx == 0 && dty == 0) continue;
+                    const int k = TR::index(lx - 64 * dtx, ly - TY * dty);
+                    if (k < 0) continue;
+                    const int tn = (so * tg.nty + tys[dty + 1]) * tg.ntx + txs[dtx + 1];
+                    acc += zring[((size_t)tn * 2 + slot) * ZW + NTH + k];
+                }
+        }
+    }
+    st32(rho_next, n, acc);
+}
+
 // Launch variants of the tile collide: tile height, z planes per segment, and
 // whether the chemical potential and the force come from one march (k_mf) or
 // from the two marches (k_march).  The taller tile halves the edge share (16%
@@ -1209,10 +1305,15 @@ __global__ void __launch_bounds__(256) k_fix(double* __restrict__ rho_next, cons
 // segment halves the two planes each segment pulls beyond its own.  The ring-
 // sum buffer has one slot per ring cell and plane of the lowest tile, for the
 // planes of the longest segment.
-struct TileVariant { int ty, fz, mf; };
-constexpr TileVariant kTileVariants[] = { {8, 32, 0}, {16, 32, 0}, {8, 64, 0}, {16, 64, 0},
-                                          {16, 32, 1}, {16, 64, 1}, {8, 64, 1} };
-constexpr int kNumTileVariants = 7;
+// zr: z-ring segments (3D without walls; 64x16 tiles): no plane is pulled
+// or collided twice, the segment ends are completed by k_fix_zr.
+struct TileVariant { int ty, fz, mf, zr; };
+constexpr TileVariant kTileVariants[] = { {8, 32, 0, 0}, {16, 32, 0, 0}, {8, 64, 0, 0}, {16, 64, 0, 0},
+                                          {16, 32, 1, 0}, {16, 64, 1, 0}, {8, 64, 1, 0},
+                                          {16, 32, 0, 1}, {16, 64, 0, 1}, {16, 64, 1, 1} };
+constexpr int kNumTileVariants = 10;
+constexpr int kZringTY = 16;
+constexpr int kZringMinFZ = 32;
 constexpr int kTileTY = 8;
 constexpr int kTileMaxFZ = 64;
 
@@ -1221,6 +1322,14 @@ inline size_t ringsum_doubles(const Grid& g, bool three_d)
     const size_t ntile = (size_t)(g.nx / 64) * (g.ny / kTileTY);
     const size_t planes = three_d ? (size_t)((g.nz + kTileMaxFZ - 1) / kTileMaxFZ) * kTileMaxFZ : 1;
     return ntile * planes * TileRing<kTileTY>::NR;
+}
+
+// Doubles of the z-ring buffer: two slots of 64*16 in-tile values and the
+// ring cells per tile segment, for the shortest z-ring segment.
+inline size_t zring_doubles(const Grid& g)
+{
+    const size_t ntile = (size_t)(g.nx / 64) * (g.ny / kZringTY) * ((g.nz + kZringMinFZ - 1) / kZringMinFZ);
+    return ntile * 2 * (64 * kZringTY + TileRing<kZringTY>::NR);
 }
 
 inline TileGeom tile_geom(const Grid& g, bool three_d, int ty, int fz)
@@ -1235,11 +1344,23 @@ inline TileGeom tile_geom(const Grid& g, bool three_d, int ty, int fz)
 
 template <int LAT, int TY>
 inline void launch_tile_ty(const double* S, double* Sn, const double* F, double* rho_next, double* ringsum,
-                           const Grid& g, const Relax& rx, int fz, hipStream_t st, const unsigned* wb)
+                           const Grid& g, const Relax& rx, int fz, hipStream_t st, const unsigned* wb,
+                           double* zring = nullptr)
 {
     const TileGeom t = tile_geom(g, LAT == 1, TY, fz);
     const unsigned nb = (unsigned)(t.ntx * t.nty * t.nsz);
     const bool full = rx.omo == 0.0 && !rx.mrt;
+    if constexpr (LAT == 1 && TY == kZringTY) {
+        if (zring) {
+            if (full)
+                hipLaunchKernelGGL((k_tile<LAT, TY, true, false, true>), dim3(nb), dim3(64 * TY), 0, st, S, Sn, F,
+                                   rho_next, ringsum, g, t, rx, nullptr, zring);
+            else
+                hipLaunchKernelGGL((k_tile<LAT, TY, false, false, true>), dim3(nb), dim3(64 * TY), 0, st, S, Sn, F,
+                                   rho_next, ringsum, g, t, rx, nullptr, zring);
+            return;
+        }
+    }
     if (wb) {
         if (full)
             hipLaunchKernelGGL((k_tile<LAT, TY, true, true>), dim3(nb), dim3(64 * TY), 0, st, S, Sn, F, rho_next,
@@ -1258,27 +1379,37 @@ inline void launch_tile_ty(const double* S, double* Sn, const double* F, double*
 
 template <int TY>
 inline void launch_fix_ty(double* rho_next, const double* ringsum, const Grid& g, bool three_d, int fz,
-                          hipStream_t st)
+                          hipStream_t st, const double* zring = nullptr)
 {
     const TileGeom t = tile_geom(g, three_d, TY, fz);
+    if (zring) {
+        const int per = 2 * 64 * TY + (t.mz - 2) * TileRing<TY>::NB;
+        hipLaunchKernelGGL((k_fix_zr<TY>), dim3((unsigned)((per + 255) / 256), (unsigned)(t.ntx * t.nty * t.nsz)),
+                           dim3(256), 0, st, rho_next, ringsum, zring, g, t, t.mz);
+        return;
+    }
     const long long items = (long long)t.ntx * t.nty * t.nsz * t.mz * TileRing<TY>::NB;
     hipLaunchKernelGGL((k_fix<TY>), dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, rho_next, ringsum,
                        g, t, t.mz);
 }
 
+// zring: the z-ring buffer, used by the variants with zr set (64x16 tiles, 3D).
 template <int LAT>
 inline void launch_tile(const TileVariant& v, const double* S, double* Sn, const double* F, double* rho_next,
                         double* ringsum, const Grid& g, const Relax& rx, hipStream_t st,
-                        const unsigned* wb = nullptr)
+                        const unsigned* wb = nullptr, double* zring = nullptr)
 {
-    if (v.ty == 16) launch_tile_ty<LAT, 16>(S, Sn, F, rho_next, ringsum, g, rx, v.fz, st, wb);
+    double* zr = v.zr ? zring : nullptr;
+    if (v.ty == 16) launch_tile_ty<LAT, 16>(S, Sn, F, rho_next, ringsum, g, rx, v.fz, st, wb, zr);
     else launch_tile_ty<LAT, 8>(S, Sn, F, rho_next, ringsum, g, rx, v.fz, st, wb);
 }
 
 template <int LAT>
-inline void launch_fix(const TileVariant& v, double* rho_next, const double* ringsum, const Grid& g, hipStream_t st)
+inline void launch_fix(const TileVariant& v, double* rho_next, const double* ringsum, const Grid& g, hipStream_t st,
+                       const double* zring = nullptr)
 {
-    if (v.ty == 16) launch_fix_ty<16>(rho_next, ringsum, g, LAT == 1, v.fz, st);
+    const double* zr = v.zr ? zring : nullptr;
+    if (v.ty == 16) launch_fix_ty<16>(rho_next, ringsum, g, LAT == 1, v.fz, st, zr);
     else launch_fix_ty<8>(rho_next, ringsum, g, LAT == 1, v.fz, st);
 }
 

@@ -35,15 +35,17 @@ def _workload(orc, lat, n, scheme):
 def _design_variants(L, sim, lat, scheme):
     """One launch variant of each design the context offers: k_fused (CD
     schemes), the first ring variant, the tile collide with the two stencil
-    marches and, where offered, with the one chemical-potential/force march."""
+    marches and, where offered, with the one chemical-potential/force march,
+    and every z-ring variant."""
     names = [sim.variant_name(v) for v in range(sim.num_variants)]
     out = []
     for kind in ("fused", "ring"):
         first = [v for v, n in enumerate(names) if n.startswith(kind)]
         out += first[:1]
-    tiles = [v for v, n in enumerate(names) if n.startswith("tile") and not n.endswith(" mf")]
+    tiles = [v for v, n in enumerate(names) if n.startswith("tile") and " mf" not in n and " zr" not in n]
     mf = [v for v, n in enumerate(names) if n.endswith(" mf")]
-    out += tiles[-1:] + mf[:1]
+    zr = [v for v, n in enumerate(names) if n.endswith(" zr")]     # the z-ring segments, every one offered
+    out += tiles[-1:] + mf[:1] + zr
     return out
 
 

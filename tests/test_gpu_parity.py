@@ -259,10 +259,11 @@ def test_launch_variants_identical(L, orc, lat, shape, tau, scheme, designs):
 
 
 @pytest.mark.parametrize("lat,shape,scheme", [(0, (100, 100), "CD4"), (1, (20, 24, 28), "CD6"),
-                                              (0, (40, 44), "OCFDS4")])
+                                              (0, (40, 44), "OCFDS4"), (1, (70, 16, 64), "CD6")])
 def test_graph_replay_equals_plain_launches(L, orc, lat, shape, scheme, monkeypatch):
     """lbm_step replays a captured two-step graph; the state after any mix of
-    odd and even step counts is bitwise that of plain launches."""
+    odd and even step counts is bitwise that of plain launches (on 70x16x64
+    the last variant is a z-ring tile collide)."""
     g, l = orc.maxwell(0.8)
     rho0 = inputs.droplet(shape, min(shape) / 4, 4.0, g, l)
     nz, ny, nx = ((1,) + shape) if lat == 0 else shape
@@ -309,7 +310,8 @@ def test_mf_march_against_oracle(L, orc, shape, scheme, steps):
 @pytest.mark.parametrize("lat,shape,scheme,tau,coll", [
     (1, (20, 16, 128), "CD6", 1.0, 0), (1, (12, 8, 64), "CD4", 0.8, 0), (1, (9, 24, 192), "OCFDS4", 1.0, 0),
     (1, (10, 16, 64), "E8", 1.0, 0), (0, (40, 64), "CD6", 1.0, 0), (0, (16, 192), "CD2", 0.9, 0),
-    (0, (48, 128), "CD6", 0.9, 1), (0, (8, 64), "CD4", 1.0, 0)])
+    (0, (48, 128), "CD6", 0.9, 1), (0, (8, 64), "CD4", 1.0, 0),
+    (1, (70, 16, 64), "CD6", 1.0, 0), (1, (33, 16, 128), "CD4", 0.8, 0), (1, (65, 32, 64), "OCFDS4", 1.0, 0)])
 def test_tile_design(L, orc, lat, shape, scheme, tau, coll):
     """The ring-free tile collide (in-tile LDS exchange plus the ring sums that
     k_fix adds at tile edges) against the oracle and against the ring collide,
@@ -328,16 +330,22 @@ def test_tile_design(L, orc, lat, shape, scheme, tau, coll):
         names[v] = [n for n, _ in s.step_timed(1)]
     tiles = [v for v, n in names.items() if n[-2:] == ["k_tile", "k_fix"]]
     ring = [v for v, n in names.items() if n[-1] == "k_ring"][0]
-    # tile heights 8 and 16; in 3D z segments of 32 and 64 planes, and for the
-    # CD schemes the fused chemical-potential/force march (64x16 z32, z64; 64x8 z64)
+    # tile heights 8 and 16; in 3D z segments of 32 and 64 planes, for the CD
+    # schemes the fused chemical-potential/force march (64x16 z32, z64; 64x8
+    # z64), and with 16-row tiles the z-ring segments (64x16 z32, z64, and
+    # for the CD schemes 64x16 z64 mf): segments of 32 or 64 planes with a
+    # short last one, or of one plane (33 = 32 + 1), or one wrapping segment
     heights = 2 if ny % 16 == 0 else 1
-    if lat == 0:
-        expect = heights
-    else:
-        expect = 2 * heights + ((3 if heights == 2 else 1) if scheme in ("CD2", "CD4", "CD6") else 0)
+    cd = scheme in ("CD2", "CD4", "CD6")
+    n_mf = ((3 if heights == 2 else 1) if cd else 0) if lat == 1 else 0
+    n_zr = (2 + cd) if (lat == 1 and heights == 2) else 0
+    expect = heights if lat == 0 else 2 * heights + n_mf + n_zr
     assert len(tiles) == expect, names
     mf = [v for v, n in names.items() if n[0] == "k_mf"]
-    assert len(mf) == (expect - 2 * heights if lat == 1 else 0), names
+    assert len(mf) == n_mf + (1 if n_zr and cd else 0), names
+    s0 = L.Simulation(p, rho0)
+    vn = {v: s0.variant_name(v) for v in tiles}
+    assert sum(1 for v in tiles if vn[v].endswith(" zr")) == n_zr, vn
     b = L.Simulation(p, rho0)
     b.set_variant(ring)
     b.step(40)
