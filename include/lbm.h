@@ -180,9 +180,11 @@ int lbm_set_variant(lbm_ctx* c, int v);
 
 /* Name of launch variant v of the context ("" if out of range), e.g.
  * "ring 64x8 occ3", "tile 64x16 z64" (the ring-free tile collide with its
- * z-segment length) or "tile 64x16 z64 mf" (the same, with the chemical
- * potential and the force of Eq 12/16 formed by one march).  The string
- * stays valid until the next call for this context. */
+ * z-segment length), "tile 64x16 z64 mf" (the same, with the chemical
+ * potential and the force of Eq 12/16 formed by one march) or
+ * "tile 64x16 z64 zr" (z segments that march their own planes only, their
+ * ends completed by the edge fix).  The string stays valid until the next
+ * call for this context. */
 const char* lbm_variant_name(lbm_ctx* c, int v);
 
 /* Name of phase k of the last timed step ("" if none). */
