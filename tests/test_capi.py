@@ -136,3 +136,18 @@ def test_static_sum_rejects_bad_arguments_without_gpu():
     assert L.lbm_sum_static(None, 10, C.byref(out), None) == lbm.LBM_EINVAL
     assert L.lbm_sum_static(fake, 10, None, None) == lbm.LBM_EINVAL
     assert out.value == -1.0
+
+
+def test_degenerate_sizes_are_refused_without_gpu():
+    """Grids below the smallest periodic lattice (nx or ny < 4, nz < 4 in 3D,
+    nz != 1 in 2D) and an empty batch are refused before any device work."""
+    L = lbm.lib()
+    for kw in (dict(lattice=lbm.D2Q9, nx=3, ny=8), dict(lattice=lbm.D2Q9, nx=8, ny=0),
+               dict(lattice=lbm.D2Q9, nx=8, ny=8, nz=2), dict(lattice=lbm.D3Q19, nx=8, ny=8, nz=3)):
+        p = lbm.Params(**kw).c()
+        assert L.lbm_workspace_bytes(C.byref(p)) == 0, kw
+    p = lbm.Params(lattice=lbm.D2Q9, nx=8, ny=8).c()
+    assert L.lbm_batch_workspace_bytes(C.byref(p), 0) == 0
+    out = C.c_void_p()
+    rc = L.lbm_batch_init(C.byref(p), None, 0, None, 0, None, C.byref(out))
+    assert rc == lbm.LBM_EINVAL and out.value is None
