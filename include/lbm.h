@@ -229,8 +229,9 @@ int lbm_gradient(lbm_ctx* c, const double* d_in, double* d_grad, double* d_lap);
 
 /* ------------------------------------------------------------------------
  * Batched sweep: many uneven D2Q9 instances (droplets, flat slabs; any
- * temperature, radius and scheme) stepped together by one cooperative
- * persistent kernel per chunk of steps.  Each instance runs exactly the step
+ * temperature, radius and scheme) stepped together, by one cooperative
+ * persistent kernel per chunk of steps or by one ordinary launch per phase of
+ * each step (lbm_batch_set_form).  Each instance runs exactly the step
  * above; every check_every steps its spurious current U is compared with the
  * previous check and the instance retires as CONVERGED (|dU| < tol) or
  * DIVERGED (non-finite state or U above the sound speed).
@@ -260,24 +261,44 @@ int lbm_batch_max_grid(const lbm_batch* b);
 int lbm_batch_set_block(lbm_batch* b, int nodes);
 int lbm_batch_block(const lbm_batch* b);
 
+/* Launch form.  LBM_BATCH_PERSISTENT (the default): one cooperative launch
+ * per chunk runs every step, its workgroups separated by grid barriers
+ * between the phases.  LBM_BATCH_PHASES: each phase of each step (density;
+ * chemical potential with the compact schemes' first line solves; their
+ * second line solves; the two halves of the convergence check on the steps
+ * where an instance is due; collision) is an ordinary launch of its own,
+ * the kernel boundary in place of the barrier, and a chunk's launches are
+ * captured as one graph.  A grid barrier costs about 0.1 us per workgroup
+ * and a launch boundary a few us; the tuner times both forms.  Both compute
+ * bitwise the same states; the block size applies to both, the workgroup
+ * count only to the persistent form.  Anything else is LBM_EINVAL;
+ * lbm_batch_form returns the current form (-1 for NULL). */
+enum { LBM_BATCH_PERSISTENT = 0, LBM_BATCH_PHASES = 1 };
+int lbm_batch_set_form(lbm_batch* b, int form);
+int lbm_batch_form(const lbm_batch* b);
+
 /* How the chunks are launched: "graph: captured cooperative launch" (each
  * chunk replays a hipGraph holding the cooperative launch and the status
  * read-back, one graph per chunk length, check interval, tolerance, block and
  * workgroup count), "graph: cooperative kernel node (...)" where stream
  * capture of a cooperative launch fails but a graph node with the
- * cooperative attribute is accepted, or "plain cooperative launches (...)"
- * with the reason (set LBM_NO_GRAPH to choose it). */
+ * cooperative attribute is accepted, "graph: captured phase kernels" (the
+ * phase form; one graph also per set of loop steps that carry a check), or
+ * "plain cooperative launches (...)" / "plain phase kernels (...)" with the
+ * reason (set LBM_NO_GRAPH to choose them). */
 const char* lbm_batch_launch_mode(const lbm_batch* b);
 
 /* Advance running instances by up to nsteps steps, in launches of at most
  * `chunk` steps; stops early once every instance has retired.  Host outputs
  * (n entries each, any may be NULL): status (LBM_RUNNING/CONVERGED/DIVERGED),
- * completed steps, and U at the last check.  Synchronises.  LBM_EHIP if the
+ * completed steps, and U at the last check.  Synchronises.  Where the
  * runtime refuses the cooperative launch (ROCm does while another process
- * holds the device), or runs it without the grid barrier (the kernel then
- * returns at once); no step of that launch is taken.  A graph replay that did
- * not run the kernel to its end (a completion count the kernel keeps shows
- * it) is retried as a plain cooperative launch. */
+ * holds the device), the chunk and every later one run in the phase form
+ * instead (the launch mode says so).  LBM_EHIP if the runtime runs the
+ * persistent kernel without the grid barrier (the kernel then returns at
+ * once; no step of that launch is taken) or a launch fails.  A graph replay
+ * that did not run the kernels to their end (a completion count the last
+ * kernel keeps shows it) is retried without a graph. */
 int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long chunk,
                   int* status, long* steps, double* umax);
 

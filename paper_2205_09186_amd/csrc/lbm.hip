@@ -1218,10 +1218,18 @@ struct lbm_batch {
     int block = kBatchDefaultBlock;   // nodes per node-block item = threads per workgroup
     int grid = 0;                     // workgroups of the cooperative launch
     int max_grid_of[kNumBatchBlocks] = {};
-    // chunk launches captured as graphs: the cooperative kernel and the two
-    // status read-backs, one graph per (chunk length, check interval,
-    // tolerance, workgroups, block); replayed on the batch's stream
-    struct Graph { int todo, check, grid, block; double tol; hipGraphExec_t exec; };
+    int form = LBM_BATCH_PERSISTENT;  // launch form
+    // chunk launches captured as graphs: the cooperative kernel (or the phase
+    // kernels) and the two status read-backs, one graph per (form, chunk
+    // length, check interval, tolerance, workgroups, block, and for the phase
+    // form the loop steps that carry a check); replayed on the batch's stream
+    struct Graph {
+        int form, todo, check, grid, block;
+        double tol;
+        std::vector<char> due;
+        hipGraphExec_t exec;
+        std::string how;    // the launch mode it reports
+    };
     std::vector<Graph> graphs;
     hipStream_t cap_stream = nullptr;
     bool use_graph = true;
@@ -1407,6 +1415,78 @@ hipError_t batch_graph(lbm_batch* b, const BatchArgs& a, hipGraphExec_t* out, st
     return e;
 }
 
+// The phase form of one chunk, issued on stream st: for each loop step the
+// density, the chemical potential (with the compact schemes' first line
+// solves), the compact schemes' second line solves, the two check kernels on
+// the loop steps in `due`, and the collision; then the counters.  Every
+// kernel strides over its items, so the grids only set how many workgroups
+// share them: one per node-block item, per BN/64 lines, per BN instances.
+template <int BN>
+hipError_t batch_phases_t(const lbm_batch* b, const BatchArgs& a, const std::vector<char>& due, hipStream_t st)
+{
+    constexpr int W = BN / 64;
+    const unsigned gi = (unsigned)std::max(1, b->nblk_total);
+    const unsigned gl = (unsigned)std::max(1, (b->nlines + W - 1) / W);
+    const unsigned gm = b->has_compact ? std::max(gi, gl) : gi;
+    const unsigned gf = (unsigned)std::max(1, (b->n + BN - 1) / BN);
+    for (int s = 0; s < a.nsteps; ++s) {
+        hipLaunchKernelGGL(k_bp_density<BN>, dim3(gi), dim3(BN), 0, st, a, s);
+        hipLaunchKernelGGL(k_bp_mu<BN>, dim3(gm), dim3(BN), 0, st, a);
+        if (b->has_compact) hipLaunchKernelGGL(k_bp_lines1<BN>, dim3(gl), dim3(BN), 0, st, a);
+        if (due[(size_t)s]) {
+            hipLaunchKernelGGL(k_bp_check<BN>, dim3(gi), dim3(BN), 0, st, a, s);
+            hipLaunchKernelGGL(k_bp_fold<BN>, dim3(gf), dim3(BN), 0, st, a, s);
+        }
+        hipLaunchKernelGGL(k_bp_collide<BN>, dim3(gi), dim3(BN), 0, st, a, s);
+    }
+    hipLaunchKernelGGL(k_bp_finish<BN>, dim3(gf), dim3(BN), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t batch_phases(const lbm_batch* b, const BatchArgs& a, const std::vector<char>& due, hipStream_t st)
+{
+    switch (b->block) {
+    case 256: return batch_phases_t<256>(b, a, due, st);
+    case 1024: return batch_phases_t<1024>(b, a, due, st);
+    default: return batch_phases_t<512>(b, a, due, st);
+    }
+}
+
+// Loop steps of the next chunk on which some instance that is still running
+// is at a multiple of check_every (from the counts read back after the last
+// chunk).  Instances that retire during the chunk were running at its start,
+// so the set covers every check the persistent kernel would make there.
+std::vector<char> batch_due(const lbm_batch* b, int todo, int check_every)
+{
+    std::vector<char> due((size_t)todo, 0);
+    for (int i = 0; i < b->n; ++i) {
+        const BState& S = b->h_st[i];
+        if (S.status != B_RUNNING) continue;
+        long long s = (check_every - S.steps % check_every) % check_every;
+        for (; s < todo; s += check_every) due[(size_t)s] = 1;
+    }
+    return due;
+}
+
+// One chunk of the phase form as a graph (stream capture), with the status
+// and flag read-backs.
+hipError_t batch_phase_graph(lbm_batch* b, const BatchArgs& a, const std::vector<char>& due, hipGraphExec_t* out)
+{
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t l = batch_phases(b, a, due, b->cap_stream);
+    if (l == hipSuccess)
+        l = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost, b->cap_stream);
+    if (l == hipSuccess) l = hipMemcpyAsync(b->h_flag, b->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, b->cap_stream);
+    e = hipStreamEndCapture(b->cap_stream, &g);
+    if (e == hipSuccess) e = l;
+    if (e == hipSuccess && !g) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1487,6 +1567,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.stop = -1; x.U = 0.0; x.U_prev = 0.0; }
     static const int zero[2] = { 0, 0 };
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->h_st), sizeof(BState) * n, hipHostMallocDefault);
+    if (e == hipSuccess) std::memcpy(b->h_st, st.data(), sizeof(BState) * n);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_flag), 2 * sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) b->h_flag[0] = b->h_flag[1] = 0;
     if (e == hipSuccess && !lines.empty())
@@ -1538,6 +1619,17 @@ int lbm_batch_set_block(lbm_batch* b, int nodes)
 
 int lbm_batch_block(const lbm_batch* b) { return b ? b->block : 0; }
 
+int lbm_batch_set_form(lbm_batch* b, int form)
+{
+    if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
+    if (form != LBM_BATCH_PERSISTENT && form != LBM_BATCH_PHASES)
+        return bfail(b, LBM_EINVAL, "form must be LBM_BATCH_PERSISTENT or LBM_BATCH_PHASES");
+    b->form = form;
+    return LBM_OK;
+}
+
+int lbm_batch_form(const lbm_batch* b) { return b ? b->form : -1; }
+
 const char* lbm_batch_launch_mode(const lbm_batch* b) { return b ? b->mode.c_str() : ""; }
 
 int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long chunk, int* status, long* steps,
@@ -1566,70 +1658,104 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
         a.launches = reinterpret_cast<unsigned*>(b->d_flag + 1);
         hipError_t e = hipSuccess;
         bool replayed = false;
+        const bool phases = b->form == LBM_BATCH_PHASES;
+        const std::vector<char> due = phases ? batch_due(b, (int)todo, (int)check_every) : std::vector<char>();
         if (b->use_graph) {
             lbm_batch::Graph* gr = nullptr;
             for (auto& g : b->graphs)
-                if (g.todo == (int)todo && g.check == (int)check_every && g.tol == tol && g.grid == b->grid &&
-                    g.block == b->block)
+                if (g.form == b->form && g.todo == (int)todo && g.check == (int)check_every && g.tol == tol &&
+                    g.grid == (phases ? 0 : b->grid) && g.block == b->block && g.due == due)
                     gr = &g;
             if (!gr) {
                 hipGraphExec_t ex = nullptr;
-                std::string how;
-                const hipError_t ge = batch_graph(b, a, &ex, how);
+                std::string how = "graph: captured phase kernels";
+                const hipError_t ge = phases ? batch_phase_graph(b, a, due, &ex) : batch_graph(b, a, &ex, how);
                 if (ge == hipSuccess) {
-                    b->graphs.push_back({ (int)todo, (int)check_every, b->grid, b->block, tol, ex });
+                    b->graphs.push_back({ b->form, (int)todo, (int)check_every, phases ? 0 : b->grid, b->block, tol,
+                                          due, ex, how });
                     gr = &b->graphs.back();
-                    b->mode = how;
                 } else {
                     (void)hipGetLastError();
                     b->use_graph = false;
-                    b->mode = std::string("plain cooperative launches (no graph: ") + hipGetErrorString(ge) + ")";
+                    b->mode = std::string(phases ? "plain phase kernels" : "plain cooperative launches") +
+                              " (no graph: " + hipGetErrorString(ge) + ")";
                 }
             }
             if (gr) {
+                b->mode = gr->how;
                 e = hipGraphLaunch(gr->exec, b->stream);
                 if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
                 if (e == hipSuccess && (b->h_flag[0] || (unsigned)b->h_flag[1] != b->launches + 1)) {
                     // the replay did not launch cooperatively (the kernel
-                    // returned at once) or did not run the kernel to its end:
-                    // no step was taken, so this chunk runs again below
+                    // returned at once) or did not run the kernels to their
+                    // end: no step was taken, so this chunk runs again below
                     static const int zero = 0;
                     e = hipMemcpyAsync(b->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
                     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
                     b->h_flag[0] = 0;
                     drop_graphs(b);
                     b->use_graph = false;
-                    b->mode = "plain cooperative launches (a graph replay did not run the kernel cooperatively)";
+                    b->mode = std::string(phases ? "plain phase kernels" : "plain cooperative launches") +
+                              " (a graph replay did not run the kernels)";
                 } else if (e == hipSuccess) {
                     b->launches++;
                     replayed = true;
                 }
             }
         }
-        if (e == hipSuccess && !replayed) {
+        if (e == hipSuccess && !replayed && !phases) {
+            if (b->mode.rfind("plain cooperative launches", 0) != 0) b->mode = "plain cooperative launches";
             void* args[] = { &a };
             e = hipLaunchCooperativeKernel(batch_kernel(b->block), dim3(b->grid), dim3(b->block), args, 0, b->stream);
-            if (e == hipSuccess) e = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost,
-                                                    b->stream);
+            if (e != hipSuccess) {
+                // this runtime refuses cooperative launches while another
+                // process holds the device: the chunk runs as phase kernels
+                // (bitwise the same steps), and so do the later ones
+                b->mode = std::string("plain phase kernels (the cooperative launch was refused: ") +
+                          hipGetErrorString(e) + ")";
+                (void)hipGetLastError();
+                e = hipSuccess;
+                b->form = LBM_BATCH_PHASES;
+                b->use_graph = false;
+                drop_graphs(b);
+            } else {
+                e = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost, b->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(b->h_flag, b->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+                if (e == hipSuccess && (b->h_flag[0] || (unsigned)b->h_flag[1] != b->launches + 1)) {
+                    // the kernel found no grid barrier and returned at once, or
+                    // did not run: no step of this launch was taken
+                    static const int zero = 0;
+                    b->h_flag[0] = 0;
+                    (void)hipMemcpyAsync(b->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
+                    (void)hipStreamSynchronize(b->stream);
+                    return bfail(b, LBM_EHIP, "the runtime did not run the batch kernel as a cooperative launch "
+                                              "(no grid barrier, or no run); no step was taken");
+                }
+                if (e == hipSuccess) {
+                    b->launches++;
+                    replayed = true;
+                }
+            }
+        }
+        if (e == hipSuccess && !replayed) {
+            // the phase form without a graph (also the fallback above)
+            if (b->mode.rfind("plain phase kernels", 0) != 0) b->mode = "plain phase kernels";
+            const std::vector<char> d = batch_due(b, (int)todo, (int)check_every);
+            e = batch_phases(b, a, d, b->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost, b->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(b->h_flag, b->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-            if (e == hipSuccess && (b->h_flag[0] || (unsigned)b->h_flag[1] != b->launches + 1)) {
-                // the kernel found no grid barrier and returned at once, or
-                // did not run: no step of this launch was taken
-                static const int zero = 0;
-                b->h_flag[0] = 0;
-                (void)hipMemcpyAsync(b->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
-                (void)hipStreamSynchronize(b->stream);
-                return bfail(b, LBM_EHIP, "the runtime did not run the batch kernel as a cooperative launch "
-                                          "(no grid barrier, or no run); no step was taken");
-            }
+            if (e == hipSuccess && (unsigned)b->h_flag[1] != b->launches + 1)
+                return bfail(b, LBM_EHIP, "the batch phase kernels did not run to their end");
             if (e == hipSuccess) b->launches++;
         }
         if (e != hipSuccess) {
             // the error is returned, not left for the caller's next runtime
-            // call (this runtime refuses cooperative launches, for one, while
-            // another process holds the device)
+            // call
             (void)hipGetLastError();
             return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
         }

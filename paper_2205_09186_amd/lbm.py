@@ -70,6 +70,8 @@ SYMBOLS = {
     "lbm_batch_max_grid": (C.c_int, [C.c_void_p]),
     "lbm_batch_set_block": (C.c_int, [C.c_void_p, C.c_int]),
     "lbm_batch_block": (C.c_int, [C.c_void_p]),
+    "lbm_batch_set_form": (C.c_int, [C.c_void_p, C.c_int]),
+    "lbm_batch_form": (C.c_int, [C.c_void_p]),
     "lbm_batch_launch_mode": (C.c_char_p, [C.c_void_p]),
     "lbm_batch_run": (C.c_int, [C.c_void_p, C.c_long, C.c_long, C.c_double, C.c_long, C.POINTER(C.c_int),
                                 C.POINTER(C.c_long), _D]),
@@ -398,8 +400,12 @@ _View.load_state = Simulation.load_state
 RUNNING, CONVERGED, DIVERGED = 0, 1, 2
 
 
+BATCH_PERSISTENT, BATCH_PHASES = 0, 1
+
+
 class Batch:
-    """Uneven D2Q9 instances stepped together by the cooperative persistent kernel."""
+    """Uneven D2Q9 instances stepped together, by the cooperative persistent
+    kernel (form BATCH_PERSISTENT) or by one launch per phase (BATCH_PHASES)."""
 
     def __init__(self, params, rho0s, device: str = "cuda:0", stream=None):
         import torch
@@ -443,6 +449,16 @@ class Batch:
             raise LbmError(code, lib().lbm_batch_last_error(self.h).decode())
 
     @property
+    def form(self) -> int:
+        return int(lib().lbm_batch_form(self.h))
+
+    def set_form(self, form: int) -> None:
+        """BATCH_PERSISTENT or BATCH_PHASES (bitwise the same states)."""
+        code = lib().lbm_batch_set_form(self.h, int(form))
+        if code != LBM_OK:
+            raise LbmError(code, lib().lbm_batch_last_error(self.h).decode())
+
+    @property
     def launch_mode(self) -> str:
         return lib().lbm_batch_launch_mode(self.h).decode()
 
@@ -471,28 +487,42 @@ class Batch:
         ctx = lib().lbm_batch_instance(self.h, int(i))
         return _View(C.c_void_p(ctx), self.params[i], self.device, self)
 
-    def tune(self, steps: int = 50, blocks=(256, 512, 1024)):
-        """Time the launch for every node-block size and, for each, the most
-        resident workgroups and a half and a quarter of them (the state
-        advances); keep the fastest.  Each combination runs once untimed (its
-        launch graph is captured then) and once timed.
-        Returns {"block/workgroups": ms per step}."""
+    def tune(self, steps: int = 50, blocks=(256, 512, 1024), forms=(BATCH_PERSISTENT, BATCH_PHASES)):
+        """Time the launch for every node-block size and, for each, the
+        persistent form with the most resident workgroups and a half and a
+        quarter of them, and the phase form (the state advances); keep the
+        fastest.  Each combination runs once untimed (its launch graph is
+        captured then) and once timed.
+        Returns {"block/workgroups": ms per step}, workgroups "phases" for the
+        phase form."""
         import time
         res = {}
         for bn in blocks:
             self.set_block(bn)
             mg = self.max_grid
-            for wg in sorted({mg, max(1, mg // 2), max(1, mg // 4)}):
+            cands = []
+            if BATCH_PERSISTENT in forms:
+                cands += [(BATCH_PERSISTENT, wg) for wg in sorted({mg, max(1, mg // 2), max(1, mg // 4)})]
+            if BATCH_PHASES in forms:
+                cands.append((BATCH_PHASES, mg))
+            for form, wg in cands:
+                self.set_form(form)
                 self.set_grid(wg)
                 self.run(steps, check_every=10 ** 9, tol=0.0, chunk=steps)
+                if self.form != form:   # the runtime refused the persistent form
+                    continue
                 self.torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 self.run(steps, check_every=10 ** 9, tol=0.0, chunk=steps)
-                res[f"{bn}/{wg}"] = (time.perf_counter() - t0) * 1e3 / steps
+                res[f"{bn}/{'phases' if form == BATCH_PHASES else wg}"] = (time.perf_counter() - t0) * 1e3 / steps
         best = min(res, key=res.get)
-        bn, wg = (int(x) for x in best.split("/"))
-        self.set_block(bn)
-        self.set_grid(wg)
+        bs, ws = best.split("/")
+        self.set_block(int(bs))
+        if ws == "phases":
+            self.set_form(BATCH_PHASES)
+        else:
+            self.set_form(BATCH_PERSISTENT)
+            self.set_grid(int(ws))
         return res
 
     def close(self):

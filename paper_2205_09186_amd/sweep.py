@@ -11,7 +11,7 @@ below Tr ~ 0.45).  Each
 instance runs until |U(t) - U(t - 100)| < 1e-10 (checked every 100 steps),
 until it diverges, or until the step cap.  --collision mrt runs every
 instance with the MRT collision of Eq 3-5 (the paper's own runs) instead of
-BGK.
+BGK.  The tuner picks the launch form; --time-forms times both.
 
 ``python -m paper_2205_09186_amd.sweep`` prints one JSON summary.
 """
@@ -80,6 +80,28 @@ def run(max_steps=150000, check_every=100, tol=1e-10, chunk=2000, tune=True, **k
                                                    for s in ("running", "converged", "diverged")}}
 
 
+def time_forms(steps=1000, warm=200, check_every=100, block=512, **kw):
+    """ms per step of each launch form on the same set with every instance
+    running (tol 0, one chunk of `steps` after `warm` untimed steps that also
+    capture the launch graph)."""
+    import torch
+    descs, params, rhos = build(**kw)
+    out = {}
+    for form, name in ((lbm.BATCH_PERSISTENT, "persistent"), (lbm.BATCH_PHASES, "phases")):
+        b = lbm.Batch(params, rhos)
+        b.set_block(block)
+        b.set_form(form)
+        b.run(warm, check_every=check_every, tol=0.0, chunk=warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(steps, check_every=check_every, tol=0.0, chunk=steps)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        nodes = sum(p.n for p in params)
+        out[name] = {"ms_per_step": round(ms, 4), "mlups": round(nodes / ms / 1e3, 1), "launch": b.launch_mode}
+        b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--max-steps", type=int, default=150000)
@@ -89,7 +111,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--collision", default="srt", choices=["srt", "mrt"],
                     help="BGK (Eq 1 with one rate) or the D2Q9 MRT of Eq 3-5")
+    ap.add_argument("--time-forms", action="store_true",
+                    help="only time the two launch forms (1000 steps each, every instance running)")
     a = ap.parse_args()
+    if a.time_forms:
+        print(json.dumps(time_forms(n_slabs=a.slabs, n_drops=a.drops, seed=a.seed)))
+        return
     res = run(max_steps=a.max_steps, chunk=a.chunk, n_slabs=a.slabs, n_drops=a.drops, seed=a.seed,
               collision=1 if a.collision == "mrt" else 0)
     res["collision"] = a.collision

@@ -1,6 +1,7 @@
-"""Batched sweep (cooperative persistent kernel) against independent plain runs
-of each instance, retirement of converged / diverged instances, and launch
-size independence."""
+"""Batched sweep (cooperative persistent kernel, or one launch per phase)
+against independent plain runs of each instance and the oracle, retirement of
+converged / diverged instances, and independence of the launch size and
+form."""
 import os
 import subprocess
 import sys
@@ -212,6 +213,62 @@ def test_batch_graph_replay_equals_plain_launches(L, monkeypatch):
     assert p.launch_mode.startswith("plain"), p.launch_mode
 
 
+def _retiring_specs(L):
+    # a CD2 droplet that diverges, the mixed set, and short checks: retirement
+    # at check steps inside launches
+    return [("drop", 100, 100, L.CD2, 0.8, 0.16, 25)] + _specs(L)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_phase_form_equals_persistent(L, monkeypatch, graph):
+    """The phase form (one launch per phase, the kernel boundary as barrier)
+    against the persistent kernel, chunk by chunk: status, step counts, U and
+    populations bitwise equal, through a divergence, checks every 70 steps
+    inside chunks of 50 and 120 (a remainder chunk included), and a loose
+    tolerance that retires every running instance at its next check."""
+    ps, rs = _build(L, _retiring_specs(L))
+    a = L.Batch(ps, rs)
+    if not graph:
+        monkeypatch.setenv("LBM_NO_GRAPH", "1")
+    b = L.Batch(ps, rs)
+    monkeypatch.delenv("LBM_NO_GRAPH", raising=False)
+    b.set_form(L.BATCH_PHASES)
+    assert a.form == L.BATCH_PERSISTENT and b.form == L.BATCH_PHASES
+    runs = [(120, 70, 0.0, 50), (240, 70, 0.0, 120), (130, 70, 0.0, 120), (300, 70, 1.0, 120)]
+    for k, (n, ce, tol, chunk) in enumerate(runs):
+        ra = a.run(n, check_every=ce, tol=tol, chunk=chunk)
+        rb = b.run(n, check_every=ce, tol=tol, chunk=chunk)
+        print(f"case batch phase form run {k} (graph={graph}): {b.launch_mode}; status {list(rb[0])} "
+              f"steps {list(rb[1])}", flush=True)
+        # the diverged instance holds NaN in both: compared as equal there
+        for x, y in zip(ra, rb):
+            assert np.array_equal(x, y, equal_nan=True), (k, x, y)
+        for i in range(len(ps)):
+            assert np.array_equal(a.instance(i).populations(), b.instance(i).populations(), equal_nan=True), (k, i)
+    st, steps, _ = rb
+    assert st[0] == L.DIVERGED and all(x == L.CONVERGED for x in st[1:]), st
+    assert b.launch_mode.startswith("graph: captured phase kernels" if graph else "plain phase kernels"), \
+        b.launch_mode
+    with pytest.raises(L.LbmError):
+        b.set_form(2)
+
+
+def test_batch_phase_form_matches_oracle_300_steps(L, orc):
+    """Every instance of the mixed batch after 300 steps of the phase form
+    against the oracle, node by node: rho and v to 1e-11."""
+    ps, rs = _build(L, _specs(L))
+    b = L.Batch(ps, rs)
+    b.set_form(L.BATCH_PHASES)
+    st, steps, _ = b.run(300, check_every=100, tol=0.0, chunk=120)
+    assert list(st) == [L.RUNNING] * len(ps) and list(steps) == [300] * len(ps)
+    for i, (p, r) in enumerate(zip(ps, rs)):
+        ro, vxo, vyo = _oracle_fields(orc, p, r, 300)
+        ra, vxa, vya, _ = b.instance(i).macros()
+        d = max(np.abs(ra - ro).max(), np.abs(vxa - vxo).max(), np.abs(vya - vyo).max())
+        print(f"case batch phase form instance {i} scheme={p.scheme}: max|diff| = {d:.2e}", flush=True)
+        assert d <= 1e-11, (i, d)
+
+
 def test_batch_block_sizes_give_the_same_state(L):
     """The node-block size (256, 512, 1024) and the workgroup count change
     which workgroup updates which node, not the arithmetic: bitwise equal."""
@@ -257,9 +314,10 @@ print("after", float(x.sum()), flush=True)
 
 def test_batch_in_a_second_process_runs_or_reports(L):
     """While this process holds the device (and a batch of its own), a batch
-    in a second process either takes every step it is asked for or reports
-    the refused cooperative launch as LbmError; it never returns with the
-    steps silently not taken, and leaves no error behind."""
+    in a second process either takes every step it is asked for (where the
+    runtime refuses its cooperative launch, in the phase form) or reports a
+    failed launch as LbmError; it never returns with the steps silently not
+    taken, and leaves no error behind."""
     ps, rs = _build(L, _specs(L)[:2])
     mine = L.Batch(ps, rs)
     mine.run(50, check_every=50, tol=0.0, chunk=50)
@@ -272,6 +330,7 @@ def test_batch_in_a_second_process_runs_or_reports(L):
     first = lines[0].split()
     assert first[0] in ("ran", "refused")
     if first[0] == "ran":
+        # a refused cooperative launch falls back to the phase form
         assert first[1] == "200" and first[2] == str(L.RUNNING)
     else:
         assert "cooperative" in lines[0] or "batch launch" in lines[0]
