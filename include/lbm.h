@@ -268,7 +268,7 @@ int lbm_batch_block(const lbm_batch* b);
  * second line solves; the two halves of the convergence check on the steps
  * where an instance is due; collision) is an ordinary launch of its own,
  * the kernel boundary in place of the barrier, and a chunk's launches are
- * captured as one graph.  A grid barrier costs about 0.1 us per workgroup
+ * captured as one graph (its chunks hold at most 1000 steps).  A grid barrier costs about 0.1 us per workgroup
  * and a launch boundary a few us; the tuner times both forms.  Both compute
  * bitwise the same states; the block size applies to both, the workgroup
  * count only to the persistent form.  Anything else is LBM_EINVAL;

@@ -1239,6 +1239,9 @@ struct lbm_batch {
 
 namespace {
 
+constexpr long kPhaseChunk = 1000;        // steps per launch sequence of the phase form
+constexpr size_t kMaxBatchGraphs = 16;   // cached chunk graphs per batch
+
 struct BatchLayout {
     std::vector<size_t> inst_off;
     size_t tables, total;
@@ -1642,7 +1645,9 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
     long done = 0;
     bool ran = false;
     while (done < nsteps) {
-        const long todo = std::min(chunk, nsteps - done);
+        // the phase form issues about four launches per step, so its chunks
+        // (and the graphs that hold them) are capped at kPhaseChunk steps
+        const long todo = std::min(b->form == LBM_BATCH_PHASES ? std::min(chunk, kPhaseChunk) : chunk, nsteps - done);
         BatchArgs a;
         a.inst = b->d_inst; a.st = b->d_st; a.ninst = b->n;
         a.nblk_total = b->nblk_total;
@@ -1667,6 +1672,9 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
                     g.grid == (phases ? 0 : b->grid) && g.block == b->block && g.due == due)
                     gr = &g;
             if (!gr) {
+                // a bounded cache: chunk lengths and check intervals that do
+                // not align give one phase graph per offset of the checks
+                if (b->graphs.size() >= kMaxBatchGraphs) drop_graphs(b);
                 hipGraphExec_t ex = nullptr;
                 std::string how = "graph: captured phase kernels";
                 const hipError_t ge = phases ? batch_phase_graph(b, a, due, &ex) : batch_graph(b, a, &ex, how);

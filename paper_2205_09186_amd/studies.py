@@ -334,6 +334,7 @@ def low_temperature_envelope(Trs=(0.3, 0.4, 0.5), widths=(5.0, 10.0, 20.0, 35.0)
                     rows.append(dict(kind=kind, Tr=Tr, W=W, via=via, kappa=kap, k=k, scheme=sname,
                                      rho_g_maxwell=g, rho_l_maxwell=l))
     b = lbm.Batch(ps, rs)
+    b.set_form(lbm.BATCH_PHASES)
     st, done, U = b.run(steps, check_every=100, tol=0.0, chunk=min(steps, 2000))
     for i, row in enumerate(rows):
         row.update(status=["running", "converged", "diverged"][int(st[i])], steps=int(done[i]), U=float(U[i]))

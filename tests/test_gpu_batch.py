@@ -253,6 +253,26 @@ def test_batch_phase_form_equals_persistent(L, monkeypatch, graph):
         b.set_form(2)
 
 
+def test_batch_phase_form_long_chunks(L):
+    """Chunks longer than the phase form's 1000-step launch sequences, with a
+    check interval that does not divide them (so the checks fall at a
+    different offset in every sequence, each with a graph of its own): bitwise
+    the persistent kernel's state, which runs each chunk in one launch."""
+    ps, rs = _build(L, _specs(L)[:4])
+    a = L.Batch(ps, rs)
+    b = L.Batch(ps, rs)
+    b.set_form(L.BATCH_PHASES)
+    for n in (2600, 1300):
+        ra = a.run(n, check_every=97, tol=0.0, chunk=2500)
+        rb = b.run(n, check_every=97, tol=0.0, chunk=2500)
+        print(f"case batch phase form chunk 2500, {n} steps: {b.launch_mode}", flush=True)
+        for x, y in zip(ra, rb):
+            assert np.array_equal(x, y), (n, x, y)
+    assert list(rb[1]) == [3900] * len(ps)
+    for i in range(len(ps)):
+        assert np.array_equal(a.instance(i).populations(), b.instance(i).populations()), i
+
+
 def test_batch_phase_form_matches_oracle_300_steps(L, orc):
     """Every instance of the mixed batch after 300 steps of the phase form
     against the oracle, node by node: rho and v to 1e-11."""
