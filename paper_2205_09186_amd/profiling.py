@@ -3,8 +3,9 @@
 ``python3 -m paper_2205_09186_amd.profiling run`` performs one plain 1 GiB
 device-to-device copy (the calibration kernel: 1 GiB read, 1 GiB written) and
 then a few steps of the benchmark workload (or, with --probe, a few launches of
-the population copy that measures the access pattern's ceiling), so one
-rocprofv3 run covers both.
+the population copy that measures the access pattern's ceiling; with --batch,
+a few steps of the batched sweep on the config-3 set), so one rocprofv3 run
+covers both.
 
 ``python3 -m paper_2205_09186_amd.profiling summarize --fetch DIR --write DIR
 --trace DIR`` reads the CSV output of the counter runs (FETCH_SIZE, then
@@ -49,6 +50,18 @@ def run(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+    if args.batch is not None:
+        # the config-3 set in one batch, every instance running, in the given
+        # launch form (512-node blocks)
+        from paper_2205_09186_amd import sweep
+        _, params, rhos = sweep.build()
+        b = lbm.Batch(params, rhos)
+        b.set_block(512)
+        b.set_form(lbm.BATCH_PHASES if args.batch == "phases" else lbm.BATCH_PERSISTENT)
+        b.run(args.steps, check_every=100, tol=0.0, chunk=args.steps)
+        torch.cuda.synchronize()
+        print(f"profiled the config-3 batch, {args.batch} form, {args.steps} steps ({b.launch_mode})", flush=True)
+        return
     lat = lbm.D3Q19 if args.lattice == "D3Q19" else lbm.D2Q9
     n = args.n
     shape = (n, n, n) if lat == lbm.D3Q19 else (n, n)
@@ -187,6 +200,8 @@ def main():
     r.add_argument("--steps", type=int, default=5)
     r.add_argument("--variant", default=None,
                    help="launch variant by name, e.g. 'tile 64x16 z64' (default: the library's)")
+    r.add_argument("--batch", choices=["phases", "persistent"], default=None,
+                   help="profile the batched sweep on the config-3 set in this launch form instead")
     r.add_argument("--probe", action="store_true",
                    help="profile the population copy (lbm_probe_copy) on the grid instead of the step")
     s = sub.add_parser("summarize")
