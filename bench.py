@@ -218,8 +218,9 @@ def main():
     stream = torch.cuda.current_stream()
     sim = lbm.Simulation(p, torch.from_numpy(rho0.reshape(-1)).cuda(), solid=solid)
     # tile-shape tuner: times every launch variant of the step kernel on this
-    # grid and keeps the fastest (counts as warm-up)
-    tuned = sim.tune(steps=3) if sim.num_variants > 1 else {0: None}
+    # grid, best of three rounds, and keeps the fastest; the state is then
+    # restored, so the timed steps follow the warm-up steps alone
+    tuned = sim.tune(steps=3, rounds=3, restore=True) if sim.num_variants > 1 else {0: None}
     sim.step(args.warmup)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

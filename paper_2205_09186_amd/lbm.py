@@ -275,17 +275,26 @@ class Simulation:
         """What launch variant v is, e.g. 'tile 64x16 z64 mf'."""
         return lib().lbm_variant_name(self.ctx, int(v)).decode()
 
-    def tune(self, steps: int = 5):
-        """Time every launch variant of the step kernel on this grid (the state
-        advances by steps * variants steps) and keep the fastest.  Returns
-        {variant: ms per step}."""
+    def tune(self, steps: int = 5, rounds: int = 1, restore: bool = False):
+        """Time every launch variant of the step kernel on this grid and keep
+        the fastest.  Each round takes every variant in turn for one untimed
+        and `steps` timed steps; a variant's time is its best round, so drift
+        over the rounds does not favour the variants timed last.  The state
+        advances by (steps + 1) * variants * rounds steps, or with
+        restore=True returns to where it was (a device state image, which
+        also restores the step count).  Returns {variant: ms per step}."""
+        img = self.save_state(device=True) if restore else None
         res = {}
-        for v in range(self.num_variants):
-            self.set_variant(v)
-            self.step_timed(1)
-            res[v] = sum(t for _, t in self.step_timed(steps))
+        for r in range(rounds):
+            for v in range(self.num_variants):
+                self.set_variant(v)
+                self.step_timed(1)
+                t = sum(t for _, t in self.step_timed(steps))
+                res[v] = t if r == 0 else min(res[v], t)
         best = min(res, key=res.get)
         self.set_variant(best)
+        if img is not None:
+            self.load_state(img)
         return res
 
     @property
