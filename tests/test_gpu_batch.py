@@ -253,6 +253,30 @@ def test_batch_phase_form_equals_persistent(L, monkeypatch, graph):
         b.set_form(2)
 
 
+def test_batch_phase_form_mrt(L):
+    """The D2Q9 MRT collision (Eq 3-5) in both launch forms: bitwise equal
+    after 250 steps with checks every 50, and equal to plain MRT runs."""
+    ps, rs = _build(L, _specs(L)[:4])
+    ps = [L.Params(lattice=p.lattice, nx=p.nx, ny=p.ny, Tr=p.Tr, k=p.k, kappa=p.kappa, scheme=p.scheme, collision=1)
+          for p in ps]
+    a = L.Batch(ps, rs)
+    b = L.Batch(ps, rs)
+    b.set_form(L.BATCH_PHASES)
+    ra = a.run(250, check_every=50, tol=0.0, chunk=100)
+    rb = b.run(250, check_every=50, tol=0.0, chunk=100)
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x, y)
+    for i in range(len(ps)):
+        fb = b.instance(i).populations()
+        assert np.array_equal(a.instance(i).populations(), fb), i
+        s = L.Simulation(ps[i], rs[i])
+        s.step(250)
+        d = np.abs(fb - s.populations()).max()
+        print(f"case batch MRT phase form instance {i}: max|diff| vs plain = {d:.2e}", flush=True)
+        assert d < 1e-11, (i, d)
+        s.close()
+
+
 def test_batch_phase_form_long_chunks(L):
     """Chunks longer than the phase form's 1000-step launch sequences, with a
     check interval that does not divide them (so the checks fall at a
