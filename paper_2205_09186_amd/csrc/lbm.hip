@@ -1212,9 +1212,13 @@ struct lbm_batch {
     unsigned launches = 0;
     BState* h_st = nullptr;     // pinned host copies read after every chunk
     int* h_flag = nullptr;
+    // the work-item tables hold the instances running when they were built
+    // (retired ones then cost nothing); rebuilt between chunks once fewer run
     int nblk_total = 0;
     int nlines = 0;
     int has_compact = 0;
+    int table_running = 0;
+    std::vector<BLine> all_lines;     // the grid lines of every compact-scheme instance
     int block = kBatchDefaultBlock;   // nodes per node-block item = threads per workgroup
     int grid = 0;                     // workgroups of the cooperative launch
     int max_grid_of[kNumBatchBlocks] = {};
@@ -1309,18 +1313,34 @@ const void* batch_kernel(int block)
 // with the instance table; synchronises.
 hipError_t batch_tables(lbm_batch* b)
 {
+    // node-block items and compact-scheme lines of the instances still
+    // running (by the status last read back); a retired instance keeps its
+    // entry in the instance table with no items
     std::vector<int> blk_inst;
+    int running = 0, compact = 0;
     for (int i = 0; i < b->n; ++i) {
         BInst& I = b->inst[i];
+        const bool run = b->h_st[i].status == B_RUNNING;
         I.blk0 = (int)blk_inst.size();
-        I.nblk = (int)((I.g.N + b->block - 1) / b->block);
+        I.nblk = run ? (int)((I.g.N + b->block - 1) / b->block) : 0;
         for (int k = 0; k < I.nblk; ++k) blk_inst.push_back(i);
         I.part0 = I.blk0;
+        running += run;
+        compact |= run && is_compact(I.scheme);
     }
+    std::vector<BLine> lines;
+    for (const BLine& ln : b->all_lines)
+        if (b->h_st[ln.inst].status == B_RUNNING) lines.push_back(ln);
     b->nblk_total = (int)blk_inst.size();
+    b->nlines = (int)lines.size();
+    b->has_compact = compact;
+    b->table_running = running;
     hipError_t e = hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * b->n, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_blk_inst, blk_inst.data(), sizeof(int) * blk_inst.size(),
-                                            hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !blk_inst.empty())
+        e = hipMemcpyAsync(b->d_blk_inst, blk_inst.data(), sizeof(int) * blk_inst.size(), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess && !lines.empty())
+        e = hipMemcpyAsync(b->d_lines, lines.data(), sizeof(BLine) * lines.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     return e;
 }
@@ -1359,6 +1379,17 @@ hipError_t ensure_cooperative(hipGraph_t g)
     return e;
 }
 
+// Workgroups of the persistent launch: the chosen count, but no more than
+// there are work items (node blocks, or wavefronts' worth of lines) for the
+// instances still running, since every grid barrier costs in proportion to
+// the workgroups that take part.
+int batch_grid(const lbm_batch* b)
+{
+    const int W = b->block / 64;
+    const int items = std::max(b->nblk_total, (b->nlines + W - 1) / W);
+    return std::max(1, std::min(b->grid, items));
+}
+
 // One chunk as a graph: the cooperative kernel, then the status and flag
 // read-backs into the pinned host buffers.  First by stream capture of the
 // cooperative launch; where the runtime cannot capture it, by building the
@@ -1371,7 +1402,7 @@ hipError_t batch_graph(lbm_batch* b, const BatchArgs& a, hipGraphExec_t* out, st
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t l = hipLaunchCooperativeKernel(kfn, dim3(b->grid), dim3(b->block), args, 0, b->cap_stream);
+        hipError_t l = hipLaunchCooperativeKernel(kfn, dim3(batch_grid(b)), dim3(b->block), args, 0, b->cap_stream);
         if (l == hipSuccess)
             l = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost, b->cap_stream);
         if (l == hipSuccess)
@@ -1392,7 +1423,7 @@ hipError_t batch_graph(lbm_batch* b, const BatchArgs& a, hipGraphExec_t* out, st
         if (e == hipSuccess) {
             hipKernelNodeParams kp{};
             kp.func = const_cast<void*>(kfn);
-            kp.gridDim = dim3(b->grid);
+            kp.gridDim = dim3(batch_grid(b));
             kp.blockDim = dim3(b->block);
             kp.sharedMemBytes = 0;
             kp.kernelParams = args;
@@ -1544,7 +1575,6 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
         I.cc = compact_scheme(ps[i].scheme);
         I.z = c->z; I.zscale = c->zscale;
         I.K = c->lines[0].K;
-        if (is_compact(ps[i].scheme)) b->has_compact = 1;
     }
     if (rc != LBM_OK) { std::string e = b->err; lbm_batch_free(b); return bfail(nullptr, rc, e); }
     size_t off = B.tables;
@@ -1565,7 +1595,7 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
             for (int j = 0; j < count; j += per) lines.push_back(BLine{ i, axis, j, std::min(per, count - j) });
         }
     }
-    b->nlines = (int)lines.size();
+    b->all_lines = lines;
     std::vector<BState> st(n);
     for (auto& x : st) { x.status = B_RUNNING; x.steps = 0; x.stop = -1; x.U = 0.0; x.U_prev = 0.0; }
     static const int zero[2] = { 0, 0 };
@@ -1573,8 +1603,6 @@ int lbm_batch_init(const lbm_params* ps, const double* const* rho0s, int n, void
     if (e == hipSuccess) std::memcpy(b->h_st, st.data(), sizeof(BState) * n);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_flag), 2 * sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) b->h_flag[0] = b->h_flag[1] = 0;
-    if (e == hipSuccess && !lines.empty())
-        e = hipMemcpyAsync(b->d_lines, lines.data(), sizeof(BLine) * lines.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_st, st.data(), sizeof(BState) * n, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_flag, zero, 2 * sizeof(int), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = batch_tables(b);
@@ -1645,6 +1673,18 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
     long done = 0;
     bool ran = false;
     while (done < nsteps) {
+        {
+            // instances retired since the tables were built: tables of the
+            // running ones (the graphs hold the old item counts, so they go)
+            int running = 0;
+            for (int i = 0; i < b->n; ++i) running += b->h_st[i].status == B_RUNNING;
+            if (running == 0) break;
+            if (running < b->table_running) {
+                const hipError_t te = batch_tables(b);
+                if (te != hipSuccess) return bfail(b, LBM_EHIP, std::string("batch tables: ") + hipGetErrorString(te));
+                drop_graphs(b);
+            }
+        }
         // the phase form issues about four launches per step, so its chunks
         // (and the graphs that hold them) are capped at kPhaseChunk steps
         const long todo = std::min(b->form == LBM_BATCH_PHASES ? std::min(chunk, kPhaseChunk) : chunk, nsteps - done);
@@ -1669,7 +1709,7 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
             lbm_batch::Graph* gr = nullptr;
             for (auto& g : b->graphs)
                 if (g.form == b->form && g.todo == (int)todo && g.check == (int)check_every && g.tol == tol &&
-                    g.grid == (phases ? 0 : b->grid) && g.block == b->block && g.due == due)
+                    g.grid == (phases ? 0 : batch_grid(b)) && g.block == b->block && g.due == due)
                     gr = &g;
             if (!gr) {
                 // a bounded cache: chunk lengths and check intervals that do
@@ -1679,7 +1719,7 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
                 std::string how = "graph: captured phase kernels";
                 const hipError_t ge = phases ? batch_phase_graph(b, a, due, &ex) : batch_graph(b, a, &ex, how);
                 if (ge == hipSuccess) {
-                    b->graphs.push_back({ b->form, (int)todo, (int)check_every, phases ? 0 : b->grid, b->block, tol,
+                    b->graphs.push_back({ b->form, (int)todo, (int)check_every, phases ? 0 : batch_grid(b), b->block, tol,
                                           due, ex, how });
                     gr = &b->graphs.back();
                 } else {
@@ -1714,7 +1754,8 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
         if (e == hipSuccess && !replayed && !phases) {
             if (b->mode.rfind("plain cooperative launches", 0) != 0) b->mode = "plain cooperative launches";
             void* args[] = { &a };
-            e = hipLaunchCooperativeKernel(batch_kernel(b->block), dim3(b->grid), dim3(b->block), args, 0, b->stream);
+            e = hipLaunchCooperativeKernel(batch_kernel(b->block), dim3(batch_grid(b)), dim3(b->block), args, 0,
+                                           b->stream);
             if (e != hipSuccess) {
                 // this runtime refuses cooperative launches while another
                 // process holds the device: the chunk runs as phase kernels

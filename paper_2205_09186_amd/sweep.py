@@ -57,10 +57,15 @@ def coexistence_of(view, d):
     return float(r[d["ny"] // 2, d["nx"] // 2]), float(r[0, 0])
 
 
-def run(max_steps=150000, check_every=100, tol=1e-10, chunk=2000, tune=True, **kw):
+def run(max_steps=150000, check_every=100, tol=1e-10, chunk=2000, tune=True, form=None, **kw):
+    """form: None lets the tuner choose (with tune=True), else
+    lbm.BATCH_PERSISTENT or lbm.BATCH_PHASES."""
     descs, params, rhos = build(**kw)
     b = lbm.Batch(params, rhos)
-    tuned = b.tune(steps=20) if tune else None
+    tuned = b.tune(steps=20, forms=(form,) if form is not None else (lbm.BATCH_PERSISTENT, lbm.BATCH_PHASES)) \
+        if tune else None
+    if form is not None:
+        b.set_form(form)
     t0 = time.perf_counter()
     st, steps, U = b.run(max_steps, check_every=check_every, tol=tol, chunk=chunk)
     wall = time.perf_counter() - t0
@@ -76,6 +81,7 @@ def run(max_steps=150000, check_every=100, tol=1e-10, chunk=2000, tune=True, **k
     # node updates actually performed (tuning steps excluded)
     nodes = np.array([p.n for p in params], dtype=np.float64)
     return {"instances": out, "wall_s": wall, "node_updates": float((nodes * np.array(steps)).sum()),
+            "form": ["persistent", "phases"][b.form], "block": b.block, "launch": b.launch_mode,
             "tuner_ms_per_step": tuned, "counts": {s: sum(1 for r in out if r["status"] == s)
                                                    for s in ("running", "converged", "diverged")}}
 
@@ -111,14 +117,17 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--collision", default="srt", choices=["srt", "mrt"],
                     help="BGK (Eq 1 with one rate) or the D2Q9 MRT of Eq 3-5")
+    ap.add_argument("--form", default="tune", choices=["tune", "persistent", "phases"],
+                    help="batch launch form (default: the tuner's choice)")
     ap.add_argument("--time-forms", action="store_true",
                     help="only time the two launch forms (1000 steps each, every instance running)")
     a = ap.parse_args()
     if a.time_forms:
         print(json.dumps(time_forms(n_slabs=a.slabs, n_drops=a.drops, seed=a.seed)))
         return
+    form = {"tune": None, "persistent": lbm.BATCH_PERSISTENT, "phases": lbm.BATCH_PHASES}[a.form]
     res = run(max_steps=a.max_steps, chunk=a.chunk, n_slabs=a.slabs, n_drops=a.drops, seed=a.seed,
-              collision=1 if a.collision == "mrt" else 0)
+              collision=1 if a.collision == "mrt" else 0, form=form)
     res["collision"] = a.collision
     res["mlups"] = res["node_updates"] / res["wall_s"] / 1e6
     print(json.dumps(res))
