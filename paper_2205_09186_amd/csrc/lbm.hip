@@ -235,7 +235,7 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
     const Compact cc = compact_scheme(c->p.scheme);
     // whole lines, one segment of kSegLen points per wave (y, z) or per lane
     // (x, rows staged in LDS), used where there are enough lines to fill the chip
-    const bool seg = lg.n <= kSegMaxWaves * kSegLen && c->g.N < (1LL << 29) &&
+    const bool seg = lg.n <= kSegMaxWavesLong * kSegLen && c->g.N < (1LL << 29) &&
                      (long long)lg.n1 * lg.n2 >= (d == 0 ? c->seg_min_lines_x : c->seg_min_lines_yz);
     if (seg) {
         const int W = (lg.n + kSegLen - 1) / kSegLen;
@@ -251,8 +251,12 @@ void compact_deriv(lbm_ctx* c, const double* in, CompactSink sink, int d)
                                c->stream, in, sink, rows, q, cc, c->z, c->zscale, zS, zLast, zN);
         } else {
             const unsigned blocks = (unsigned)(((lg.n1 + 63) / 64) * (long long)lg.n2);
-            hipLaunchKernelGGL(k_compact_seg<kSegLen>, dim3(blocks), dim3(64 * W), 0, c->stream, in, sink, lg, cc,
-                               c->z, c->zscale, zS, zLast, zN);
+            if (W <= kSegMaxWaves)
+                hipLaunchKernelGGL((k_compact_seg<kSegLen, kSegMaxWaves>), dim3(blocks), dim3(64 * W), 0, c->stream,
+                                   in, sink, lg, cc, c->z, c->zscale, zS, zLast, zN);
+            else
+                hipLaunchKernelGGL((k_compact_seg<kSegLen, kSegMaxWavesLong>), dim3(blocks), dim3(64 * W), 0,
+                                   c->stream, in, sink, lg, cc, c->z, c->zscale, zS, zLast, zN);
         }
         return;
     }

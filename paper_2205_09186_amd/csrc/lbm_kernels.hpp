@@ -760,7 +760,7 @@ __global__ void __launch_bounds__(256) k_compact_wave(const double* __restrict__
 }
 
 // Compact derivative along y or z of whole lines in one pass (lines of at
-// most kSegMaxWaves * kSegLen = 256 points; lanes along x with unit stride).  A workgroup
+// most kSegMaxWavesLong * kSegLen = 384 points; lanes along x with unit stride).  A workgroup
 // takes 64 neighbouring lines; wave w solves points [w S, w S + L_w) of each
 // in registers.  Both recursions run locally from a zero start and are then
 // made exact for the periodic line by the carries of the other segments:
@@ -774,13 +774,14 @@ __global__ void __launch_bounds__(256) k_compact_wave(const double* __restrict__
 // three-point halos of the right-hand side) and each output written once.
 constexpr int kSegMaxWaves = 8;
 constexpr int kSegLen = 32;   // 64-point segments spill registers
+constexpr int kSegMaxWavesLong = 12;   // y and z lines of up to 384 points
 
-template <int S>
-__global__ void __launch_bounds__(64 * kSegMaxWaves)
+template <int S, int MAXW>
+__global__ void __launch_bounds__(64 * MAXW)
 k_compact_seg(const double* __restrict__ f, CompactSink sink, LineGeom lg, Compact c, double z, double scale,
               double zS, double zLast, double zN)
 {
-    __shared__ double ends[kSegMaxWaves][64];
+    __shared__ double ends[MAXW][64];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int W = blockDim.x >> 6;
@@ -856,23 +857,25 @@ k_compact_seg(const double* __restrict__ f, CompactSink sink, LineGeom lg, Compa
             if (i < L) { r[i] = scale * (r[i] + q * u); q *= z; }
         }
     }
-    // the sink, in runs of 16 points
+    // the sink, in runs of SR points (shorter runs where more waves share the
+    // registers)
+    constexpr int SR = MAXW > 8 ? 8 : 16;
 #pragma unroll
-    for (int h = 0; h < S; h += 16) {
-        unsigned o[16];
-        double v[16];
-        bool ok[16];
+    for (int h = 0; h < S; h += SR) {
+        unsigned o[SR];
+        double v[SR];
+        bool ok[SR];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
+        for (int m = 0; m < SR; ++m) {
             o[m] = base + (unsigned)(s0 + h + m) * sa;
             v[m] = r[h + m];
             ok[m] = active && h + m < L;
         }
-        sink_run<16>(sink, o, v, ok);
+        sink_run<SR>(sink, o, v, ok);
     }
 }
 
-// Compact derivative along x of rows of at most 8 * kSegLen = 256 points, the
+// Compact derivative along x of rows of at most 12 * kSegLen = 384 points, the
 // row-wise counterpart of k_compact_seg.  Each wavefront stages RW rows in
 // LDS with coalesced loads; lane l then solves segment s = l % NS (NS = the
 // segments per row) of row l / NS from LDS, the periodic carries between the
@@ -884,7 +887,7 @@ k_compact_seg(const double* __restrict__ f, CompactSink sink, LineGeom lg, Compa
 // different banks.
 struct XSegGeom {
     int n, NS, RW, P;     // row length, segments per row, rows per wave, LDS row stride
-    unsigned magic;       // e / n == (e * magic) >> 20 for 0 <= e < 2048
+    unsigned magic;       // e / n == (e * magic) >> 20 for 0 <= e < 2048 (n < 512)
 };
 
 inline XSegGeom xseg_geom(int n)

@@ -1,8 +1,9 @@
 """The compact schemes' line solves on multi-segment lines: lines along x, y
 and z longer than one 32-point segment, with a ragged last segment, solved in
-one pass with exact periodic carries between segments, y and z lines of up
-to 1024 points by one wavefront each (and, for comparison, by the chunked
-recursions), against the oracle's Thomas + Sherman-Morrison solves."""
+one pass with exact periodic carries between segments (lines of up to 384
+points, 12 segments), y and z lines of up to 1024 points by one wavefront
+each (and, for comparison, by the chunked recursions), against the oracle's
+Thomas + Sherman-Morrison solves."""
 import numpy as np
 import pytest
 
@@ -25,7 +26,7 @@ def L():
 def solver(request, monkeypatch):
     """Every line solver: the one-pass segment kernels (forced on these small
     grids), one wavefront per y or z line (exact scans across the lanes; the
-    solver for y and z lines of 257 to 1024 points) and the chunked
+    solver for y and z lines of 385 to 1024 points) and the chunked
     forward/backward recursions."""
     monkeypatch.setenv("LBM_SEG_MIN_LINES", "0" if request.param == "segments" else str(1 << 62))
     if request.param == "chunks":
@@ -37,7 +38,8 @@ def solver(request, monkeypatch):
 
 @pytest.mark.parametrize("scheme", ["OCFDS4", "CFDS4", "CFDS6", "CFDS8"])
 @pytest.mark.parametrize("shape", [(70, 37, 64), (33, 256, 20), (4, 65, 96), (300, 6, 8), (4, 1024, 6),
-                                   (6, 4, 1000)])
+                                   (6, 4, 1000), (6, 384, 10), (384, 5, 12), (4, 333, 70), (4, 6, 350),
+                                   (5, 4, 384)])
 def test_gradient_multisegment_lines(L, orc, scheme, shape, solver):
     rng = np.random.default_rng(7)
     grids = np.meshgrid(*[np.arange(s) * 2 * np.pi / s for s in shape], indexing="ij")
@@ -59,7 +61,7 @@ def test_gradient_multisegment_lines(L, orc, scheme, shape, solver):
 
 
 @pytest.mark.parametrize("scheme", ["OCFDS4", "CFDS8"])
-@pytest.mark.parametrize("shape", [(70, 37, 64), (600, 40)])
+@pytest.mark.parametrize("shape", [(70, 37, 64), (600, 40), (370, 40)])
 def test_step_multisegment_lines(L, orc, scheme, shape, solver):
     g, l = orc.maxwell(0.9)
     rho0 = inputs.droplet(shape, 12, 4.0, g, l)

@@ -51,7 +51,7 @@ def _design_variants(L, sim, lat, scheme):
 
 @pytest.mark.parametrize("lat,n,scheme,steps", [(1, 256, "CD6", 50), (1, 256, "OCFDS4", 2), (0, 1024, "CD6", 20),
                                                 (0, 1024, "OCFDS4", 10), (1, 384, "CD6", 2), (1, 256, "E8", 2),
-                                                (1, 256, "CD2", 5), (1, 256, "CD4", 5)])
+                                                (1, 256, "CD2", 5), (1, 256, "CD4", 5), (1, 384, "OCFDS4", 2)])
 def test_full_size_against_oracle(L, orc, lat, n, scheme, steps):
     import torch
     shape, rho0, kw = _workload(orc, lat, n, L.SCHEMES[scheme])
