@@ -1771,6 +1771,7 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
                 b->form = LBM_BATCH_PHASES;
                 b->use_graph = false;
                 drop_graphs(b);
+                a.nsteps = (int)std::min(todo, kPhaseChunk);   // the phase form's launch sequences stay bounded
             } else {
                 e = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost, b->stream);
                 if (e == hipSuccess)
@@ -1795,7 +1796,7 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
         if (e == hipSuccess && !replayed) {
             // the phase form without a graph (also the fallback above)
             if (b->mode.rfind("plain phase kernels", 0) != 0) b->mode = "plain phase kernels";
-            const std::vector<char> d = batch_due(b, (int)todo, (int)check_every);
+            const std::vector<char> d = batch_due(b, a.nsteps, (int)check_every);
             e = batch_phases(b, a, d, b->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(b->h_st, b->d_st, sizeof(BState) * b->n, hipMemcpyDeviceToHost, b->stream);
@@ -1813,7 +1814,7 @@ int lbm_batch_run(lbm_batch* b, long nsteps, long check_every, double tol, long 
             return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
         }
         ran = true;
-        done += todo;
+        done += a.nsteps;
         bool running = false;
         for (int i = 0; i < b->n; ++i) running |= b->h_st[i].status == B_RUNNING;
         if (!running) break;
