@@ -415,6 +415,13 @@ __global__ void __launch_bounds__(MX * TYM) k_march(const double* __restrict__ r
             }
         }
         if (p < pe) fetch(p + 1);
+        // NF = 1, CD schemes in 3D: the own node's bulk potential comes from
+        // its z queue, so it is evaluated before the barrier, while the next
+        // plane's loads are in flight (0.117 -> 0.111 ms on 256^3 CD6)
+        double mb = 0.0;
+        if constexpr (NF == 1 && DIM == 3 && !ISO) {
+            if (in) mb = mu_bulk(q[0][R], e);
+        }
         __syncthreads();
         if constexpr (SLOTS && !ISO) {
 #pragma unroll
@@ -541,8 +548,9 @@ __global__ void __launch_bounds__(MX * TYM) k_march(const double* __restrict__ r
                 acc += w * (c[0][c0 + m * WR] + c[0][c0 - m * WR]);
                 if constexpr (DIM == 3) acc += w * (q[0][R + m] + q[0][R - m]);
             }
+            if constexpr (DIM != 3) mb = mu_bulk(f0, e);
             // solid nodes (wetting boundary) carry the wall's chemical potential
-            st32(out, n, g.wl && g.wl[n] ? e.mu_wall : mu_bulk(f0, e) - e.kappa * acc);
+            st32(out, n, g.wl && g.wl[n] ? e.mu_wall : mb - e.kappa * acc);
         } else {
             double grx = 0.0, gry = 0.0, grz = 0.0, gmx = 0.0, gmy = 0.0, gmz = 0.0;
 #pragma unroll
@@ -698,6 +706,17 @@ k_mf(const double* __restrict__ rho, double* __restrict__ out, Grid g, TileGeom 
     const int pb = z0 - 2 * R, pe = z1 - 1 + 2 * R;
     fetch(pb);
     for (int p = pb; p <= pe; ++p) {
+        // bulk potential of the mu_hat cells of plane p - R (rq[s][R + 1]
+        // before the queues advance), evaluated before the barrier so that it
+        // fills the wait for the other waves' stores
+        double mb[SMC];
+#pragma unroll
+        for (int s = 0; s < SMC; ++s) mb[s] = 0.0;
+        if (p >= z0) {
+#pragma unroll
+            for (int s = 0; s < SMC; ++s)
+                if (cv[s]) mb[s] = mu_bulk(rq[s][R + 1], e);
+        }
 #pragma unroll
         for (int k = 0; k < SPP; ++k)
             if (lid + k * NTH < CP) sp[lid + k * NTH] = sv[k];
@@ -737,7 +756,7 @@ k_mf(const double* __restrict__ rho, double* __restrict__ out, Grid g, TileGeom 
                 double acc = lq[s][0] + d2(SCH, 0) * c;
 #pragma unroll
                 for (int m = 1; m <= R; ++m) acc += d2(SCH, m) * (rq[s][R + m] + rq[s][R - m]);
-                const double mu = mu_bulk(c, e) - e.kappa * acc;
+                const double mu = mb[s] - e.kappa * acc;
                 (*M)[cm[s]] = mu;
                 if (s == 0) {
 #pragma unroll
