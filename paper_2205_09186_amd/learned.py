@@ -369,12 +369,19 @@ def gain(net: Net = None, n: int = 16, seed: int = 60, lmax: int = 128, tol: flo
     cmp_ = [r for r in rows if "ratio" in r]
     ratio = np.array([r["ratio"] for r in cmp_])
     dU = np.array([r["dU"] for r in cmp_])
+    # steps saved over the droplets that met the criterion from both starts
+    # (a run stopped by the cap would count its cap as its steps)
+    both = [i for i in range(n) if t[0][i] == lbm.CONVERGED and lrn[0][i] == lbm.CONVERGED]
+    st_t = sum(int(t[1][i]) for i in both)
+    st_l = sum(int(lrn[1][i]) for i in both)
     summary = dict(
         droplets=n, fallback=fallback, compared=len(cmp_),
         steps_ratio_median=float(np.median(ratio)) if cmp_ else None,
         learned_fewer_steps=int((ratio < 1).sum()),
-        steps_saved_total=(float(1 - sum(int(x) for x in lrn[1]) / sum(int(x) for x in t[1]))
-                           if sum(int(x) for x in t[1]) > 0 else None),
+        steps_saved_total=float(1 - st_l / st_t) if st_t > 0 else None,
+        both_converged=len(both),
+        not_converged={"tanh": int(sum(int(x) != lbm.CONVERGED for x in t[0])),
+                       "learned": int(sum(int(x) != lbm.CONVERGED for x in lrn[0]))},
         U_reldiff_median=float(np.median(dU)) if cmp_ else None,
         U_reldiff_max=float(dU.max()) if cmp_ else None,
         U_within_1e6=int((dU <= 1e-6).sum()),
