@@ -152,10 +152,13 @@ def device_sum(x) -> float:
 
 
 def mass_matched_field(net: Net, p: lbm.Params, R0, Tr, k, scheme, rho_g, rho_l, target_mass, iters=60,
-                       rel_tol=1e-10):
+                       rel_tol=1e-10, noise=None):
     """Bisection on the radius so that the learned field has the target mass,
     then lbm_interface_mass for the residual the FP32 network leaves (only
     interface nodes change; the bulk densities stay as the network set them).
+    noise (host array of p.n values, or None): the relative perturbation the
+    tanh start carries (inputs.droplet with relative=True), applied to the
+    field before the residual is taken, so that both starts carry the same one.
     Returns (rho0 device tensor, radius), or (None, R0) when the target is not
     bracketed or the mass still misses it by more than rel_tol."""
     lo, hi = 0.25 * R0, min(p.nx, p.ny) * 0.5
@@ -172,9 +175,12 @@ def mass_matched_field(net: Net, p: lbm.Params, R0, Tr, k, scheme, rho_g, rho_l,
             hi = mid
     R = 0.5 * (lo + hi)
     rho = net.field(p, R, Tr, k, scheme, rho_g, rho_l)
+    import torch
+    if noise is not None:
+        # input preparation, on the host as in inputs.droplet
+        rho = torch.from_numpy(rho.cpu().numpy() * (1.0 + np.asarray(noise, np.float64).reshape(-1))).to(rho.device)
     # the network evaluates in FP32, so the mass moves in small steps with R:
     # the library puts the last residual into the interface nodes
-    import torch
     scratch = torch.empty(int(lbm.lib().lbm_sum_scratch_bytes(rho.numel())) // 8 + 1, dtype=torch.float64,
                           device=rho.device)
     lbm._check(lbm.lib().lbm_interface_mass(_ptr(rho), rho.numel(), float(rho_g), float(rho_l), float(target_mass),
@@ -271,7 +277,8 @@ def evaluate(net: Net, n=64, seed=7, max_steps=30000, check_every=100, tol=1e-10
     log(f"eval: building {len(specs)} learned initial states")
     for p, r, d in zip(ps, rs, specs):
         g, l = lbm.coexistence(d["Tr"])
-        rho, _ = mass_matched_field(net, p, d["R"], d["Tr"], d["k"], d["scheme"], g, l, float(r.sum()))
+        rho, _ = mass_matched_field(net, p, d["R"], d["Tr"], d["k"], d["scheme"], g, l, float(r.sum()),
+                                    noise=inputs.noise(r.shape, 1e-6, d["instance_id"]))
         if rho is None or not bool(torch.isfinite(rho).all()):
             fallback += 1
             learned.append(r)
@@ -334,7 +341,8 @@ def gain(net: Net = None, n: int = 16, seed: int = 60, lmax: int = 128, tol: flo
     starts, fallback = [], 0
     for p, r, d in zip(ps, rs, specs):
         g, l = lbm.coexistence(d["Tr"])
-        rho, _ = mass_matched_field(net, p, d["R"], d["Tr"], d["k"], d["scheme"], g, l, float(r.sum()))
+        rho, _ = mass_matched_field(net, p, d["R"], d["Tr"], d["k"], d["scheme"], g, l, float(r.sum()),
+                                    noise=inputs.noise(r.shape, 1e-6, d["instance_id"]))
         if rho is None or not bool(torch.isfinite(rho).all()):
             fallback += 1
             starts.append(r)
@@ -421,7 +429,8 @@ def big_droplet(net: Net, scheme: int, L: int = 384, R: float = 80.0, Tr: float 
     g, l = lbm.coexistence(Tr)
     p = lbm.Params(lattice=lbm.D3Q19, nx=L, ny=L, nz=L, Tr=Tr, k=k, kappa=0.004, scheme=scheme)
     r_t = inputs.droplet((L, L, L), R, 10.0, g, l, instance_id=30000 + scheme, relative=True)
-    rho, _ = mass_matched_field(net, p, R, Tr, k, scheme, g, l, float(r_t.sum()))
+    rho, _ = mass_matched_field(net, p, R, Tr, k, scheme, g, l, float(r_t.sum()),
+                                noise=inputs.noise(r_t.shape, 1e-6, 30000 + scheme))
     rows = {}
     for name, r0 in (("tanh", r_t), ("learned", rho if rho is not None else r_t)):
         if name not in starts:
@@ -504,7 +513,8 @@ def evaluate_3d(net: Net, n=8, seed=7, max_steps=60000, check_every=100, tol=1e-
         g, l = lbm.coexistence(d["Tr"])
         p = lbm.Params(lattice=lbm.D3Q19, nx=L, ny=L, nz=L, Tr=d["Tr"], k=d["k"], kappa=0.004, scheme=d["scheme"])
         r_t = inputs.droplet((L, L, L), d["R"], 10.0, g, l, instance_id=d["instance_id"], relative=True)
-        rho, _ = mass_matched_field(net, p, d["R"], d["Tr"], d["k"], d["scheme"], g, l, float(r_t.sum()))
+        rho, _ = mass_matched_field(net, p, d["R"], d["Tr"], d["k"], d["scheme"], g, l, float(r_t.sum()),
+                                    noise=inputs.noise(r_t.shape, 1e-6, d["instance_id"]))
         if rho is None or not bool(torch.isfinite(rho).all()):
             fallback += 1
             r_l = r_t
