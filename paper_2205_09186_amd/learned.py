@@ -363,7 +363,18 @@ def gain(net: Net = None, n: int = 16, seed: int = 60, lmax: int = 128, tol: flo
             dens.append((float(rr[d["L"] // 2, d["L"] // 2]), float(rr[0, 0])))
         res[name] = (st, steps, U, dens, wall, b.launch_mode)
         b.close()
-    t, lrn = res["tanh"], res["learned"]
+    return gain_summary(specs, fallback, res["tanh"], res["learned"])
+
+
+def gain_summary(specs, fallback, t, lrn):
+    """Rows and summary of the learned-vs-tanh comparison (host logic).
+    t and lrn are the two runs' (status, steps, U, [(centre, corner) density],
+    wall seconds, launch mode), one entry per droplet of specs.  A droplet is
+    compared when both runs met the criterion and both still hold a droplet
+    (centre density above 1.5 x the corner's); the steps saved are counted over
+    every droplet whose two runs met the criterion, since a run stopped by the
+    cap would count its cap as its steps."""
+    n = len(specs)
     rows = []
     for i, d in enumerate(specs):
         row = dict(L=d["L"], R=d["R"], scheme=int(d["scheme"]), Tr=d["Tr"], k=d["k"],
@@ -377,8 +388,6 @@ def gain(net: Net = None, n: int = 16, seed: int = 60, lmax: int = 128, tol: flo
     cmp_ = [r for r in rows if "ratio" in r]
     ratio = np.array([r["ratio"] for r in cmp_])
     dU = np.array([r["dU"] for r in cmp_])
-    # steps saved over the droplets that met the criterion from both starts
-    # (a run stopped by the cap would count its cap as its steps)
     both = [i for i in range(n) if t[0][i] == lbm.CONVERGED and lrn[0][i] == lbm.CONVERGED]
     st_t = sum(int(t[1][i]) for i in both)
     st_l = sum(int(lrn[1][i]) for i in both)
